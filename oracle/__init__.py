@@ -1,0 +1,174 @@
+"""Python view of the C oracle for the integral-image sliding-window method.
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the CPU-baseline leg of the benchmark
+use this module to produce expected values.  The product library never imports it, and it
+imports nothing from the product package.
+
+Every function takes numpy arrays, calls the serial C code in sat_oracle.c and returns numpy
+arrays.  Images are 2-D uint8 or uint16 arrays whose rows may be padded (any row stride that is a
+whole number of elements); tables and outputs come back dense.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_lib = None
+_i64 = ctypes.c_int64
+_p = ctypes.c_void_p
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_build.LIB):
+            _build.build()
+        lib = ctypes.CDLL(_build.LIB)
+        lib.oracle_window_shape.argtypes = [_i64] * 5 + [_p, _p]
+        lib.oracle_sat.argtypes = [_p, ctypes.c_int, _i64, _i64, _i64, _p, _p]
+        lib.oracle_window_sum_sat.argtypes = [_p] + [_i64] * 5 + [_p]
+        lib.oracle_window_sum_direct.argtypes = [_p, ctypes.c_int] + [_i64] * 6 + [ctypes.c_int, _p]
+        lib.oracle_window_at.argtypes = [_p, ctypes.c_int] + [_i64] * 5 + [_p, _p]
+        lib.oracle_window_at.restype = None
+        lib.oracle_mean_std.argtypes = [_p, _p, _i64, ctypes.c_uint64, _p, _p]
+        lib.oracle_mean_std.restype = None
+        lib.oracle_coverage_total.argtypes = [_p, ctypes.c_int] + [_i64] * 6
+        lib.oracle_coverage_total.restype = ctypes.c_uint64
+        lib.oracle_stream.argtypes = ([_p, ctypes.c_int, _i64, _i64, _i64, ctypes.c_int, _i64, _p, _p,
+                                       _i64, _p, _p, _p, _i64, _p, _p, _p])
+        _lib = lib
+    return _lib
+
+
+def _image(img):
+    img = np.asarray(img)
+    if img.ndim != 2 or img.dtype not in (np.uint8, np.uint16):
+        raise ValueError("image must be a 2-D uint8 or uint16 array")
+    if img.strides[1] != img.itemsize or img.strides[0] % img.itemsize or img.strides[0] < 0:
+        img = np.ascontiguousarray(img)
+    pitch = img.strides[0] // img.itemsize
+    return img, img.itemsize, pitch
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def window_shape(H, W, h, w, s=1):
+    """Output shape (rows, cols) of the valid region, or None if the window does not fit."""
+    oh, ow = ctypes.c_int64(), ctypes.c_int64()
+    if _load().oracle_window_shape(H, W, h, w, s, ctypes.byref(oh), ctypes.byref(ow)):
+        return None
+    return oh.value, ow.value
+
+
+def sat(img, squares=False):
+    """Inclusive integral image (uint64, dense); with squares=True also the table of I^2."""
+    img, bpp, pitch = _image(img)
+    H, W = img.shape
+    S = np.empty((H, W), np.uint64)
+    Q = np.empty((H, W), np.uint64) if squares else None
+    rc = _load().oracle_sat(_ptr(img), bpp, H, W, pitch, _ptr(S), _ptr(Q) if squares else None)
+    if rc:
+        raise ValueError("oracle_sat rejected its arguments")
+    return (S, Q) if squares else S
+
+
+def window_sum_sat(S, h, w, s=1):
+    """Window sums by four-corner lookup into a dense uint64 table S (uint64 output)."""
+    S = np.ascontiguousarray(S, dtype=np.uint64)
+    H, W = S.shape
+    shape = window_shape(H, W, h, w, s)
+    if shape is None:
+        raise ValueError("window does not fit")
+    out = np.empty(shape, np.uint64)
+    if _load().oracle_window_sum_sat(_ptr(S), H, W, h, w, s, _ptr(out)):
+        raise ValueError("oracle_window_sum_sat rejected its arguments")
+    return out
+
+
+def window_sum_direct(img, h, w, s=1, squares=False):
+    """Window sums by direct summation of every window (uint64 output)."""
+    img, bpp, pitch = _image(img)
+    H, W = img.shape
+    shape = window_shape(H, W, h, w, s)
+    if shape is None:
+        raise ValueError("window does not fit")
+    out = np.empty(shape, np.uint64)
+    if _load().oracle_window_sum_direct(_ptr(img), bpp, H, W, pitch, h, w, s, int(squares), _ptr(out)):
+        raise ValueError("oracle_window_sum_direct rejected its arguments")
+    return out
+
+
+def window_at(img, y0, x0, h, w):
+    """(sum, sum of squares) of one window, summed directly."""
+    img, bpp, pitch = _image(img)
+    a, b = ctypes.c_uint64(), ctypes.c_uint64()
+    _load().oracle_window_at(_ptr(img), bpp, pitch, y0, x0, h, w, ctypes.byref(a), ctypes.byref(b))
+    return a.value, b.value
+
+
+def mean_std(sums, sum_sqs, n):
+    """FP64 window mean and population std from exact integer sums over n pixels."""
+    sums = np.ascontiguousarray(sums, dtype=np.uint64)
+    sum_sqs = np.ascontiguousarray(sum_sqs, dtype=np.uint64)
+    if sums.shape != sum_sqs.shape:
+        raise ValueError("shape mismatch")
+    mean = np.empty(sums.shape, np.float64)
+    std = np.empty(sums.shape, np.float64)
+    _load().oracle_mean_std(_ptr(sums), _ptr(sum_sqs), sums.size, int(n), _ptr(mean), _ptr(std))
+    return mean, std
+
+
+def window_stats(img, h, w, s=1):
+    """(sum, mean, std) of every window: integral images, corner lookups, then mean_std."""
+    S, Q = sat(img, squares=True)
+    sums = window_sum_sat(S, h, w, s)
+    sqs = window_sum_sat(Q, h, w, s)
+    mean, std = mean_std(sums, sqs, h * w)
+    return sums, mean, std
+
+
+def coverage_total(img, h, w, s=1):
+    """Sum of all window sums (mod 2^64), from pixels weighted by how many windows hold them."""
+    img, bpp, pitch = _image(img)
+    H, W = img.shape
+    return int(_load().oracle_coverage_total(_ptr(img), bpp, H, W, pitch, h, w, s))
+
+
+def stream(img, windows, s, rows, sat_rows=(), squares=False):
+    """Serial integral image over a large image keeping only a ring of rows.
+
+    windows: list of (h, w); rows: list (one per window) of ascending output-row indices.
+    Returns (outs, sat_out, total): outs[i] is a (len(rows[i]), ow_i) uint64 array, sat_out a
+    (len(sat_rows), W) uint64 array of table rows, total the last table entry (mod 2^64).
+    """
+    img, bpp, pitch = _image(img)
+    H, W = img.shape
+    nwin = len(windows)
+    wh = np.array([w[0] for w in windows], np.int64)
+    ww = np.array([w[1] for w in windows], np.int64)
+    nrows = np.array([len(r) for r in rows], np.int64)
+    flat = np.concatenate([np.asarray(r, np.int64) for r in rows]) if nwin else np.zeros(0, np.int64)
+    ows = []
+    for (h, w) in windows:
+        shape = window_shape(H, W, h, w, s)
+        if shape is None:
+            raise ValueError("window does not fit")
+        ows.append(shape[1])
+    out = np.zeros(int(sum(n * o for n, o in zip(nrows, ows))), np.uint64)
+    srows = np.asarray(sat_rows, np.int64)
+    sat_out = np.zeros((len(srows), W), np.uint64)
+    total = ctypes.c_uint64()
+    rc = _load().oracle_stream(_ptr(img), bpp, H, W, pitch, int(squares), nwin, _ptr(wh), _ptr(ww), s,
+                               _ptr(nrows), _ptr(flat), _ptr(out), len(srows), _ptr(srows),
+                               _ptr(sat_out), ctypes.byref(total))
+    if rc:
+        raise ValueError("oracle_stream failed (%d)" % rc)
+    outs, pos = [], 0
+    for n, o in zip(nrows, ows):
+        outs.append(out[pos:pos + n * o].reshape(n, o))
+        pos += n * o
+    return outs, sat_out, total.value
