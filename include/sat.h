@@ -1,0 +1,178 @@
+/*
+ * sat.h -- C ABI of libsat.so: integral image (summed-area table) and sliding-window statistics
+ * on an AMD Instinct MI355X (gfx950).
+ *
+ * The operations are those of Ockerman, Klamer, Haab, "Accelerating Biological Spatial Cluster
+ * Analysis with the Parallel Integral Image Technique":
+ *   sat_build        the integral image: entry (y, x) is the sum of every pixel above and to the
+ *                    left of (y, x), pixel (y, x) included (Sec. II-B; cost O(r*c), Sec. III-B);
+ *                    optionally the same table over squared pixels;
+ *   window_sum       the sum of every window position of the valid region, one output per
+ *                    position, (r-w+1)(c-w+1) of them at stride 1 (Sec. II-A, Sec. III-A), each by
+ *                    the four-corner lookup into the table (Sec. II-B; cost 4(r*c), Sec. III-B);
+ *   window_mean_std  the window average and standard deviation from the two tables (Sec. II-A);
+ *   window_sum_multi several window sizes from one table in one pass (Sec. I, Sec. V);
+ *   *_batched        the same over many images in one launch.
+ *
+ * Conventions shared by every call:
+ *   - Images are row-major, 8- or 16-bit unsigned, with a row pitch in ELEMENTS (>= width; the
+ *     base may have any alignment).  Widths and pitches are at most 2^24 elements, heights at
+ *     most 2^31-1 rows.  Tables are uint64_t, row-major, pitch in
+ *     elements.  Outputs are row-major with a pitch in elements.
+ *   - Every data pointer (image, tables, outputs, workspace) is a DEVICE pointer owned by the
+ *     caller; the library never allocates, frees or keeps device memory.
+ *   - Every compute call is asynchronous on `stream` (a hipStream_t passed as void*; NULL is the
+ *     default stream).  Results are valid once the stream has been synchronised.
+ *   - Arguments are validated completely, on the host, before any HIP call.  On any error the
+ *     call enqueues nothing and touches no output; the return value says why and
+ *     sat_last_error() gives a message.  No call throws, aborts or exits.
+ *   - Table arithmetic wraps modulo 2^64.  A window sum is exact whenever its true value is below
+ *     2^64 (every 8-bit window, and every 16-bit window of fewer than 2^32 pixels, squared or not).
+ *   - Window (k, l) covers rows k*stride .. k*stride+win_h-1 and columns l*stride ..
+ *     l*stride+win_w-1; only windows that fit entirely inside the image exist (valid region).
+ *   - Inputs and outputs must not overlap.  Calls on different streams may run concurrently
+ *     provided their outputs and workspaces are distinct.
+ */
+#ifndef SAT_H
+#define SAT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SAT_OK = 0,
+    SAT_ERR_ARG = 1,       /* NULL pointer, size < 1, pitch < width, bad dtype, overlap, ... */
+    SAT_ERR_WINDOW = 2,    /* win_h > H or win_w > W: the valid region is empty (Sec. III-A)    */
+    SAT_ERR_OVERFLOW = 3,  /* uint32 output asked for but win_h*win_w*max_pixel > UINT32_MAX,
+                              or an image too tall for exact 62-bit column totals                */
+    SAT_ERR_WORKSPACE = 4, /* workspace NULL or smaller than the matching *_workspace_bytes()   */
+    SAT_ERR_HIP = 5,       /* the HIP runtime refused a launch or a query                       */
+    SAT_ERR_DEVICE = 6     /* a kernel reported a protocol fault (see sat_workspace_check)      */
+} sat_status;
+
+typedef enum {
+    SAT_U8 = 1,   /* uint8_t pixels                                     */
+    SAT_U16 = 2,  /* uint16_t pixels                                    */
+    SAT_U32 = 3,  /* uint32_t window sums (or per-pixel maximum 2^32-1) */
+    SAT_U64 = 4,  /* uint64_t window sums                               */
+    SAT_F64 = 5   /* double                                             */
+} sat_dtype;
+
+/* Output shape of the valid region: out_h = (H - win_h) / stride + 1, out_w likewise
+ * (Sec. III-A gives (r-w+1)(c-w+1) positions for stride 1).  Pure host arithmetic.
+ * Errors: SAT_ERR_ARG (NULL out pointer, any size or the stride < 1), SAT_ERR_WINDOW. */
+sat_status window_out_shape(int64_t H, int64_t W, int64_t win_h, int64_t win_w, int64_t stride,
+                            int64_t *out_h, int64_t *out_w);
+
+/* Bytes of device workspace sat_build needs for an H x W image (with_sq != 0: also the squared
+ * table).  Returns 0 for invalid sizes.  The workspace holds the per-strip lookback words of the
+ * column scan and two control words; its contents need no initialisation and are scratch after
+ * the call returns, but the workspace must not be shared by two builds in flight. */
+size_t sat_build_workspace_bytes(int64_t H, int64_t W, sat_dtype pixel_type, int with_sq);
+
+/* Integral image of an H x W image (Sec. II-B, Sec. III-B):
+ *   sat[y*sat_pitch + x]    = sum_{i<=y, j<=x} image[i*image_pitch + j]           (mod 2^64)
+ *   sat_sq[y*sat_pitch + x] = sum_{i<=y, j<=x} image[i*image_pitch + j]^2        (mod 2^64)
+ * image: device, pixel_type SAT_U8 or SAT_U16, pitch image_pitch >= W elements.
+ * sat: device, H rows of sat_pitch >= W uint64_t; sat_sq: same shape and pitch, or NULL to skip
+ * the squared table.  Entries beyond column W-1 of each row are not written.
+ * workspace: device, >= sat_build_workspace_bytes(H, W, pixel_type, sat_sq != NULL) bytes.
+ * Errors: SAT_ERR_ARG, SAT_ERR_OVERFLOW (H * max_pixel^2 >= 2^62 with sat_sq, H * max_pixel
+ * >= 2^62 without), SAT_ERR_WORKSPACE, SAT_ERR_HIP. */
+sat_status sat_build(const void *image, sat_dtype pixel_type, int64_t H, int64_t W,
+                     int64_t image_pitch, uint64_t *sat, uint64_t *sat_sq, int64_t sat_pitch,
+                     void *workspace, size_t workspace_bytes, void *stream);
+
+/* Sum of every window of the valid region by the four-corner lookup (Sec. II-B):
+ *   out[k*out_pitch + l] = T(y1, x1) - T(y0-1, x1) - T(y1, x0-1) + T(y0-1, x0-1),
+ *   y0 = k*stride, y1 = y0+win_h-1, x0 = l*stride, x1 = x0+win_w-1, T(-1, .) = T(., -1) = 0.
+ * sat: device table of an H x W image (pitch sat_pitch).  pixel_type gives the largest pixel the
+ * table may hold (SAT_U8: 255, SAT_U16: 65535, SAT_U32: 2^32-1 e.g. a table of squared 16-bit
+ * pixels) and is used only to refuse a uint32 output that could overflow.
+ * out: device, out_h rows (window_out_shape) of out_pitch >= out_w elements of out_type
+ * (SAT_U32 or SAT_U64).
+ * Errors: SAT_ERR_ARG, SAT_ERR_WINDOW, SAT_ERR_OVERFLOW, SAT_ERR_HIP. */
+sat_status window_sum(const uint64_t *sat, sat_dtype pixel_type, int64_t H, int64_t W,
+                      int64_t sat_pitch, int64_t win_h, int64_t win_w, int64_t stride,
+                      void *out, sat_dtype out_type, int64_t out_pitch, void *stream);
+
+/* Window mean and population standard deviation (Sec. II-A) from the table of pixels and the
+ * table of squared pixels, n = win_h*win_w:
+ *   S1 = window sum of sat, Q1 = window sum of sat_sq (both by the corner lookup, exact);
+ *   mean = (double)S1 / n;  std = sqrt((double)(n*Q1 - S1^2)) / n, the numerator formed
+ *   exactly in 128-bit integers and rounded to double once.
+ * sat_sq may equal sat for 0/1 images.  sum_out (uint64_t S1) may be NULL; mean_out and
+ * std_out are required.  All three share out_pitch (>= out_w elements).
+ * Errors: SAT_ERR_ARG, SAT_ERR_WINDOW, SAT_ERR_HIP. */
+sat_status window_mean_std(const uint64_t *sat, const uint64_t *sat_sq, int64_t H, int64_t W,
+                           int64_t sat_pitch, int64_t win_h, int64_t win_w, int64_t stride,
+                           uint64_t *sum_out, double *mean_out, double *std_out,
+                           int64_t out_pitch, void *stream);
+
+/* Several window sizes from one table in one pass over it (Sec. I: variable window sizes in
+ * constant time; Sec. V: multiple window sizes from a single integral image).  Window i is
+ * win_h[i] x win_w[i]; all share `stride`; outs[i] (device, out_type elements, pitch
+ * out_pitch[i]) receives exactly what window_sum would write for it.  1 <= n_windows <= 8.
+ * win_h, win_w, outs and out_pitch are host arrays read before the call returns.
+ * Errors: as window_sum, for any window. */
+sat_status window_sum_multi(const uint64_t *sat, sat_dtype pixel_type, int64_t H, int64_t W,
+                            int64_t sat_pitch, int32_t n_windows, const int64_t *win_h,
+                            const int64_t *win_w, int64_t stride, void *const *outs,
+                            sat_dtype out_type, const int64_t *out_pitch, void *stream);
+
+/* One image of a batch (host struct; the pointers in it are device pointers).  For
+ * sat_build_batched: image, H, W, image_pitch, sat, sat_sq (may be NULL), sat_pitch.  For
+ * window_mean_std_batched additionally sum_out (may be NULL), mean_out, std_out, out_pitch. */
+typedef struct {
+    const void *image;
+    int64_t H, W, image_pitch;
+    uint64_t *sat;
+    uint64_t *sat_sq;
+    int64_t sat_pitch;
+    uint64_t *sum_out;
+    double *mean_out;
+    double *std_out;
+    int64_t out_pitch;
+} sat_batch_item;
+
+/* Workspace bytes for sat_build_batched / window_mean_std_batched over these items. */
+size_t sat_batch_workspace_bytes(const sat_batch_item *items, int32_t n, sat_dtype pixel_type,
+                                 int with_sq);
+
+/* The integral images of n images of uneven sizes in ONE persistent launch: workgroups take
+ * (image, strip) work items from one queue; each image gets its own column lookback state.
+ * Same per-image contract as sat_build.  items is a host array copied before the call returns.
+ * Errors: as sat_build, for any item (index in the message), SAT_ERR_ARG for n < 1. */
+sat_status sat_build_batched(const sat_batch_item *items, int32_t n, sat_dtype pixel_type,
+                             void *workspace, size_t workspace_bytes, void *stream);
+
+/* window_mean_std over n images in one launch, one window size and stride for all.  Items
+ * whose image is smaller than the window are an error (SAT_ERR_WINDOW, index in the message). */
+sat_status window_mean_std_batched(const sat_batch_item *items, int32_t n, int64_t win_h,
+                                   int64_t win_w, int64_t stride, void *workspace,
+                                   size_t workspace_bytes, void *stream);
+
+/* Synchronises `stream` and reads the fault word a build left in `workspace`: SAT_OK, or
+ * SAT_ERR_DEVICE if a column-lookback wait hit its spin bound (the tables of that call are then
+ * unreliable), or SAT_ERR_HIP.  Meant for tests and debugging; the fast path never waits. */
+sat_status sat_workspace_check(void *workspace, void *stream);
+
+/* Message for the last error returned on the calling thread (static storage, never NULL). */
+const char *sat_last_error(void);
+
+/* Build and tuning introspection: number of compiled kernel variants of kind 0 (table build)
+ * or 1 (window gather), the name of variant i, and the variant a later call on this thread
+ * will use (-1 restores the built-in choice).  Used by the tile-shape tuner. */
+int32_t sat_variant_count(int32_t kind);
+const char *sat_variant_name(int32_t kind, int32_t index);
+sat_status sat_force_variant(int32_t kind, int32_t index);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SAT_H */

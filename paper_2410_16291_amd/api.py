@@ -1,0 +1,195 @@
+"""torch-tensor face of libsat: sat_build, window_sum, window_mean_std, window_sum_multi.
+
+torch supplies device memory and the stream; every step of the computation runs in the HIP
+kernels behind the C ABI.  Tables are uint64 tensors of shape (H, W) that may be views of a
+wider allocation (row pitch = stride(0)); outputs likewise.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Dict, List, Optional, Sequence, Tuple
+
+import torch
+
+from . import _lib
+from ._lib import SAT_F64, SAT_U8, SAT_U16, SAT_U32, SAT_U64, BatchItem, check
+
+_PIXEL = {torch.uint8: SAT_U8, torch.uint16: SAT_U16}
+_MAXPIX = {"u8": 255, "u16": 65535, "u32": (1 << 32) - 1}
+_PIXCODE = {"u8": SAT_U8, "u16": SAT_U16, "u32": SAT_U32}
+
+# Per (device, stream) workspace cache: a build workspace may not be shared by two builds in
+# flight, and builds on one stream are ordered, so one buffer per stream suffices.
+_workspaces: Dict[Tuple[int, int], torch.Tensor] = {}
+
+
+def _stream_handle(device: torch.device, stream: Optional[torch.cuda.Stream]) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream(device)
+    return s.cuda_stream
+
+
+def _require_cuda(t: torch.Tensor, name: str) -> None:
+    if not t.is_cuda:
+        raise ValueError("%s must be a device (cuda) tensor" % name)
+    if t.dim() != 2 or t.stride(1) != 1:
+        raise ValueError("%s must be 2-D with unit column stride" % name)
+
+
+def workspace(nbytes: int, device: torch.device, stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:
+    """A cached device workspace of at least nbytes for builds on this stream."""
+    key = (device.index if device.index is not None else torch.cuda.current_device(),
+           _stream_handle(device, stream))
+    ws = _workspaces.get(key)
+    if ws is None or ws.numel() < nbytes:
+        ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+        _workspaces[key] = ws
+    return ws
+
+
+def table_pitch(W: int) -> int:
+    """Row pitch (elements) used for tables allocated here: width rounded up to 16 elements."""
+    return (W + 15) // 16 * 16
+
+
+def empty_table(H: int, W: int, device, pitch: Optional[int] = None) -> torch.Tensor:
+    pitch = table_pitch(W) if pitch is None else pitch
+    return torch.empty((H, pitch), dtype=torch.uint64, device=device)[:, :W]
+
+
+def build_workspace_bytes(H: int, W: int, pixel_type: int, squares: bool) -> int:
+    n = _lib.load().sat_build_workspace_bytes(H, W, pixel_type, int(squares))
+    if n == 0:
+        raise ValueError("invalid image size %dx%d" % (H, W))
+    return n
+
+
+def sat_build(image: torch.Tensor, squares: bool = False, sat: Optional[torch.Tensor] = None,
+              sat_sq: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None,
+              stream: Optional[torch.cuda.Stream] = None):
+    """Integral image of a 2-D uint8/uint16 device image; with squares=True also of its squares.
+
+    Returns S, or (S, Q).  S[y, x] = sum of image[:y+1, :x+1] (mod 2^64).
+    """
+    _require_cuda(image, "image")
+    if image.dtype not in _PIXEL:
+        raise ValueError("image dtype must be uint8 or uint16")
+    H, W = image.shape
+    dev = image.device
+    S = sat if sat is not None else empty_table(H, W, dev)
+    Q = sat_sq if sat_sq is not None else (empty_table(H, W, dev, S.stride(0)) if squares else None)
+    _require_cuda(S, "sat")
+    if Q is not None:
+        _require_cuda(Q, "sat_sq")
+        if Q.stride(0) != S.stride(0):
+            raise ValueError("sat and sat_sq must share a row pitch")
+    ptype = _PIXEL[image.dtype]
+    need = build_workspace_bytes(H, W, ptype, Q is not None)
+    wsb = ws if ws is not None else workspace(need, dev, stream)
+    check(_lib.load().sat_build(image.data_ptr(), ptype, H, W, image.stride(0), S.data_ptr(),
+                                Q.data_ptr() if Q is not None else None, S.stride(0), wsb.data_ptr(),
+                                wsb.numel(), _stream_handle(dev, stream)))
+    return (S, Q) if squares or sat_sq is not None else S
+
+
+def out_shape(H: int, W: int, h: int, w: int, stride: int = 1) -> Tuple[int, int]:
+    oh, ow = ctypes.c_int64(), ctypes.c_int64()
+    check(_lib.load().window_out_shape(H, W, h, w, stride, ctypes.byref(oh), ctypes.byref(ow)))
+    return oh.value, ow.value
+
+
+def default_out_dtype(h: int, w: int, pixel_type: str) -> torch.dtype:
+    return torch.uint32 if h * w * _MAXPIX[pixel_type] <= 0xFFFFFFFF else torch.uint64
+
+
+def window_sum(S: torch.Tensor, h: int, w: int, stride: int = 1, pixel_type: str = "u16",
+               out_dtype: Optional[torch.dtype] = None, out: Optional[torch.Tensor] = None,
+               stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:
+    """Sum of every h x w window (valid region, step `stride`) by four-corner lookup into S."""
+    _require_cuda(S, "sat")
+    H, W = S.shape
+    oh, ow = out_shape(H, W, h, w, stride)
+    if out is None:
+        out_dtype = out_dtype or default_out_dtype(h, w, pixel_type)
+        out = torch.empty((oh, ow), dtype=out_dtype, device=S.device)
+    _require_cuda(out, "out")
+    code = {torch.uint32: SAT_U32, torch.uint64: SAT_U64}.get(out.dtype)
+    if code is None:
+        raise ValueError("out dtype must be uint32 or uint64")
+    check(_lib.load().window_sum(S.data_ptr(), _PIXCODE[pixel_type], H, W, S.stride(0), h, w, stride,
+                                 out.data_ptr(), code, out.stride(0), _stream_handle(S.device, stream)))
+    return out
+
+
+def window_sum_multi(S: torch.Tensor, windows: Sequence[Tuple[int, int]], stride: int = 1,
+                     pixel_type: str = "u16", out_dtype: Optional[torch.dtype] = None,
+                     stream: Optional[torch.cuda.Stream] = None) -> List[torch.Tensor]:
+    """window_sum for several (h, w) windows in one pass over S."""
+    _require_cuda(S, "sat")
+    H, W = S.shape
+    n = len(windows)
+    if out_dtype is None:
+        big = any(default_out_dtype(h, w, pixel_type) == torch.uint64 for h, w in windows)
+        out_dtype = torch.uint64 if big else torch.uint32
+    outs = [torch.empty(out_shape(H, W, h, w, stride), dtype=out_dtype, device=S.device) for h, w in windows]
+    hs = (ctypes.c_int64 * n)(*[h for h, _ in windows])
+    ws = (ctypes.c_int64 * n)(*[w for _, w in windows])
+    ptrs = (ctypes.c_void_p * n)(*[o.data_ptr() for o in outs])
+    pitches = (ctypes.c_int64 * n)(*[o.stride(0) for o in outs])
+    code = SAT_U32 if out_dtype == torch.uint32 else SAT_U64
+    check(_lib.load().window_sum_multi(S.data_ptr(), _PIXCODE[pixel_type], H, W, S.stride(0), n, hs, ws, stride,
+                                       ptrs, code, pitches, _stream_handle(S.device, stream)))
+    return outs
+
+
+def window_mean_std(S: torch.Tensor, Q: torch.Tensor, h: int, w: int, stride: int = 1, with_sum: bool = True,
+                    stream: Optional[torch.cuda.Stream] = None):
+    """(sum or None, mean, std) of every window from the tables of pixels and squared pixels."""
+    _require_cuda(S, "sat")
+    _require_cuda(Q, "sat_sq")
+    if Q.shape != S.shape or Q.stride(0) != S.stride(0):
+        raise ValueError("sat and sat_sq must have the same shape and pitch")
+    H, W = S.shape
+    oh, ow = out_shape(H, W, h, w, stride)
+    pitch = ow
+    s1 = torch.empty((oh, pitch), dtype=torch.uint64, device=S.device) if with_sum else None
+    mean = torch.empty((oh, pitch), dtype=torch.float64, device=S.device)
+    std = torch.empty((oh, pitch), dtype=torch.float64, device=S.device)
+    check(_lib.load().window_mean_std(S.data_ptr(), Q.data_ptr(), H, W, S.stride(0), h, w, stride,
+                                      s1.data_ptr() if s1 is not None else None, mean.data_ptr(), std.data_ptr(),
+                                      pitch, _stream_handle(S.device, stream)))
+    return s1, mean, std
+
+
+def workspace_check(ws: torch.Tensor, stream: Optional[torch.cuda.Stream] = None) -> None:
+    """Synchronise and raise if a build that used `ws` reported a lookback fault."""
+    check(_lib.load().sat_workspace_check(ws.data_ptr(), _stream_handle(ws.device, stream)))
+
+
+def variants(kind: int) -> List[str]:
+    lib = _lib.load()
+    return [lib.sat_variant_name(kind, i).decode() for i in range(lib.sat_variant_count(kind))]
+
+
+def force_variant(kind: int, index: int) -> None:
+    """Make later calls on this thread use build (kind 0) or gather (kind 1) variant `index`."""
+    check(_lib.load().sat_force_variant(kind, index))
+
+
+# ---------------------------------------------------------------- batches
+
+def batch_items(images: Sequence[torch.Tensor], tables: Sequence[Tuple[torch.Tensor, Optional[torch.Tensor]]],
+                outs: Optional[Sequence[Tuple[Optional[torch.Tensor], torch.Tensor, torch.Tensor]]] = None):
+    n = len(tables)
+    arr = (BatchItem * n)()
+    for i, (S, Q) in enumerate(tables):
+        it = arr[i]
+        if images is not None:
+            img = images[i]
+            it.image, it.image_pitch = img.data_ptr(), img.stride(0)
+        it.H, it.W = S.shape
+        it.sat, it.sat_sq, it.sat_pitch = S.data_ptr(), (Q.data_ptr() if Q is not None else None), S.stride(0)
+        if outs is not None:
+            s1, mean, std = outs[i]
+            it.sum_out = s1.data_ptr() if s1 is not None else None
+            it.mean_out, it.std_out, it.out_pitch = mean.data_ptr(), std.data_ptr(), mean.stride(0)
+    return arr

@@ -1,0 +1,562 @@
+// sat_api.cpp -- the C ABI of libsat.so (declared in include/sat.h): argument validation, shape
+// and workspace arithmetic, kernel-variant choice and launch.  Validation is complete and
+// synchronous before the first HIP call, so every error path is testable without a GPU.
+#include "sat.h"
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "sat_internal.h"
+
+namespace {
+
+thread_local std::string g_err = "no error";
+thread_local int g_force[2] = {-1, -1};
+
+sat_status fail(sat_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+sat_status ok() {
+    g_err = "no error";
+    return SAT_OK;
+}
+
+sat_status hip_fail(hipError_t e, const char *what) {
+    return fail(SAT_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+constexpr int64_t kMaxDim = (1ll << 31) - 1;
+constexpr int64_t kMaxRowElems = 1ll << 24;   // 32-bit buffer offsets over a strip of rows stay in range
+
+int bytes_of(sat_dtype t) {
+    switch (t) {
+        case SAT_U8: return 1;
+        case SAT_U16: return 2;
+        case SAT_U32: return 4;
+        case SAT_U64: return 8;
+        case SAT_F64: return 8;
+    }
+    return 0;
+}
+
+uint64_t max_pixel(sat_dtype t) {
+    switch (t) {
+        case SAT_U8: return 255u;
+        case SAT_U16: return 65535u;
+        case SAT_U32: return 4294967295u;
+        default: return 0;
+    }
+}
+
+// Byte extent [p, p + bytes) of a row-major 2-D array.
+struct Span {
+    uintptr_t lo = 0, hi = 0;
+};
+Span span(const void *p, int64_t rows, int64_t pitch, int64_t cols, int elem) {
+    Span s;
+    if (!p) return s;
+    s.lo = reinterpret_cast<uintptr_t>(p);
+    s.hi = s.lo + static_cast<uintptr_t>(((rows - 1) * pitch + cols) * elem);
+    return s;
+}
+bool overlap(const Span &a, const Span &b) {
+    return a.lo != a.hi && b.lo != b.hi && a.lo < b.hi && b.lo < a.hi;
+}
+
+sat_status check_dims(int64_t H, int64_t W, const char *who) {
+    if (H < 1 || W < 1) return fail(SAT_ERR_ARG, "%s: image size %lld x %lld must be at least 1 x 1", who,
+                                    (long long)H, (long long)W);
+    if (H > kMaxDim || W > kMaxRowElems)
+        return fail(SAT_ERR_ARG, "%s: image height above 2^31-1 or width above 2^24", who);
+    return SAT_OK;
+}
+
+sat_status check_pitch(int64_t pitch, int64_t W, int64_t H, int elem, const char *who, const char *what) {
+    if (pitch < W) return fail(SAT_ERR_ARG, "%s: %s pitch %lld is below the width %lld", who, what,
+                               (long long)pitch, (long long)W);
+    // 32-bit buffer offsets span up to 128 rows of a strip; rows * pitch * elem stays far from
+    // int64 overflow
+    if (pitch > kMaxRowElems || H > ((1ll << 60) / (pitch * elem)))
+        return fail(SAT_ERR_ARG, "%s: %s pitch above 2^24 elements or extent too large", who, what);
+    return SAT_OK;
+}
+
+// ------------------------------------------------------------------ build planning
+
+struct BuildPlan {
+    int variant;
+    std::vector<satk::BuildDesc> descs;
+    int64_t total_items = 0;
+    int64_t state_words = 0;
+};
+
+int device_cus() {
+    static int cus = 0;
+    if (cus == 0) {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+            cus = v;
+        else
+            cus = 256;
+    }
+    return cus;
+}
+
+// Tallest strips that still give every compute unit about two strips to work on.
+int choose_build_variant(int64_t total_rows, int n_images) {
+    const int v = g_force[0];
+    if (v >= 0) return v;
+    const int64_t want = 2ll * device_cus();
+    const int64_t strips64 = (total_rows + 63 * n_images) / 64;
+    if (strips64 >= want) return 0;
+    const int64_t strips32 = (total_rows + 31 * n_images) / 32;
+    if (strips32 >= want) return 1;
+    return 2;
+}
+
+int64_t state_words_for(const satk::BuildVariant &v, int64_t H, int64_t W, bool sq) {
+    const int64_t strips = (H + v.th() - 1) / v.th();
+    const int64_t wp = (W + v.bw() - 1) / v.bw() * v.bw();
+    int64_t words = strips * wp * (sq ? 2 : 1);
+    return (words + 1) & ~1ll;
+}
+
+int64_t max_state_words(int64_t H, int64_t W, bool sq) {
+    int64_t m = 0;
+    for (int i = 0; i < satk::build_variant_count(); ++i) {
+        const int64_t w = state_words_for(satk::build_variant(i), H, W, sq);
+        if (w > m) m = w;
+    }
+    return m;
+}
+
+void fill_desc(satk::BuildDesc &d, const satk::BuildVariant &v, const void *image, int bpp, int64_t H,
+               int64_t W, int64_t ipitch, uint64_t *sat, uint64_t *sat_sq, int64_t spitch) {
+    d.img = image;
+    d.S = sat;
+    d.Q = sat_sq;
+    d.H = H;
+    d.W = W;
+    d.ipitch = ipitch;
+    d.spitch = spitch;
+    d.nstrips = static_cast<int32_t>((H + v.th() - 1) / v.th());
+    d.nblocks = static_cast<int32_t>((W + v.bw() - 1) / v.bw());
+    d.Wp = static_cast<int64_t>(d.nblocks) * v.bw();
+    const uintptr_t ia = reinterpret_cast<uintptr_t>(image);
+    const int64_t row_bytes = ipitch * bpp;
+    d.img_vb = 0;
+    for (int vb = 16; vb >= 4; vb /= 2)
+        if (ia % vb == 0 && row_bytes % vb == 0 && vb <= v.bw() * bpp) {
+            d.img_vb = vb;
+            break;
+        }
+    const bool sa = reinterpret_cast<uintptr_t>(sat) % 16 == 0 &&
+                    (!sat_sq || reinterpret_cast<uintptr_t>(sat_sq) % 16 == 0);
+    d.sat_vec = (sa && spitch % 2 == 0) ? 1 : 0;
+}
+
+sat_status validate_build_item(const void *image, sat_dtype pixel_type, int64_t H, int64_t W, int64_t ipitch,
+                               const uint64_t *sat, const uint64_t *sat_sq, int64_t spitch, const char *who) {
+    if (!image || !sat) return fail(SAT_ERR_ARG, "%s: image and sat must be non-NULL", who);
+    if (pixel_type != SAT_U8 && pixel_type != SAT_U16)
+        return fail(SAT_ERR_ARG, "%s: pixel_type must be SAT_U8 or SAT_U16", who);
+    sat_status st = check_dims(H, W, who);
+    if (st) return st;
+    const int bpp = bytes_of(pixel_type);
+    if ((st = check_pitch(ipitch, W, H, bpp, who, "image"))) return st;
+    if ((st = check_pitch(spitch, W, H, 8, who, "table"))) return st;
+    if (sat == sat_sq) return fail(SAT_ERR_ARG, "%s: sat and sat_sq must be distinct", who);
+    const unsigned __int128 m = max_pixel(pixel_type);
+    const unsigned __int128 col = static_cast<unsigned __int128>(H) * (sat_sq ? m * m : m);
+    if (col >= (static_cast<unsigned __int128>(1) << 62))
+        return fail(SAT_ERR_OVERFLOW, "%s: %lld rows are too many for exact 62-bit column totals", who,
+                    (long long)H);
+    const Span si = span(image, H, ipitch, W, bpp), ss = span(sat, H, spitch, W, 8),
+               sq = span(sat_sq, H, spitch, W, 8);
+    if (overlap(si, ss) || overlap(si, sq) || overlap(ss, sq))
+        return fail(SAT_ERR_ARG, "%s: image, sat and sat_sq must not overlap", who);
+    return SAT_OK;
+}
+
+// ------------------------------------------------------------------ gather planning
+
+sat_status validate_window(const uint64_t *sat, int64_t H, int64_t W, int64_t spitch, int64_t win_h,
+                           int64_t win_w, int64_t stride, const char *who, int64_t *oh, int64_t *ow) {
+    if (!sat) return fail(SAT_ERR_ARG, "%s: sat must be non-NULL", who);
+    sat_status st = check_dims(H, W, who);
+    if (st) return st;
+    if ((st = check_pitch(spitch, W, H, 8, who, "table"))) return st;
+    if (win_h < 1 || win_w < 1 || stride < 1)
+        return fail(SAT_ERR_ARG, "%s: window %lld x %lld and stride %lld must be >= 1", who, (long long)win_h,
+                    (long long)win_w, (long long)stride);
+    if (win_h > H || win_w > W)
+        return fail(SAT_ERR_WINDOW, "%s: window %lld x %lld does not fit the %lld x %lld image", who,
+                    (long long)win_h, (long long)win_w, (long long)H, (long long)W);
+    *oh = (H - win_h) / stride + 1;
+    *ow = (W - win_w) / stride + 1;
+    return SAT_OK;
+}
+
+satk::GatherDesc gather_desc(const uint64_t *sat, const uint64_t *sat_sq, int64_t spitch, int64_t oh, int64_t ow,
+                             int64_t win_h, int64_t win_w, int64_t stride, void *out, double *mean, double *stdv,
+                             int64_t opitch) {
+    satk::GatherDesc d{};
+    d.S = sat;
+    d.Q = sat_sq;
+    d.spitch = spitch;
+    d.oh = oh;
+    d.ow = ow;
+    d.win_h = win_h;
+    d.win_w = win_w;
+    d.stride = stride;
+    d.out = out;
+    d.mean = mean;
+    d.stdv = stdv;
+    d.opitch = opitch;
+    return d;
+}
+
+constexpr int64_t kMeanStdChunk = 512;   // outputs per mean/std work item (256 threads x 2)
+
+}  // namespace
+
+extern "C" {
+
+const char *sat_last_error(void) { return g_err.c_str(); }
+
+sat_status window_out_shape(int64_t H, int64_t W, int64_t win_h, int64_t win_w, int64_t stride, int64_t *out_h,
+                            int64_t *out_w) {
+    if (!out_h || !out_w) return fail(SAT_ERR_ARG, "window_out_shape: output pointers must be non-NULL");
+    if (H < 1 || W < 1 || win_h < 1 || win_w < 1 || stride < 1)
+        return fail(SAT_ERR_ARG, "window_out_shape: sizes and stride must be >= 1");
+    if (win_h > H || win_w > W) return fail(SAT_ERR_WINDOW, "window_out_shape: window larger than image");
+    *out_h = (H - win_h) / stride + 1;
+    *out_w = (W - win_w) / stride + 1;
+    return ok();
+}
+
+size_t sat_build_workspace_bytes(int64_t H, int64_t W, sat_dtype pixel_type, int with_sq) {
+    if (H < 1 || W < 1 || H > kMaxDim || W > kMaxDim) return 0;
+    if (pixel_type != SAT_U8 && pixel_type != SAT_U16) return 0;
+    return sizeof(satk::BuildCtrl) + 8 * static_cast<size_t>(max_state_words(H, W, with_sq != 0));
+}
+
+sat_status sat_build(const void *image, sat_dtype pixel_type, int64_t H, int64_t W, int64_t image_pitch,
+                     uint64_t *sat, uint64_t *sat_sq, int64_t sat_pitch, void *workspace, size_t workspace_bytes,
+                     void *stream) {
+    const char *who = "sat_build";
+    sat_status st = validate_build_item(image, pixel_type, H, W, image_pitch, sat, sat_sq, sat_pitch, who);
+    if (st) return st;
+    const size_t need = sat_build_workspace_bytes(H, W, pixel_type, sat_sq != nullptr);
+    if (!workspace || workspace_bytes < need)
+        return fail(SAT_ERR_WORKSPACE, "%s: workspace of %zu bytes is below the %zu needed", who, workspace_bytes,
+                    need);
+    if (reinterpret_cast<uintptr_t>(workspace) % 16)
+        return fail(SAT_ERR_ARG, "%s: workspace must be 16-byte aligned", who);
+    const Span sw{reinterpret_cast<uintptr_t>(workspace), reinterpret_cast<uintptr_t>(workspace) + workspace_bytes};
+    const int bpp = bytes_of(pixel_type);
+    if (overlap(sw, span(image, H, image_pitch, W, bpp)) || overlap(sw, span(sat, H, sat_pitch, W, 8)) ||
+        overlap(sw, span(sat_sq, H, sat_pitch, W, 8)))
+        return fail(SAT_ERR_ARG, "%s: workspace overlaps an input or output", who);
+    const int v = choose_build_variant(H, 1);
+    if (v < 0 || v >= satk::build_variant_count()) return fail(SAT_ERR_ARG, "%s: forced variant out of range", who);
+    const satk::BuildVariant &var = satk::build_variant(v);
+    satk::BuildDesc d{};
+    fill_desc(d, var, image, bpp, H, W, image_pitch, sat, sat_sq, sat_pitch);
+    d.state_off = 0;
+    d.state_q_off = static_cast<int64_t>(d.nstrips) * d.Wp;
+    d.first_item = 0;
+    const int64_t words = state_words_for(var, H, W, sat_sq != nullptr);
+    hipError_t e = satk::launch_build(v, bpp, sat_sq != nullptr, &d, 1, nullptr, d.nstrips, workspace, words,
+                                      static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, who);
+    return ok();
+}
+
+sat_status window_sum(const uint64_t *sat, sat_dtype pixel_type, int64_t H, int64_t W, int64_t sat_pitch,
+                      int64_t win_h, int64_t win_w, int64_t stride, void *out, sat_dtype out_type, int64_t out_pitch,
+                      void *stream) {
+    const char *who = "window_sum";
+    int64_t oh = 0, ow = 0;
+    sat_status st = validate_window(sat, H, W, sat_pitch, win_h, win_w, stride, who, &oh, &ow);
+    if (st) return st;
+    if (!out) return fail(SAT_ERR_ARG, "%s: out must be non-NULL", who);
+    if (pixel_type != SAT_U8 && pixel_type != SAT_U16 && pixel_type != SAT_U32)
+        return fail(SAT_ERR_ARG, "%s: pixel_type must be SAT_U8, SAT_U16 or SAT_U32", who);
+    if (out_type != SAT_U32 && out_type != SAT_U64)
+        return fail(SAT_ERR_ARG, "%s: out_type must be SAT_U32 or SAT_U64", who);
+    if (out_type == SAT_U32) {
+        const unsigned __int128 worst = static_cast<unsigned __int128>(win_h) * static_cast<unsigned __int128>(win_w) *
+                                        max_pixel(pixel_type);
+        if (worst > 0xffffffffu)
+            return fail(SAT_ERR_OVERFLOW, "%s: a %lld x %lld window of this pixel type can exceed uint32", who,
+                        (long long)win_h, (long long)win_w);
+    }
+    if ((st = check_pitch(out_pitch, ow, oh, bytes_of(out_type), who, "output"))) return st;
+    if (overlap(span(out, oh, out_pitch, ow, bytes_of(out_type)), span(sat, H, sat_pitch, W, 8)))
+        return fail(SAT_ERR_ARG, "%s: out overlaps the table", who);
+    int v = g_force[1];
+    if (v < 0) v = 0;
+    if (v >= satk::gather_variant_count()) return fail(SAT_ERR_ARG, "%s: forced variant out of range", who);
+    satk::GatherDesc d = gather_desc(sat, nullptr, sat_pitch, oh, ow, win_h, win_w, stride, out, nullptr, nullptr,
+                                     out_pitch);
+    hipError_t e = satk::launch_window_sum(v, d, out_type == SAT_U64, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, who);
+    return ok();
+}
+
+sat_status window_sum_multi(const uint64_t *sat, sat_dtype pixel_type, int64_t H, int64_t W, int64_t sat_pitch,
+                            int32_t n_windows, const int64_t *win_h, const int64_t *win_w, int64_t stride,
+                            void *const *outs, sat_dtype out_type, const int64_t *out_pitch, void *stream) {
+    const char *who = "window_sum_multi";
+    if (n_windows < 1 || n_windows > 8) return fail(SAT_ERR_ARG, "%s: n_windows must be 1..8", who);
+    if (!win_h || !win_w || !outs || !out_pitch) return fail(SAT_ERR_ARG, "%s: NULL array argument", who);
+    if (pixel_type != SAT_U8 && pixel_type != SAT_U16 && pixel_type != SAT_U32)
+        return fail(SAT_ERR_ARG, "%s: pixel_type must be SAT_U8, SAT_U16 or SAT_U32", who);
+    if (out_type != SAT_U32 && out_type != SAT_U64)
+        return fail(SAT_ERR_ARG, "%s: out_type must be SAT_U32 or SAT_U64", who);
+    satk::GatherDesc d[8];
+    Span spans[8];
+    const Span ssat = span(sat, H, sat_pitch, W, 8);
+    for (int i = 0; i < n_windows; ++i) {
+        int64_t oh = 0, ow = 0;
+        sat_status st = validate_window(sat, H, W, sat_pitch, win_h[i], win_w[i], stride, who, &oh, &ow);
+        if (st) return st;
+        if (!outs[i]) return fail(SAT_ERR_ARG, "%s: outs[%d] is NULL", who, i);
+        if (out_type == SAT_U32) {
+            const unsigned __int128 worst = static_cast<unsigned __int128>(win_h[i]) *
+                                            static_cast<unsigned __int128>(win_w[i]) * max_pixel(pixel_type);
+            if (worst > 0xffffffffu)
+                return fail(SAT_ERR_OVERFLOW, "%s: window %d can exceed uint32", who, i);
+        }
+        if ((st = check_pitch(out_pitch[i], ow, oh, bytes_of(out_type), who, "output"))) return st;
+        spans[i] = span(outs[i], oh, out_pitch[i], ow, bytes_of(out_type));
+        if (overlap(spans[i], ssat)) return fail(SAT_ERR_ARG, "%s: outs[%d] overlaps the table", who, i);
+        for (int j = 0; j < i; ++j)
+            if (overlap(spans[i], spans[j])) return fail(SAT_ERR_ARG, "%s: outs[%d] and outs[%d] overlap", who, j, i);
+        d[i] = gather_desc(sat, nullptr, sat_pitch, oh, ow, win_h[i], win_w[i], stride, outs[i], nullptr, nullptr,
+                           out_pitch[i]);
+    }
+    hipError_t e = satk::launch_window_sum_multi(d, n_windows, out_type == SAT_U64, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, who);
+    return ok();
+}
+
+sat_status window_mean_std(const uint64_t *sat, const uint64_t *sat_sq, int64_t H, int64_t W, int64_t sat_pitch,
+                           int64_t win_h, int64_t win_w, int64_t stride, uint64_t *sum_out, double *mean_out,
+                           double *std_out, int64_t out_pitch, void *stream) {
+    const char *who = "window_mean_std";
+    int64_t oh = 0, ow = 0;
+    sat_status st = validate_window(sat, H, W, sat_pitch, win_h, win_w, stride, who, &oh, &ow);
+    if (st) return st;
+    if (!sat_sq || !mean_out || !std_out)
+        return fail(SAT_ERR_ARG, "%s: sat_sq, mean_out and std_out must be non-NULL", who);
+    if ((st = check_pitch(out_pitch, ow, oh, 8, who, "output"))) return st;
+    const Span ssat = span(sat, H, sat_pitch, W, 8), ssq = span(sat_sq, H, sat_pitch, W, 8);
+    const Span so[3] = {span(sum_out, oh, out_pitch, ow, 8), span(mean_out, oh, out_pitch, ow, 8),
+                        span(std_out, oh, out_pitch, ow, 8)};
+    for (int i = 0; i < 3; ++i) {
+        if (overlap(so[i], ssat) || overlap(so[i], ssq))
+            return fail(SAT_ERR_ARG, "%s: an output overlaps a table", who);
+        for (int j = 0; j < i; ++j)
+            if (overlap(so[i], so[j])) return fail(SAT_ERR_ARG, "%s: outputs overlap each other", who);
+    }
+    satk::GatherDesc d = gather_desc(sat, sat_sq, sat_pitch, oh, ow, win_h, win_w, stride, sum_out, mean_out,
+                                     std_out, out_pitch);
+    hipError_t e = satk::launch_mean_std(&d, 1, nullptr, 0, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, who);
+    return ok();
+}
+
+// ------------------------------------------------------------------ batches
+
+static size_t round256(size_t b) { return (b + 255) & ~static_cast<size_t>(255); }
+
+size_t sat_batch_workspace_bytes(const sat_batch_item *items, int32_t n, sat_dtype pixel_type, int with_sq) {
+    if (!items || n < 1) return 0;
+    if (pixel_type != SAT_U8 && pixel_type != SAT_U16) return 0;
+    size_t words = 0;
+    for (int i = 0; i < n; ++i) {
+        if (items[i].H < 1 || items[i].W < 1 || items[i].H > kMaxDim || items[i].W > kMaxDim) return 0;
+        words += static_cast<size_t>(max_state_words(items[i].H, items[i].W, with_sq != 0));
+    }
+    const size_t descs = round256(static_cast<size_t>(n) *
+                                  (sizeof(satk::BuildDesc) > sizeof(satk::GatherDesc) ? sizeof(satk::BuildDesc)
+                                                                                      : sizeof(satk::GatherDesc)));
+    return sizeof(satk::BuildCtrl) + descs + 8 * words + 256;   // 256: alignment slack
+}
+
+sat_status sat_build_batched(const sat_batch_item *items, int32_t n, sat_dtype pixel_type, void *workspace,
+                             size_t workspace_bytes, void *stream) {
+    const char *who = "sat_build_batched";
+    if (!items || n < 1) return fail(SAT_ERR_ARG, "%s: need at least one item", who);
+    if (pixel_type != SAT_U8 && pixel_type != SAT_U16)
+        return fail(SAT_ERR_ARG, "%s: pixel_type must be SAT_U8 or SAT_U16", who);
+    const bool sq = items[0].sat_sq != nullptr;
+    int64_t rows = 0;
+    for (int i = 0; i < n; ++i) {
+        char tag[64];
+        snprintf(tag, sizeof tag, "%s item %d", who, i);
+        const sat_batch_item &it = items[i];
+        sat_status st = validate_build_item(it.image, pixel_type, it.H, it.W, it.image_pitch, it.sat, it.sat_sq,
+                                            it.sat_pitch, tag);
+        if (st) return st;
+        if ((it.sat_sq != nullptr) != sq)
+            return fail(SAT_ERR_ARG, "%s: item %d: every item or none must have sat_sq", who, i);
+        rows += it.H;
+    }
+    const bool with_sq = sq;
+    const size_t need = sat_batch_workspace_bytes(items, n, pixel_type, with_sq);
+    if (!workspace || workspace_bytes < need)
+        return fail(SAT_ERR_WORKSPACE, "%s: workspace of %zu bytes is below the %zu needed", who, workspace_bytes,
+                    need);
+    if (reinterpret_cast<uintptr_t>(workspace) % 256)
+        return fail(SAT_ERR_ARG, "%s: workspace must be 256-byte aligned", who);
+    // outputs of different items must not overlap each other or the workspace
+    const Span sw{reinterpret_cast<uintptr_t>(workspace), reinterpret_cast<uintptr_t>(workspace) + workspace_bytes};
+    const int bpp = bytes_of(pixel_type);
+    std::vector<Span> outs;
+    for (int i = 0; i < n; ++i) {
+        const sat_batch_item &it = items[i];
+        const Span a = span(it.sat, it.H, it.sat_pitch, it.W, 8), b = span(it.sat_sq, it.H, it.sat_pitch, it.W, 8);
+        if (overlap(a, sw) || overlap(b, sw) || overlap(span(it.image, it.H, it.image_pitch, it.W, bpp), sw))
+            return fail(SAT_ERR_ARG, "%s: item %d overlaps the workspace", who, i);
+        for (const Span &o : outs)
+            if (overlap(o, a) || overlap(o, b)) return fail(SAT_ERR_ARG, "%s: item %d tables overlap another", who, i);
+        outs.push_back(a);
+        if (b.lo != b.hi) outs.push_back(b);
+    }
+    const int v = choose_build_variant(rows, n);
+    if (v < 0 || v >= satk::build_variant_count()) return fail(SAT_ERR_ARG, "%s: forced variant out of range", who);
+    const satk::BuildVariant &var = satk::build_variant(v);
+    std::vector<satk::BuildDesc> d(n);
+    int64_t off = 0, items_total = 0;
+    for (int i = 0; i < n; ++i) {
+        const sat_batch_item &it = items[i];
+        fill_desc(d[i], var, it.image, bpp, it.H, it.W, it.image_pitch, it.sat, it.sat_sq, it.sat_pitch);
+        const int64_t plane = static_cast<int64_t>(d[i].nstrips) * d[i].Wp;
+        d[i].state_off = off;
+        d[i].state_q_off = off + plane;
+        off += plane * (with_sq ? 2 : 1);
+        d[i].first_item = items_total;
+        items_total += d[i].nstrips;
+    }
+    off = (off + 1) & ~1ll;
+    // Layout: [control 256 B][descriptors][state]; the kernels see the state right after the
+    // control header, so the descriptors go at the end of the used state.
+    char *base = static_cast<char *>(workspace);
+    const size_t desc_bytes = round256(static_cast<size_t>(n) * sizeof(satk::BuildDesc));
+    char *dev_desc = base + sizeof(satk::BuildCtrl) + 8 * static_cast<size_t>(off);
+    dev_desc = reinterpret_cast<char *>((reinterpret_cast<uintptr_t>(dev_desc) + 255) & ~static_cast<uintptr_t>(255));
+    if (dev_desc + desc_bytes > base + workspace_bytes)
+        return fail(SAT_ERR_WORKSPACE, "%s: workspace too small for the descriptor table", who);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = hipMemcpyAsync(dev_desc, d.data(), static_cast<size_t>(n) * sizeof(satk::BuildDesc),
+                                  hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, who);
+    e = satk::launch_build(v, bpp, with_sq, d.data(), n, reinterpret_cast<satk::BuildDesc *>(dev_desc), items_total,
+                           workspace, off, s);
+    if (e != hipSuccess) return hip_fail(e, who);
+    return ok();
+}
+
+sat_status window_mean_std_batched(const sat_batch_item *items, int32_t n, int64_t win_h, int64_t win_w,
+                                   int64_t stride, void *workspace, size_t workspace_bytes, void *stream) {
+    const char *who = "window_mean_std_batched";
+    if (!items || n < 1) return fail(SAT_ERR_ARG, "%s: need at least one item", who);
+    if (!workspace) return fail(SAT_ERR_WORKSPACE, "%s: workspace must be non-NULL", who);
+    if (reinterpret_cast<uintptr_t>(workspace) % 256)
+        return fail(SAT_ERR_ARG, "%s: workspace must be 256-byte aligned", who);
+    const size_t desc_bytes = round256(static_cast<size_t>(n) * sizeof(satk::GatherDesc));
+    if (workspace_bytes < desc_bytes)
+        return fail(SAT_ERR_WORKSPACE, "%s: workspace of %zu bytes is below the %zu needed", who, workspace_bytes,
+                    desc_bytes);
+    std::vector<satk::GatherDesc> d(n);
+    int64_t total = 0;
+    const Span sw{reinterpret_cast<uintptr_t>(workspace), reinterpret_cast<uintptr_t>(workspace) + workspace_bytes};
+    std::vector<Span> outs;
+    for (int i = 0; i < n; ++i) {
+        char tag[64];
+        snprintf(tag, sizeof tag, "%s item %d", who, i);
+        const sat_batch_item &it = items[i];
+        int64_t oh = 0, ow = 0;
+        sat_status st = validate_window(it.sat, it.H, it.W, it.sat_pitch, win_h, win_w, stride, tag, &oh, &ow);
+        if (st) return st;
+        if (!it.sat_sq || !it.mean_out || !it.std_out)
+            return fail(SAT_ERR_ARG, "%s: sat_sq, mean_out and std_out must be non-NULL", tag);
+        if ((st = check_pitch(it.out_pitch, ow, oh, 8, tag, "output"))) return st;
+        const Span so[3] = {span(it.sum_out, oh, it.out_pitch, ow, 8), span(it.mean_out, oh, it.out_pitch, ow, 8),
+                            span(it.std_out, oh, it.out_pitch, ow, 8)};
+        for (int a = 0; a < 3; ++a) {
+            if (overlap(so[a], sw)) return fail(SAT_ERR_ARG, "%s: output overlaps the workspace", tag);
+            for (const Span &o : outs)
+                if (overlap(o, so[a])) return fail(SAT_ERR_ARG, "%s: outputs overlap", tag);
+        }
+        for (int a = 0; a < 3; ++a)
+            if (so[a].lo != so[a].hi) outs.push_back(so[a]);
+        d[i] = gather_desc(it.sat, it.sat_sq, it.sat_pitch, oh, ow, win_h, win_w, stride, it.sum_out, it.mean_out,
+                           it.std_out, it.out_pitch);
+        d[i].chunks = (ow + kMeanStdChunk - 1) / kMeanStdChunk;
+        d[i].first_item = total;
+        total += oh * d[i].chunks;
+    }
+    for (int i = 0; i < n; ++i) {
+        const Span a = span(items[i].sat, items[i].H, items[i].sat_pitch, items[i].W, 8);
+        const Span b = span(items[i].sat_sq, items[i].H, items[i].sat_pitch, items[i].W, 8);
+        for (const Span &o : outs)
+            if (overlap(o, a) || overlap(o, b)) return fail(SAT_ERR_ARG, "%s: an output overlaps a table", who);
+    }
+    if (total > 0xffffffffll) return fail(SAT_ERR_ARG, "%s: too many work items", who);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = hipMemcpyAsync(workspace, d.data(), static_cast<size_t>(n) * sizeof(satk::GatherDesc),
+                                  hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, who);
+    e = satk::launch_mean_std(d.data(), n, static_cast<satk::GatherDesc *>(workspace), total, s);
+    if (e != hipSuccess) return hip_fail(e, who);
+    return ok();
+}
+
+sat_status sat_workspace_check(void *workspace, void *stream) {
+    if (!workspace) return fail(SAT_ERR_ARG, "sat_workspace_check: workspace must be non-NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "sat_workspace_check");
+    satk::BuildCtrl ctrl;
+    e = hipMemcpy(&ctrl, workspace, sizeof ctrl, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "sat_workspace_check");
+    if (ctrl.fault) return fail(SAT_ERR_DEVICE, "sat_workspace_check: a lookback wait exceeded its spin bound");
+    return ok();
+}
+
+int32_t sat_variant_count(int32_t kind) {
+    if (kind == 0) return satk::build_variant_count();
+    if (kind == 1) return satk::gather_variant_count();
+    return 0;
+}
+
+const char *sat_variant_name(int32_t kind, int32_t index) {
+    if (kind == 0 && index >= 0 && index < satk::build_variant_count()) return satk::build_variant(index).name;
+    if (kind == 1 && index >= 0 && index < satk::gather_variant_count()) return satk::gather_variant_name(index);
+    return "";
+}
+
+sat_status sat_force_variant(int32_t kind, int32_t index) {
+    if (kind != 0 && kind != 1) return fail(SAT_ERR_ARG, "sat_force_variant: kind must be 0 or 1");
+    if (index < -1 || index >= sat_variant_count(kind))
+        return fail(SAT_ERR_ARG, "sat_force_variant: index out of range");
+    g_force[kind] = index;
+    return ok();
+}
+
+}  // extern "C"

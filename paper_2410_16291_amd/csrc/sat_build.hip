@@ -1,0 +1,681 @@
+// sat_build.hip -- integral-image (summed-area table) construction for gfx950.
+//
+// The table is the inclusive 2-D prefix sum of the image (Sec. II-B); its cost is one pass over
+// the image (the O(r*c) term of Sec. III-B).  Decomposition used here:
+//
+//   S[y][x] = U_w[x] + sum_{y' = y0_w .. y} R[y'][x]
+//   R[y][x] = L[y] + (prefix of row y inside the current column block)
+//   U_w[x]  = S[y0_w - 1][x] = sum_{x' <= x} C_w[x']
+//   C_w[x]  = sum of column x above row y0_w  (strip column totals from the lookback, plus the
+//             rows of the waves above this one inside the strip)
+//
+// A workgroup owns one strip of TH = RW*NW rows and sweeps it left to right in blocks of
+// BW = 64*PX columns; wave w owns RW rows of the strip and lane l owns PX adjacent columns of a
+// block.  The row direction is handled by the sweep itself (the left carry L of each row is a
+// register); the column direction crosses strips, and the totals of the strips above come from
+// a decoupled lookback down each column:
+//   - for block b the strip publishes its column totals A (status "aggregate"),
+//   - reads the state of the strip above: an inclusive total P ends the walk, an aggregate is
+//     added and the walk continues one strip higher,
+//   - publishes P = (totals above) + A (status "prefix").
+// Each lookback word is a single 64-bit value, status in bits 62-63 and the column total in
+// bits 0-61, so a relaxed agent-scope atomic store or load moves a complete, self-describing
+// state and no fence is needed.  Strips are handed out by an atomic ticket, so a workgroup only
+// ever waits for strips whose workgroups have already started: forward progress does not depend
+// on dispatch order.  Every wait is bounded; a wait that exceeds the bound sets a fault word in
+// the workspace and the kernel still completes.
+//
+// The same strip code also runs in a reduce-then-scan mode (an ablation): one kernel writes the
+// strip column totals, a second scans them down each column, and the strip kernel then reads
+// its totals instead of looking back.
+//
+// Per-row work: the 64 lanes of a wave scan a row of BW pixels with DPP (row_shr 1/2/4/8 within
+// rows of 16 lanes, then row_bcast 15 and 31 across them) in 32-bit integers, which cannot
+// overflow for a block (BW * 65535 < 2^32); the 64-bit carries are added once per pixel.
+#include "sat_internal.h"
+
+#include <type_traits>
+
+namespace satk {
+namespace {
+
+constexpr uint64_t kStAggregate = 1ull << 62;
+constexpr uint64_t kStPrefix = 2ull << 62;
+constexpr uint64_t kValueMask = (1ull << 62) - 1;
+constexpr uint32_t kSpinLimit = 1u << 22;
+
+typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// ------------------------------------------------------------------ cross-lane helpers
+
+template <int CTRL, int ROW_MASK, bool BOUND_ZERO>
+__device__ __forceinline__ uint32_t dpp(uint32_t v) {
+    return static_cast<uint32_t>(
+        __builtin_amdgcn_update_dpp(0, static_cast<int>(v), CTRL, ROW_MASK, 0xf, BOUND_ZERO));
+}
+
+template <int CTRL, int ROW_MASK, bool BOUND_ZERO>
+__device__ __forceinline__ uint64_t dpp(uint64_t v) {
+    const uint32_t lo = dpp<CTRL, ROW_MASK, BOUND_ZERO>(static_cast<uint32_t>(v));
+    const uint32_t hi = dpp<CTRL, ROW_MASK, BOUND_ZERO>(static_cast<uint32_t>(v >> 32));
+    return (static_cast<uint64_t>(hi) << 32) | lo;
+}
+
+// Inclusive prefix sum across the 64 lanes of a wave.
+template <typename U>
+__device__ __forceinline__ U wave_scan(U v) {
+    v += dpp<0x111, 0xf, true>(v);   // row_shr:1
+    v += dpp<0x112, 0xf, true>(v);   // row_shr:2
+    v += dpp<0x114, 0xf, true>(v);   // row_shr:4
+    v += dpp<0x118, 0xf, true>(v);   // row_shr:8   -> prefix within each row of 16 lanes
+    v += dpp<0x142, 0xa, false>(v);  // row_bcast:15 -> rows 1 and 3 add lane 15 / 47
+    v += dpp<0x143, 0xc, false>(v);  // row_bcast:31 -> rows 2 and 3 add lane 31
+    return v;
+}
+
+__device__ __forceinline__ uint32_t readlane(uint32_t v, int l) {
+    return static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(v), l));
+}
+__device__ __forceinline__ uint64_t readlane(uint64_t v, int l) {
+    return (static_cast<uint64_t>(readlane(static_cast<uint32_t>(v >> 32), l)) << 32) |
+           readlane(static_cast<uint32_t>(v), l);
+}
+
+__device__ __forceinline__ void store_state(uint64_t *p, uint64_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t load_state(const uint64_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ------------------------------------------------------------------ the strip worker
+
+constexpr int kRsrcWord3 = 0x00020000;   // raw buffer resource, 32-bit data format (gfx9 family)
+
+template <typename T, bool SQ, int PX, int RW, int NW, int MODE>
+struct Build {
+    static constexpr int TH = RW * NW;                       // strip height
+    static constexpr int BW = 64 * PX;                       // block width
+    static constexpr int NT = NW * 64;                       // threads per workgroup
+    static constexpr int PXB = PX * static_cast<int>(sizeof(T));   // bytes a lane owns in a row
+    static constexpr int NWORDS = PXB / 4;
+    static constexpr int ROWB = BW * static_cast<int>(sizeof(T));  // bytes of one tile row
+    static constexpr int TILEB = TH * ROWB;                  // bytes of one image tile
+    static constexpr int PFW = TILEB / NT / 4;               // prefetch dwords per thread
+    static_assert(NWORDS >= 1 && PFW >= 4 && PFW % 4 == 0, "tile split into whole 16-byte chunks");
+    // Squared partial sums: 8-bit squares fit 32 bits for a whole block, 16-bit ones do not.
+    using QT = typename std::conditional<sizeof(T) == 1, uint32_t, uint64_t>::type;
+
+    struct Smem {
+        uint32_t tile[TILEB / 4];                            // image tile of the current block
+        uint32_t cs[2][NW][BW];                              // per-wave column sums (2 buffers)
+        QT csq[SQ ? 2 : 1][SQ ? NW : 1][SQ ? BW : 1];
+        uint64_t v[BW];                                      // column totals above the strip
+        uint64_t vq[SQ ? BW : 1];
+        long long ticket;
+    };
+
+    static __device__ __forceinline__ uint32_t pix(const uint32_t (&raw)[NWORDS], int p) {
+        if (sizeof(T) == 1) return (raw[p >> 2] >> (8 * (p & 3))) & 0xffu;
+        return (raw[p >> 1] >> (16 * (p & 1))) & 0xffffu;
+    }
+
+    // This lane's PX pixels of tile row `row` (LDS).
+    static __device__ __forceinline__ void tile_px(const Smem &sm, int row, int lane, uint32_t (&raw)[NWORDS]) {
+        const uint32_t *src = sm.tile + (row * ROWB + lane * PXB) / 4;
+        if (NWORDS == 1) {
+            raw[0] = src[0];
+        } else if (NWORDS == 2) {
+            const u32x2 t = *reinterpret_cast<const u32x2 *>(src);
+            raw[0] = t.x;
+            raw[NWORDS > 1 ? 1 : 0] = t.y;
+        } else {
+#pragma unroll
+            for (int i = 0; i < NWORDS; i += 4) {
+                const u32x4 t = *reinterpret_cast<const u32x4 *>(src + i);
+                raw[i] = t.x;
+                raw[(i + 1) % NWORDS] = t.y;
+                raw[(i + 2) % NWORDS] = t.z;
+                raw[(i + 3) % NWORDS] = t.w;
+            }
+        }
+    }
+
+    // ---- image tile staging.  Fast path: a tile wholly inside the image whose rows allow
+    // VB-byte loads; every thread loads PFW dwords of it as VB-byte chunks (consecutive threads,
+    // consecutive chunks of a row) into registers, committed to LDS later.
+    template <int VB>
+    static __device__ __forceinline__ void fetch(const BuildDesc &d, int64_t ys, int64_t xb, uint32_t (&pf)[PFW]) {
+        constexpr int CPR = ROWB / VB;                       // chunks per tile row
+        constexpr int WPC = VB / 4;                          // dwords per chunk
+        constexpr int NCH = PFW / WPC;                       // chunks per thread
+        constexpr int RPI = NT / CPR;                        // tile rows advanced per chunk index
+        static_assert(NT % CPR == 0, "a workgroup covers whole tile rows per step");
+        const int64_t pitchb = d.ipitch * static_cast<int64_t>(sizeof(T));
+        const unsigned char *base = static_cast<const unsigned char *>(d.img) +
+                                    (ys * d.ipitch + xb) * static_cast<int64_t>(sizeof(T));
+        // The tile lies wholly inside the image here; the resource only carries the addressing.
+        const __amdgpu_buffer_rsrc_t rs =
+            __builtin_amdgcn_make_buffer_rsrc(const_cast<unsigned char *>(base), 0, 0x7fffffff, kRsrcWord3);
+        const uint32_t voff = static_cast<uint32_t>((threadIdx.x / CPR) * pitchb + (threadIdx.x % CPR) * VB);
+        const uint32_t step = static_cast<uint32_t>(RPI * pitchb);
+#pragma unroll
+        for (int i = 0; i < NCH; ++i) {
+            const int so = static_cast<int>(i * step);
+            if (VB == 16) {
+                const u32x4 t = __builtin_amdgcn_raw_buffer_load_b128(rs, voff, so, 0);
+                pf[i * WPC] = t.x; pf[i * WPC + (WPC > 1 ? 1 : 0)] = t.y;
+                pf[i * WPC + (WPC > 2 ? 2 : 0)] = t.z; pf[i * WPC + (WPC > 3 ? 3 : 0)] = t.w;
+            } else if (VB == 8) {
+                const u32x2 t = __builtin_amdgcn_raw_buffer_load_b64(rs, voff, so, 0);
+                pf[i * WPC] = t.x; pf[i * WPC + (WPC > 1 ? 1 : 0)] = t.y;
+            } else {
+                pf[i] = __builtin_amdgcn_raw_buffer_load_b32(rs, voff, so, 0);
+            }
+        }
+    }
+
+    template <int VB>
+    static __device__ __forceinline__ void commit(Smem &sm, const uint32_t (&pf)[PFW]) {
+        constexpr int CPR = ROWB / VB;
+        constexpr int WPC = VB / 4;
+        constexpr int NCH = PFW / WPC;
+#pragma unroll
+        for (int i = 0; i < NCH; ++i) {
+            const int c = i * NT + static_cast<int>(threadIdx.x);
+            const int row = c / CPR, off = (c % CPR) * VB;
+            uint32_t *dst = sm.tile + (row * ROWB + off) / 4;
+#pragma unroll
+            for (int k = 0; k < WPC; ++k) dst[k] = pf[i * WPC + k];
+        }
+    }
+
+    static __device__ __forceinline__ bool fast_tile(const BuildDesc &d, int64_t ys, int64_t xb) {
+        return d.img_vb != 0 && xb + BW <= d.W && ys + TH <= d.H;
+    }
+
+    static __device__ __forceinline__ void fetch_any(const BuildDesc &d, int64_t ys, int64_t xb, uint32_t (&pf)[PFW]) {
+        if (d.img_vb == 16) fetch<16>(d, ys, xb, pf);
+        else if (d.img_vb == 8) fetch<8>(d, ys, xb, pf);
+        else fetch<4>(d, ys, xb, pf);
+    }
+    static __device__ __forceinline__ void commit_any(const BuildDesc &d, Smem &sm, const uint32_t (&pf)[PFW]) {
+        if (d.img_vb == 16) commit<16>(sm, pf);
+        else if (d.img_vb == 8) commit<8>(sm, pf);
+        else commit<4>(sm, pf);
+    }
+
+    // Slow path (ragged or unaligned tiles): element by element, zeros outside the image.
+    static __device__ void load_tile_slow(const BuildDesc &d, Smem &sm, int64_t ys, int64_t xb) {
+        const T *img = static_cast<const T *>(d.img);
+        T *tile = reinterpret_cast<T *>(sm.tile);
+#pragma unroll 4
+        for (int e = threadIdx.x; e < TH * BW; e += NT) {
+            const int row = e / BW, col = e % BW;
+            const int64_t y = ys + row, x = xb + col;
+            tile[e] = (y < d.H && x < d.W) ? img[y * d.ipitch + x] : static_cast<T>(0);
+        }
+    }
+
+    // Column totals of all strips above `strip` for this lane's PX columns (decoupled lookback),
+    // after publishing this strip's own totals a / aq.  Run by one full wave.
+    static __device__ void lookback(const BuildDesc &d, int strip, int64_t xcol,
+                                    const uint64_t (&a)[PX], const uint64_t (&aq)[PX],
+                                    uint64_t (&v)[PX], uint64_t (&vq)[PX], uint64_t *state,
+                                    unsigned int *fault) {
+        uint64_t *mine = state + d.state_off + static_cast<int64_t>(strip) * d.Wp + xcol;
+        uint64_t *mine_q = state + d.state_q_off + static_cast<int64_t>(strip) * d.Wp + xcol;
+#pragma unroll
+        for (int p = 0; p < PX; ++p) { v[p] = 0; vq[p] = 0; }
+        if (strip == 0) {
+#pragma unroll
+            for (int p = 0; p < PX; ++p) {
+                store_state(mine + p, kStPrefix | a[p]);
+                if (SQ) store_state(mine_q + p, kStPrefix | aq[p]);
+            }
+            return;
+        }
+#pragma unroll
+        for (int p = 0; p < PX; ++p) {
+            store_state(mine + p, kStAggregate | a[p]);
+            if (SQ) store_state(mine_q + p, kStAggregate | aq[p]);
+        }
+        constexpr uint32_t kAll = SQ ? ((1u << (2 * PX)) - 1u) : ((1u << PX) - 1u);
+        uint32_t done = 0;
+        uint32_t spins = 0;
+        int j = strip - 1;
+        for (;;) {
+            const uint64_t *up = state + d.state_off + static_cast<int64_t>(j) * d.Wp + xcol;
+            const uint64_t *up_q = state + d.state_q_off + static_cast<int64_t>(j) * d.Wp + xcol;
+            uint64_t w[PX], wq[PX];
+            bool ready = true;
+#pragma unroll
+            for (int p = 0; p < PX; ++p) {
+                w[p] = 0;
+                wq[p] = 0;
+                if (!(done & (1u << p))) {
+                    w[p] = load_state(up + p);
+                    ready = ready && (w[p] >> 62) != 0;
+                }
+                if (SQ && !(done & (1u << (PX + p)))) {
+                    wq[p] = load_state(up_q + p);
+                    ready = ready && (wq[p] >> 62) != 0;
+                }
+            }
+            if (!__all(ready)) {
+                if (++spins > kSpinLimit) {
+                    atomicOr(fault, 1u);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+                continue;
+            }
+#pragma unroll
+            for (int p = 0; p < PX; ++p) {
+                if (!(done & (1u << p))) {
+                    v[p] += w[p] & kValueMask;
+                    if ((w[p] >> 62) == 2 || j == 0) done |= 1u << p;
+                }
+                if (SQ && !(done & (1u << (PX + p)))) {
+                    vq[p] += wq[p] & kValueMask;
+                    if ((wq[p] >> 62) == 2 || j == 0) done |= 1u << (PX + p);
+                }
+            }
+            if (__all(done == kAll)) break;
+            --j;
+        }
+#pragma unroll
+        for (int p = 0; p < PX; ++p) {
+            store_state(mine + p, kStPrefix | (v[p] + a[p]));
+            if (SQ) store_state(mine_q + p, kStPrefix | (vq[p] + aq[p]));
+        }
+    }
+
+    // One table's rows of the block for this wave; returns the row totals (lane r holds row r's)
+    // to add to the left carries.  Stores go through buffer resources so that the hardware range
+    // check, not a branch per row, drops what lies outside the image:
+    //   VEC (block wholly inside the image width, 16-byte aligned rows): one resource spanning
+    //     the wave's rows from the block start, records ending at the last valid row's width;
+    //     row r is addressed by the scalar offset r * pitch.
+    //   ragged: one resource per row covering exactly [block start, W) of that row.
+    template <typename ST, bool SQUARE, bool VEC>
+    static __device__ __forceinline__ uint64_t rows_pass(const Smem &sm, int wave, int lane, const uint64_t (&u)[PX],
+                                                         uint64_t lcarry, uint64_t *blk0, int rows_ok,
+                                                         uint32_t row_recs, uint32_t pitch_bytes) {
+        uint64_t acc[PX];
+#pragma unroll
+        for (int p = 0; p < PX; ++p) acc[p] = 0;
+        uint64_t tvec = 0;
+        const uint32_t voff = static_cast<uint32_t>(lane) * PX * 8;
+        const int nvalid = rows_ok > 0 ? rows_ok : 0;
+        const uint32_t blk_recs = nvalid > 0 ? (nvalid - 1) * pitch_bytes + row_recs : 0;
+        const __amdgpu_buffer_rsrc_t rs_blk =
+            __builtin_amdgcn_make_buffer_rsrc(blk0, 0, VEC ? static_cast<int>(blk_recs) : 0, kRsrcWord3);
+        const char *rowp = reinterpret_cast<const char *>(blk0);
+        uint32_t roff = 0;
+#pragma unroll 1
+        for (int r = 0; r < RW; ++r) {
+            uint32_t raw[NWORDS];
+            tile_px(sm, wave * RW + r, lane, raw);
+            ST pre[PX];
+            ST s = 0;
+#pragma unroll
+            for (int p = 0; p < PX; ++p) {
+                const ST v = pix(raw, p);
+                s += SQUARE ? v * v : v;
+                pre[p] = s;
+            }
+            const ST incl = wave_scan(s);
+            const uint64_t base = readlane(lcarry, r) + (incl - s);
+            const ST row_total = readlane(incl, 63);
+            if (lane == r) tvec = row_total;
+            uint64_t out[PX];
+#pragma unroll
+            for (int p = 0; p < PX; ++p) {
+                acc[p] += base + pre[p];
+                out[p] = u[p] + acc[p];
+            }
+            if (VEC) {
+#pragma unroll
+                for (int p = 0; p < PX; p += 2)
+                    __builtin_amdgcn_raw_buffer_store_b128(
+                        u32x4{static_cast<uint32_t>(out[p]), static_cast<uint32_t>(out[p] >> 32),
+                              static_cast<uint32_t>(out[p + 1]), static_cast<uint32_t>(out[p + 1] >> 32)},
+                        rs_blk, voff + 8 * p, static_cast<int>(roff), 0);
+            } else {
+                const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                    const_cast<char *>(rowp), 0, r < rows_ok ? static_cast<int>(row_recs) : 0, kRsrcWord3);
+#pragma unroll
+                for (int p = 0; p < PX; ++p)
+                    __builtin_amdgcn_raw_buffer_store_b64(
+                        u32x2{static_cast<uint32_t>(out[p]), static_cast<uint32_t>(out[p] >> 32)}, rs,
+                        voff + 8 * p, 0, 0);
+                rowp += pitch_bytes;
+            }
+            roff += pitch_bytes;
+        }
+        return tvec;
+    }
+
+    static __device__ void strip(const BuildDesc &d, int strip_idx, uint64_t *state, unsigned int *fault, Smem &sm) {
+        const int lane = threadIdx.x & 63;
+        const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+        const int64_t ys = static_cast<int64_t>(strip_idx) * TH;       // first row of the strip
+        const int64_t yw = ys + wave * RW;                                // first row of this wave
+        const int rows_ok = static_cast<int>(d.H - yw < RW ? d.H - yw : RW);   // may be <= 0
+        uint64_t *S_w = d.S + yw * d.spitch;
+        uint64_t *Q_w = SQ ? d.Q + yw * d.spitch : nullptr;
+        const uint32_t pitch_bytes = static_cast<uint32_t>(d.spitch * 8);
+
+        uint64_t lrow = 0, lrow_q = 0;       // lane r: sum of row yw+r left of the block
+        uint64_t ucarry = 0, ucarry_q = 0;   // table value at (yw-1, block start - 1)
+
+        // Stage block 0.
+        uint32_t pf[PFW];
+        if (fast_tile(d, ys, 0)) {
+            fetch_any(d, ys, 0, pf);
+            commit_any(d, sm, pf);
+        } else {
+            load_tile_slow(d, sm, ys, 0);
+        }
+        __syncthreads();
+
+        for (int b = 0; b < d.nblocks; ++b) {
+            const int buf = b & 1;
+            const int64_t xb = static_cast<int64_t>(b) * BW;
+            const int64_t xcol = xb + lane * PX;
+
+            // Column sums of this wave's rows.
+            {
+                uint32_t cs[PX];
+                QT csq[PX];
+#pragma unroll
+                for (int p = 0; p < PX; ++p) { cs[p] = 0; csq[p] = 0; }
+#pragma unroll 2
+                for (int r = 0; r < RW; ++r) {
+                    uint32_t raw[NWORDS];
+                    tile_px(sm, wave * RW + r, lane, raw);
+#pragma unroll
+                    for (int p = 0; p < PX; ++p) {
+                        const uint32_t v = pix(raw, p);
+                        cs[p] += v;
+                        if (SQ) csq[p] += static_cast<QT>(v) * v;
+                    }
+                }
+#pragma unroll
+                for (int p = 0; p < PX; ++p) {
+                    sm.cs[buf][wave][lane * PX + p] = cs[p];
+                    if (SQ) sm.csq[buf][wave][lane * PX + p] = csq[p];
+                }
+            }
+            // Prefetch the next block's tile while this block's lookback and rows run.
+            const bool next_fast = b + 1 < d.nblocks && fast_tile(d, ys, xb + BW);
+            if (next_fast) fetch_any(d, ys, xb + BW, pf);
+            __syncthreads();
+
+            if (wave == 0) {
+                uint64_t a[PX], aq[PX], v[PX], vq[PX];
+#pragma unroll
+                for (int p = 0; p < PX; ++p) {
+                    a[p] = 0;
+                    aq[p] = 0;
+#pragma unroll
+                    for (int w = 0; w < NW; ++w) {
+                        a[p] += sm.cs[buf][w][lane * PX + p];
+                        if (SQ) aq[p] += sm.csq[buf][w][lane * PX + p];
+                    }
+                }
+                if (MODE == MODE_LOOKBACK) {
+                    lookback(d, strip_idx, xcol, a, aq, v, vq, state, fault);
+                } else {
+                    const uint64_t *tot = state + d.state_off + static_cast<int64_t>(strip_idx) * d.Wp + xcol;
+                    const uint64_t *tot_q = state + d.state_q_off + static_cast<int64_t>(strip_idx) * d.Wp + xcol;
+#pragma unroll
+                    for (int p = 0; p < PX; ++p) {
+                        v[p] = tot[p];
+                        vq[p] = SQ ? tot_q[p] : 0;
+                    }
+                }
+#pragma unroll
+                for (int p = 0; p < PX; ++p) {
+                    sm.v[lane * PX + p] = v[p];
+                    if (SQ) sm.vq[lane * PX + p] = vq[p];
+                }
+            }
+            __syncthreads();
+
+            // Table row just above this wave's rows: prefix along x of the column totals above.
+            uint64_t u[PX], uq[PX];
+            {
+                uint64_t c[PX], cq[PX];
+#pragma unroll
+                for (int p = 0; p < PX; ++p) {
+                    c[p] = sm.v[lane * PX + p];
+                    cq[p] = SQ ? sm.vq[lane * PX + p] : 0;
+                }
+                for (int w = 0; w < wave; ++w)
+#pragma unroll
+                    for (int p = 0; p < PX; ++p) {
+                        c[p] += sm.cs[buf][w][lane * PX + p];
+                        if (SQ) cq[p] += sm.csq[buf][w][lane * PX + p];
+                    }
+#pragma unroll
+                for (int p = 1; p < PX; ++p) {
+                    c[p] += c[p - 1];
+                    if (SQ) cq[p] += cq[p - 1];
+                }
+                const uint64_t incl = wave_scan(c[PX - 1]);
+                const uint64_t base = ucarry + (incl - c[PX - 1]);
+#pragma unroll
+                for (int p = 0; p < PX; ++p) u[p] = base + c[p];
+                ucarry += readlane(incl, 63);
+                if (SQ) {
+                    const uint64_t incl_q = wave_scan(cq[PX - 1]);
+                    const uint64_t base_q = ucarry_q + (incl_q - cq[PX - 1]);
+#pragma unroll
+                    for (int p = 0; p < PX; ++p) uq[p] = base_q + cq[p];
+                    ucarry_q += readlane(incl_q, 63);
+                }
+            }
+
+            // Rows: row prefix (lane-serial, then DPP across lanes) plus the row's left carry,
+            // accumulated down the wave's rows and offset by the table row above.  The squared
+            // table is a second pass over the same tile to keep live ranges short.
+            const bool vec = d.sat_vec && xb + BW <= d.W;
+            const uint32_t row_recs = static_cast<uint32_t>((d.W - xb) * 8);   // bytes from block start to W
+            if (vec) {
+                lrow += rows_pass<uint32_t, false, true>(sm, wave, lane, u, lrow, S_w + xb, rows_ok, row_recs, pitch_bytes);
+                if (SQ) lrow_q += rows_pass<QT, true, true>(sm, wave, lane, uq, lrow_q, Q_w + xb, rows_ok, row_recs, pitch_bytes);
+            } else {
+                lrow += rows_pass<uint32_t, false, false>(sm, wave, lane, u, lrow, S_w + xb, rows_ok, row_recs, pitch_bytes);
+                if (SQ) lrow_q += rows_pass<QT, true, false>(sm, wave, lane, uq, lrow_q, Q_w + xb, rows_ok, row_recs, pitch_bytes);
+            }
+
+            // Replace the tile with the next block's.
+            if (b + 1 < d.nblocks) {
+                __syncthreads();
+                if (next_fast) commit_any(d, sm, pf);
+                else load_tile_slow(d, sm, ys, xb + BW);
+                __syncthreads();
+            }
+        }
+    }
+};
+
+// Persistent strip kernel: each workgroup takes strips (of one image, or of a batch) from the
+// ticket counter until none are left.
+template <typename T, bool SQ, int PX, int RW, int NW, int MODE>
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(16 / NW > 4 ? 4 : 16 / NW)))
+void build_kernel(const BuildDesc *__restrict__ many, int n, long long total_items, uint64_t *state,
+                  BuildCtrl *ctrl) {
+    using B = Build<T, SQ, PX, RW, NW, MODE>;
+    __shared__ typename B::Smem sm;
+    for (;;) {
+        if (threadIdx.x == 0) sm.ticket = static_cast<long long>(atomicAdd(&ctrl->ticket, 1ull));
+        __syncthreads();
+        const long long t = static_cast<long long>(__builtin_amdgcn_readfirstlane(static_cast<int>(sm.ticket))) |
+                            (static_cast<long long>(__builtin_amdgcn_readfirstlane(static_cast<int>(sm.ticket >> 32))) << 32);
+        __syncthreads();
+        if (t >= total_items) return;
+        int lo = 0, hi = n - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (many[mid].first_item <= t) lo = mid;
+            else hi = mid - 1;
+        }
+        const BuildDesc &d = many[lo];
+        B::strip(d, __builtin_amdgcn_readfirstlane(static_cast<int>(t - d.first_item)), state, &ctrl->fault, sm);
+    }
+}
+
+// Zero the lookback words and reset the control header.
+// When `slot` is non-null the single-image descriptor `one` is written there as well.
+__global__ void clear_kernel(uint64_t *state, long long nwords, BuildCtrl *ctrl, BuildDesc one, BuildDesc *slot) {
+    const long long i0 = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i0 == 0) {
+        ctrl->ticket = 0;
+        ctrl->fault = 0;
+        if (slot) *slot = one;
+    }
+    const long long step = static_cast<long long>(gridDim.x) * blockDim.x;
+    for (long long i = i0; 2 * i < nwords; i += step)
+        *reinterpret_cast<u64x2 *>(state + 2 * i) = u64x2{0, 0};
+}
+
+// Reduce-then-scan ablation, phase 1: column totals of every strip (TH rows) of one image.
+template <typename T, bool SQ, int PX, int TH>
+__global__ __launch_bounds__(256) void colsum_kernel(BuildDesc d, uint64_t *state) {
+    const int64_t xcol = (static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x) * PX;
+    if (xcol >= d.Wp) return;
+    const int64_t strip = blockIdx.y;
+    uint64_t cs[PX], csq[PX];
+#pragma unroll
+    for (int p = 0; p < PX; ++p) { cs[p] = 0; csq[p] = 0; }
+    const T *img = static_cast<const T *>(d.img);
+    for (int r = 0; r < TH; ++r) {
+        const int64_t y = strip * TH + r;
+        if (y >= d.H) break;
+#pragma unroll
+        for (int p = 0; p < PX; ++p) {
+            if (xcol + p < d.W) {
+                const uint64_t v = img[y * d.ipitch + xcol + p];
+                cs[p] += v;
+                csq[p] += v * v;
+            }
+        }
+    }
+#pragma unroll
+    for (int p = 0; p < PX; ++p) {
+        state[d.state_off + strip * d.Wp + xcol + p] = cs[p];
+        if (SQ) state[d.state_q_off + strip * d.Wp + xcol + p] = csq[p];
+    }
+}
+
+// Reduce-then-scan ablation, phase 2: exclusive scan of the strip totals down each column.
+__global__ __launch_bounds__(256) void colscan_kernel(uint64_t *state, long long off, long long Wp,
+                                                      int nstrips) {
+    const long long x = static_cast<long long>(blockIdx.x) * 256 + threadIdx.x;
+    if (x >= Wp) return;
+    uint64_t run = 0;
+    for (int i = 0; i < nstrips; ++i) {
+        uint64_t *p = state + off + static_cast<long long>(i) * Wp + x;
+        const uint64_t t = *p;
+        *p = run;
+        run += t;
+    }
+}
+
+// ------------------------------------------------------------------ variants and launch
+
+const BuildVariant kVariants[] = {
+    {"lookback_px4_rw16_nw4", 4, 16, 4, MODE_LOOKBACK},
+    {"lookback_px4_rw8_nw4", 4, 8, 4, MODE_LOOKBACK},
+    {"lookback_px4_rw4_nw4", 4, 4, 4, MODE_LOOKBACK},
+    {"lookback_px8_rw16_nw4", 8, 16, 4, MODE_LOOKBACK},
+    {"lookback_px4_rw8_nw8", 4, 8, 8, MODE_LOOKBACK},
+    {"reduce_scan_px4_rw16_nw4", 4, 16, 4, MODE_REDUCE_SCAN},
+};
+constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
+
+int resident_capacity(const void *kernel, int threads) {
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 1024;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 1024;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    return cus * per_cu;
+}
+
+template <typename T, bool SQ, int PX, int RW, int NW, int MODE>
+hipError_t launch_typed(const BuildDesc *descs, int n, const BuildDesc *dev_descs, int64_t total_items,
+                        void *workspace, int64_t state_words, hipStream_t stream) {
+    BuildCtrl *ctrl = static_cast<BuildCtrl *>(workspace);
+    uint64_t *state = reinterpret_cast<uint64_t *>(static_cast<char *>(workspace) + sizeof(BuildCtrl));
+    BuildDesc *slot = n == 1 ? &ctrl->one : nullptr;
+    const BuildDesc *table = n == 1 ? slot : dev_descs;
+    constexpr int TH = RW * NW;
+    if (MODE == MODE_LOOKBACK) {
+        const long long pairs = (state_words + 1) / 2;
+        const long long blocks = pairs > 0 ? (pairs + 255) / 256 : 1;
+        const unsigned grid = static_cast<unsigned>(blocks < 8192 ? blocks : 8192);
+        hipLaunchKernelGGL(clear_kernel, dim3(grid), dim3(256), 0, stream, state,
+                           static_cast<long long>(state_words), ctrl, descs[0], slot);
+    } else {
+        hipLaunchKernelGGL(clear_kernel, dim3(1), dim3(256), 0, stream, state, 0ll, ctrl, descs[0], slot);
+        for (int i = 0; i < n; ++i) {
+            const BuildDesc &d = descs[i];
+            const int64_t xb = (d.Wp / PX + 255) / 256;
+            hipLaunchKernelGGL((colsum_kernel<T, SQ, PX, TH>), dim3(static_cast<unsigned>(xb), d.nstrips),
+                               dim3(256), 0, stream, d, state);
+            const unsigned cb = static_cast<unsigned>((d.Wp + 255) / 256);
+            hipLaunchKernelGGL(colscan_kernel, dim3(cb), dim3(256), 0, stream, state,
+                               static_cast<long long>(d.state_off), static_cast<long long>(d.Wp), d.nstrips);
+            if (SQ)
+                hipLaunchKernelGGL(colscan_kernel, dim3(cb), dim3(256), 0, stream, state,
+                                   static_cast<long long>(d.state_q_off), static_cast<long long>(d.Wp),
+                                   d.nstrips);
+        }
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const void *kfn = reinterpret_cast<const void *>(&build_kernel<T, SQ, PX, RW, NW, MODE>);
+    static int cap = 0;   // per instantiation; the library drives one device model
+    if (cap == 0) cap = resident_capacity(kfn, NW * 64);
+    const int64_t grid = total_items < cap ? total_items : cap;
+    hipLaunchKernelGGL((build_kernel<T, SQ, PX, RW, NW, MODE>), dim3(static_cast<unsigned>(grid)),
+                       dim3(NW * 64), 0, stream, table, n, static_cast<long long>(total_items), state, ctrl);
+    return hipGetLastError();
+}
+
+template <typename T, bool SQ>
+hipError_t launch_variant(int v, const BuildDesc *descs, int n, const BuildDesc *dev_descs, int64_t total,
+                          void *ws, int64_t words, hipStream_t s) {
+    switch (v) {
+        case 0: return launch_typed<T, SQ, 4, 16, 4, MODE_LOOKBACK>(descs, n, dev_descs, total, ws, words, s);
+        case 1: return launch_typed<T, SQ, 4, 8, 4, MODE_LOOKBACK>(descs, n, dev_descs, total, ws, words, s);
+        case 2: return launch_typed<T, SQ, 4, 4, 4, MODE_LOOKBACK>(descs, n, dev_descs, total, ws, words, s);
+        case 3: return launch_typed<T, SQ, 8, 16, 4, MODE_LOOKBACK>(descs, n, dev_descs, total, ws, words, s);
+        case 4: return launch_typed<T, SQ, 4, 8, 8, MODE_LOOKBACK>(descs, n, dev_descs, total, ws, words, s);
+        case 5: return launch_typed<T, SQ, 4, 16, 4, MODE_REDUCE_SCAN>(descs, n, dev_descs, total, ws, words, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+int build_variant_count() { return kNumVariants; }
+const BuildVariant &build_variant(int v) { return kVariants[v]; }
+
+hipError_t launch_build(int variant, int bpp, bool sq, const BuildDesc *descs, int n,
+                        const BuildDesc *dev_descs, int64_t total_items, void *workspace,
+                        int64_t state_words, hipStream_t stream) {
+    if (bpp == 1)
+        return sq ? launch_variant<uint8_t, true>(variant, descs, n, dev_descs, total_items, workspace, state_words, stream)
+                  : launch_variant<uint8_t, false>(variant, descs, n, dev_descs, total_items, workspace, state_words, stream);
+    return sq ? launch_variant<uint16_t, true>(variant, descs, n, dev_descs, total_items, workspace, state_words, stream)
+              : launch_variant<uint16_t, false>(variant, descs, n, dev_descs, total_items, workspace, state_words, stream);
+}
+
+}  // namespace satk

@@ -1,0 +1,86 @@
+// sat_internal.h -- descriptors and launchers shared by the C-ABI front end and the kernels.
+// Internal to libsat.so; the public interface is include/sat.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace satk {
+
+// ---------------------------------------------------------------- table build
+
+// One image to build.  All pointers are device pointers; pitches are in elements.
+struct BuildDesc {
+    const void *img;
+    uint64_t *S;          // table of pixels
+    uint64_t *Q;          // table of squared pixels, or nullptr
+    int64_t H, W, ipitch, spitch;
+    int64_t Wp;           // state row length: nblocks * block width
+    int64_t state_off;    // first lookback word of this image in the state array (S part)
+    int64_t state_q_off;  // first lookback word of the squared table's state (Q part)
+    int64_t first_item;   // first work item (strip) of this image in the batch
+    int32_t nstrips, nblocks;
+    int32_t img_vb;       // widest load (16, 8 or 4 bytes) that every image row start allows; 0: none
+    int32_t sat_vec;      // 1: table rows allow 16-byte vector stores
+};
+
+// Workspace layout: 256-byte control header, then the lookback state.
+struct BuildCtrl {
+    unsigned long long ticket;   // next work item
+    unsigned int fault;          // nonzero: a lookback wait hit its spin bound
+    unsigned int pad0;
+    BuildDesc one;               // descriptor of a single-image build (written by the clear kernel)
+    unsigned char pad[256 - 16 - sizeof(BuildDesc)];
+};
+static_assert(sizeof(BuildCtrl) == 256, "control header is 256 bytes");
+
+enum BuildMode { MODE_LOOKBACK = 0, MODE_REDUCE_SCAN = 1 };
+
+struct BuildVariant {
+    const char *name;
+    int px;       // pixels per lane along a row
+    int rw;       // rows per wave
+    int nw;       // waves per workgroup
+    int mode;     // BuildMode
+    int th() const { return rw * nw; }       // strip height
+    int bw() const { return 64 * px; }        // block width
+};
+
+int build_variant_count();
+const BuildVariant &build_variant(int v);
+
+// Enqueue the whole build (state clear + kernels) of n images sharing pixel type and squared
+// flag.  `dev_descs` is a device copy of `descs` when n > 1 (nullptr when n == 1: the single
+// descriptor is passed by value).  Returns the HIP error of the first failing launch.
+hipError_t launch_build(int variant, int bpp, bool sq, const BuildDesc *descs, int n,
+                        const BuildDesc *dev_descs, int64_t total_items, void *workspace,
+                        int64_t state_words, hipStream_t stream);
+
+// ---------------------------------------------------------------- window gathers
+
+struct GatherDesc {
+    const uint64_t *S;
+    const uint64_t *Q;       // mean/std only
+    int64_t spitch;
+    int64_t oh, ow;
+    int64_t win_h, win_w, stride;
+    void *out;               // window sums (u32 or u64), may be nullptr for mean/std
+    double *mean;
+    double *stdv;
+    int64_t opitch;
+    int64_t chunks;          // column chunks per output row
+    int64_t first_item;      // batched: first work item of this image
+};
+
+int gather_variant_count();
+const char *gather_variant_name(int v);
+
+hipError_t launch_window_sum(int variant, const GatherDesc &d, bool out64, hipStream_t stream);
+hipError_t launch_window_sum_multi(const GatherDesc *d, int n, bool out64, hipStream_t stream);
+hipError_t launch_mean_std(const GatherDesc *descs, int n, const GatherDesc *dev_descs,
+                           int64_t total_items, hipStream_t stream);
+
+int64_t gather_chunk_outputs(int variant);   // outputs per work item along a row
+
+}  // namespace satk

@@ -1,0 +1,159 @@
+"""The C ABI without a GPU: the library loads, exports what include/sat.h declares, and rejects
+every invalid argument with its status code before making any HIP call."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2410_16291_amd import _lib
+from paper_2410_16291_amd._lib import (SAT_ERR_ARG, SAT_ERR_OVERFLOW, SAT_ERR_WINDOW, SAT_ERR_WORKSPACE, SAT_F64,
+                                       SAT_OK, SAT_U8, SAT_U16, SAT_U32, SAT_U64, BatchItem)
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sat.h")
+
+# Fake device addresses: validation looks only at their values (NULL-ness, alignment, overlap).
+IMG, SAT, SQ, OUT, OUT2, OUT3, WS = (0x10000000000 * k for k in range(1, 8))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return _lib.load()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = "\n".join(l for l in text.splitlines() if not l.strip().startswith("#"))
+    return sorted(set(re.findall(r"\b([A-Za-z_]\w*)\s*\([^;{}]*\)\s*;", text)))
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared_functions()
+    assert "sat_build" in names and "window_sum" in names and "window_mean_std" in names
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_window_out_shape(lib):
+    oh, ow = ctypes.c_int64(), ctypes.c_int64()
+    for (H, W, h, w, s, exp) in [(512, 512, 32, 32, 1, (481, 481)), (8192, 8192, 64, 64, 1, (8129, 8129)),
+                                 (70000, 85000, 100, 100, 1, (69901, 84901)),
+                                 (70000, 85000, 250, 250, 1, (69751, 84751)),
+                                 (70000, 85000, 500, 500, 1, (69501, 84501)), (10, 7, 3, 2, 4, (2, 2)),
+                                 (1, 1, 1, 1, 1, (1, 1))]:
+        assert lib.window_out_shape(H, W, h, w, s, ctypes.byref(oh), ctypes.byref(ow)) == SAT_OK
+        assert (oh.value, ow.value) == exp
+    assert lib.window_out_shape(10, 10, 11, 1, 1, ctypes.byref(oh), ctypes.byref(ow)) == SAT_ERR_WINDOW
+    assert lib.window_out_shape(10, 10, 1, 1, 0, ctypes.byref(oh), ctypes.byref(ow)) == SAT_ERR_ARG
+    assert lib.window_out_shape(10, 10, 1, 1, 1, None, ctypes.byref(ow)) == SAT_ERR_ARG
+    assert b"window" in lib.sat_last_error()
+
+
+def test_workspace_bytes(lib):
+    a = lib.sat_build_workspace_bytes(512, 512, SAT_U8, 0)
+    b = lib.sat_build_workspace_bytes(512, 512, SAT_U8, 1)
+    assert 256 < a < b
+    assert lib.sat_build_workspace_bytes(0, 5, SAT_U8, 0) == 0
+    assert lib.sat_build_workspace_bytes(5, 5, SAT_U32, 0) == 0
+    full = lib.sat_build_workspace_bytes(70000, 85000, SAT_U8, 0)
+    assert full < 70000 * 85000          # lookback state stays below one byte per pixel
+
+
+def build(lib, image=IMG, ptype=SAT_U8, H=64, W=80, ipitch=80, sat=SAT, sat_sq=None, spitch=80, ws=WS, wsb=None):
+    if wsb is None:
+        wsb = lib.sat_build_workspace_bytes(H, W, ptype if ptype in (SAT_U8, SAT_U16) else SAT_U8, int(bool(sat_sq)))
+    return lib.sat_build(image, ptype, H, W, ipitch, sat, sat_sq, spitch, ws, wsb, None)
+
+
+def test_sat_build_validation(lib):
+    assert build(lib, image=None) == SAT_ERR_ARG
+    assert build(lib, sat=None) == SAT_ERR_ARG
+    assert build(lib, ptype=SAT_U32) == SAT_ERR_ARG
+    assert build(lib, H=0) == SAT_ERR_ARG
+    assert build(lib, W=0, ipitch=0, spitch=0) == SAT_ERR_ARG
+    assert build(lib, ipitch=79) == SAT_ERR_ARG
+    assert build(lib, spitch=79) == SAT_ERR_ARG
+    assert build(lib, sat_sq=SAT) == SAT_ERR_ARG                    # identical tables
+    assert build(lib, sat=IMG + 16) == SAT_ERR_ARG                  # table overlaps image
+    assert build(lib, sat_sq=SAT + 8 * 100) == SAT_ERR_ARG          # squared table overlaps table
+    assert build(lib, ws=None) == SAT_ERR_WORKSPACE
+    assert build(lib, wsb=100) == SAT_ERR_WORKSPACE
+    assert build(lib, ws=SAT + 64) == SAT_ERR_ARG                   # workspace overlaps table
+    assert build(lib, ws=WS + 4) == SAT_ERR_ARG                     # misaligned workspace
+    # 16-bit squares: column totals need H * 65535^2 < 2^62
+    big_h = (1 << 62) // (65535 * 65535) + 1
+    assert build(lib, ptype=SAT_U16, H=big_h, W=1, ipitch=1, spitch=1, sat_sq=SQ, wsb=1 << 40) in (
+        SAT_ERR_OVERFLOW, SAT_ERR_ARG)
+
+
+def test_window_sum_validation(lib):
+    def call(sat=SAT, ptype=SAT_U8, H=100, W=120, sp=120, h=10, w=10, s=1, out=OUT, ot=SAT_U32, op=111):
+        return lib.window_sum(sat, ptype, H, W, sp, h, w, s, out, ot, op, None)
+    assert call(sat=None) == SAT_ERR_ARG
+    assert call(out=None) == SAT_ERR_ARG
+    assert call(h=101) == SAT_ERR_WINDOW
+    assert call(w=121) == SAT_ERR_WINDOW
+    assert call(h=0) == SAT_ERR_ARG
+    assert call(s=0) == SAT_ERR_ARG
+    assert call(ot=SAT_F64) == SAT_ERR_ARG
+    assert call(ptype=SAT_U64) == SAT_ERR_ARG
+    assert call(op=110) == SAT_ERR_ARG                               # ow = 111
+    assert call(out=SAT + 8) == SAT_ERR_ARG                          # out overlaps table
+    # uint32 overflow: 7000^2 * 255 > 2^32 - 1, 4104^2 * 255 <= 2^32 - 1 < 4105^2 * 255
+    assert call(H=8000, W=8000, sp=8000, h=7000, w=7000, op=1001) == SAT_ERR_OVERFLOW
+    assert call(H=8000, W=8000, sp=8000, h=4105, w=4105, op=3896, ot=SAT_U32) == SAT_ERR_OVERFLOW
+    assert call(ptype=SAT_U16, H=400, W=400, sp=400, h=300, w=300, op=101) == SAT_ERR_OVERFLOW  # 9e4 * 65535 > 2^32
+    assert b"uint32" in lib.sat_last_error()
+
+
+def test_window_mean_std_validation(lib):
+    def call(sat=SAT, sq=SQ, s1=OUT, mean=OUT2, std=OUT3, h=4, w=4, op=97):
+        return lib.window_mean_std(sat, sq, 100, 100, 100, h, w, 1, s1, mean, std, op, None)
+    assert call(sq=None) == SAT_ERR_ARG
+    assert call(mean=None) == SAT_ERR_ARG
+    assert call(std=None) == SAT_ERR_ARG
+    assert call(h=101) == SAT_ERR_WINDOW
+    assert call(op=96) == SAT_ERR_ARG
+    assert call(mean=OUT) == SAT_ERR_ARG                             # outputs overlap
+    assert call(std=SQ + 8) == SAT_ERR_ARG                           # output overlaps a table
+
+
+def test_multi_and_batch_validation(lib):
+    hs = (ctypes.c_int64 * 2)(10, 20)
+    ws = (ctypes.c_int64 * 2)(10, 200)
+    outs = (ctypes.c_void_p * 2)(OUT, OUT2)
+    pitches = (ctypes.c_int64 * 2)(200, 200)
+    assert lib.window_sum_multi(SAT, SAT_U8, 100, 120, 120, 2, hs, ws, 1, outs, SAT_U32, pitches, None) == SAT_ERR_WINDOW
+    assert lib.window_sum_multi(SAT, SAT_U8, 100, 120, 120, 0, hs, ws, 1, outs, SAT_U32, pitches, None) == SAT_ERR_ARG
+    assert lib.window_sum_multi(SAT, SAT_U8, 100, 120, 120, 9, hs, ws, 1, outs, SAT_U32, pitches, None) == SAT_ERR_ARG
+    items = (BatchItem * 2)()
+    for i in range(2):
+        items[i].image, items[i].H, items[i].W, items[i].image_pitch = IMG + i * 0x1000000, 50, 60, 60
+        items[i].sat, items[i].sat_pitch = SAT + i * 0x1000000, 60
+    need = lib.sat_batch_workspace_bytes(items, 2, SAT_U8, 0)
+    assert need > 256
+    assert lib.sat_build_batched(items, 0, SAT_U8, WS, need, None) == SAT_ERR_ARG
+    assert lib.sat_build_batched(items, 2, SAT_U8, WS, need - 1, None) == SAT_ERR_WORKSPACE
+    items[1].sat = items[0].sat + 8                                  # tables of two items overlap
+    assert lib.sat_build_batched(items, 2, SAT_U8, WS, need, None) == SAT_ERR_ARG
+    items[1].sat = SAT + 0x1000000
+    items[1].sat_sq = SQ                                             # mixed squared / not squared
+    assert lib.sat_build_batched(items, 2, SAT_U8, WS, need, None) == SAT_ERR_ARG
+    items[1].sat_sq = None
+    items[1].W = 0
+    assert lib.sat_build_batched(items, 2, SAT_U8, WS, need, None) == SAT_ERR_ARG
+    assert b"item 1" in lib.sat_last_error()
+
+
+def test_variants(lib):
+    nb, ng = lib.sat_variant_count(0), lib.sat_variant_count(1)
+    assert nb >= 5 and ng >= 3
+    names = [lib.sat_variant_name(0, i).decode() for i in range(nb)]
+    assert any("lookback" in n for n in names) and any("reduce_scan" in n for n in names)
+    assert lib.sat_force_variant(0, nb) == SAT_ERR_ARG
+    assert lib.sat_force_variant(2, 0) == SAT_ERR_ARG
+    assert lib.sat_force_variant(0, 1) == SAT_OK
+    assert lib.sat_force_variant(0, -1) == SAT_OK

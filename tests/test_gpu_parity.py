@@ -1,0 +1,234 @@
+"""HIP path vs the oracle, element by element, through the C ABI (needs an MI355X).
+
+Integer results (tables, window sums, counts) must be bit-exact; the FP64 mean must be
+bit-exact (one correctly rounded division of exact operands on both sides); the FP64 std must be
+within 1e-12 relative (exactly 0 where the oracle gives 0).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2410_16291_amd import api, synth
+from gpu_util import padded_image, to_device, to_host
+
+pytestmark = pytest.mark.gpu
+
+STD_RTOL = 1e-12
+
+
+def check_std(got, ref):
+    zero = ref == 0
+    assert np.all(got[zero] == 0.0)
+    rel = np.abs(got[~zero] - ref[~zero]) / ref[~zero]
+    assert rel.size == 0 or rel.max() <= STD_RTOL, rel.max()
+
+
+def gpu_stats(img_np, h, w, s, squares_only=False):
+    img = to_device(img_np)
+    S, Q = api.sat_build(img, squares=True)
+    s1, mean, std = api.window_mean_std(S, Q, h, w, s)
+    torch.cuda.synchronize()
+    return S, Q, s1, mean, std
+
+
+# ------------------------------------------------------------------ the paper-shaped small cases
+
+def test_cfg_small_poisson_512():
+    print("case: 512x512 u8 poisson, 32x32 stride 1", flush=True)
+    img_np = synth.poisson_counts(512, 512, 0.05, seed=0)
+    img = to_device(img_np)
+    S = api.sat_build(img)
+    out = api.window_sum(S, 32, 32, 1, pixel_type="u8")
+    torch.cuda.synchronize()
+    assert out.dtype == torch.uint32 and tuple(out.shape) == (481, 481)
+    ref_S = oracle.sat(img_np)
+    assert np.array_equal(to_host(S), ref_S)
+    ref = oracle.window_sum_sat(ref_S, 32, 32, 1)
+    assert np.array_equal(to_host(out).astype(np.uint64), ref)
+    assert np.array_equal(ref, oracle.window_sum_direct(img_np, 32, 32, 1))
+
+
+def test_cfg_lognormal_8192_mean_std():
+    print("case: 8192x8192 u16 lognormal, S and Q, 64x64 stride 1", flush=True)
+    img_np = synth.lognormal_u16(8192, 8192, seed=1)
+    S, Q, s1, mean, std = gpu_stats(img_np, 64, 64, 1)
+    ref_S, ref_Q = oracle.sat(img_np, squares=True)
+    assert np.array_equal(to_host(S), ref_S)
+    assert np.array_equal(to_host(Q), ref_Q)
+    del S, Q
+    sums = oracle.window_sum_sat(ref_S, 64, 64, 1)
+    sqs = oracle.window_sum_sat(ref_Q, 64, 64, 1)
+    del ref_S, ref_Q
+    ref_mean, ref_std = oracle.mean_std(sums, sqs, 64 * 64)
+    assert np.array_equal(to_host(s1), sums)
+    assert np.array_equal(to_host(mean), ref_mean)
+    check_std(to_host(std), ref_std)
+
+
+# ------------------------------------------------------------------ shapes and edges
+
+SHAPES = [(1, 1), (1, 300), (300, 1), (17, 257), (64, 256), (65, 255), (129, 513), (200, 1000), (333, 77)]
+
+
+@pytest.mark.parametrize("dtype", [np.uint8, np.uint16])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_build_shapes_bit_exact(shape, dtype):
+    print("case: build", shape, np.dtype(dtype).name, flush=True)
+    rng = np.random.default_rng(hash(shape) % 1000)
+    hi = 256 if dtype == np.uint8 else 65536
+    img_np = rng.integers(0, hi, shape).astype(dtype)
+    S, Q = api.sat_build(to_device(img_np), squares=True)
+    ref_S, ref_Q = oracle.sat(img_np, squares=True)
+    assert np.array_equal(to_host(S), ref_S)
+    assert np.array_equal(to_host(Q), ref_Q)
+
+
+@pytest.mark.parametrize("dtype", [np.uint8, np.uint16])
+def test_windows_and_strides(dtype):
+    rng = np.random.default_rng(7)
+    hi = 256 if dtype == np.uint8 else 65536
+    img_np = rng.integers(0, hi, (301, 517)).astype(dtype)
+    S, Q = api.sat_build(to_device(img_np), squares=True)
+    ref_S, ref_Q = oracle.sat(img_np, squares=True)
+    ptype = "u8" if dtype == np.uint8 else "u16"
+    cases = [(1, 1, 1), (301, 517, 1), (301, 1, 1), (1, 517, 2), (32, 32, 1), (64, 64, 4), (7, 300, 3),
+             (300, 7, 5), (100, 250, 8), (13, 17, 16)]
+    for (h, w, s) in cases:
+        print("case: window", h, w, s, ptype, flush=True)
+        out = api.window_sum(S, h, w, s, pixel_type=ptype, out_dtype=torch.uint64)
+        ref = oracle.window_sum_sat(ref_S, h, w, s)
+        assert np.array_equal(to_host(out), ref), (h, w, s)
+        if h * w * (hi - 1) <= 0xFFFFFFFF:
+            out32 = api.window_sum(S, h, w, s, pixel_type=ptype, out_dtype=torch.uint32)
+            assert np.array_equal(to_host(out32).astype(np.uint64), ref), (h, w, s)
+        s1, mean, std = api.window_mean_std(S, Q, h, w, s)
+        sqs = oracle.window_sum_sat(ref_Q, h, w, s)
+        ref_mean, ref_std = oracle.mean_std(ref, sqs, h * w)
+        assert np.array_equal(to_host(s1), ref)
+        assert np.array_equal(to_host(mean), ref_mean)
+        check_std(to_host(std), ref_std)
+    # spot check against direct summation of the image itself
+    out = to_host(api.window_sum(S, 9, 11, 2, pixel_type=ptype, out_dtype=torch.uint64))
+    assert np.array_equal(out, oracle.window_sum_direct(img_np, 9, 11, 2))
+
+
+@pytest.mark.parametrize("dtype,offset,pitch_extra", [(np.uint8, 3, 5), (np.uint8, 1, 0), (np.uint16, 1, 3),
+                                                      (np.uint16, 2, 1)])
+def test_unaligned_image_and_odd_table_pitch(dtype, offset, pitch_extra):
+    print("case: unaligned", np.dtype(dtype).name, offset, pitch_extra, flush=True)
+    rng = np.random.default_rng(8)
+    H, W = 150, 700
+    hi = 256 if dtype == np.uint8 else 65536
+    img_np = rng.integers(0, hi, (H, W)).astype(dtype)
+    img = padded_image(img_np, W + pitch_extra, offset)
+    assert img.data_ptr() % 4 != 0 or pitch_extra % 4 != 0
+    big = torch.empty((H, W + 1), dtype=torch.uint64, device="cuda:0")     # odd pitch: scalar stores
+    S = big[:, :W]
+    bigq = torch.empty((H, W + 1), dtype=torch.uint64, device="cuda:0")
+    Q = bigq[:, :W]
+    api.sat_build(img, sat=S, sat_sq=Q)
+    ref_S, ref_Q = oracle.sat(img_np, squares=True)
+    assert np.array_equal(to_host(S), ref_S)
+    assert np.array_equal(to_host(Q), ref_Q)
+    out = api.window_sum(S, 5, 9, 1, pixel_type="u16", out_dtype=torch.uint64)
+    assert np.array_equal(to_host(out), oracle.window_sum_sat(ref_S, 5, 9, 1))
+
+
+def test_max_pixel_values():
+    for dtype, m in [(np.uint8, 255), (np.uint16, 65535)]:
+        img_np = np.full((257, 1031), m, dtype)
+        S, Q = api.sat_build(to_device(img_np), squares=True)
+        ref_S, ref_Q = oracle.sat(img_np, squares=True)
+        assert np.array_equal(to_host(S), ref_S)
+        assert np.array_equal(to_host(Q), ref_Q)
+        s1, mean, std = api.window_mean_std(S, Q, 64, 64, 1)
+        assert np.all(to_host(std) == 0.0) and np.all(to_host(mean) == float(m))
+
+
+# ------------------------------------------------------------------ variants, stress, fault word
+
+def test_every_build_variant_bit_exact():
+    rng = np.random.default_rng(9)
+    img_np = rng.integers(0, 65536, (1100, 2600)).astype(np.uint16)
+    ref_S, ref_Q = oracle.sat(img_np, squares=True)
+    img = to_device(img_np)
+    names = api.variants(0)
+    try:
+        for v, name in enumerate(names):
+            print("case: build variant", name, flush=True)
+            api.force_variant(0, v)
+            ws = torch.empty(api.build_workspace_bytes(1100, 2600, 2, True), dtype=torch.uint8, device="cuda:0")
+            S, Q = api.sat_build(img, squares=True, ws=ws)
+            api.workspace_check(ws)
+            assert np.array_equal(to_host(S), ref_S), name
+            assert np.array_equal(to_host(Q), ref_Q), name
+            img8 = to_device((img_np & 0xFF).astype(np.uint8))
+            S8 = api.sat_build(img8, ws=ws)
+            assert np.array_equal(to_host(S8), oracle.sat((img_np & 0xFF).astype(np.uint8))), name
+    finally:
+        api.force_variant(0, -1)
+
+
+def test_every_gather_variant_bit_exact():
+    rng = np.random.default_rng(10)
+    img_np = rng.integers(0, 256, (700, 3000)).astype(np.uint8)
+    S = api.sat_build(to_device(img_np))
+    ref_S = oracle.sat(img_np)
+    try:
+        for v, name in enumerate(api.variants(1)):
+            print("case: gather variant", name, flush=True)
+            api.force_variant(1, v)
+            for (h, w, s) in [(100, 100, 1), (250, 31, 2), (3, 2999, 1)]:
+                out = api.window_sum(S, h, w, s, pixel_type="u8")
+                assert np.array_equal(to_host(out).astype(np.uint64), oracle.window_sum_sat(ref_S, h, w, s)), name
+    finally:
+        api.force_variant(1, -1)
+
+
+def test_lookback_repeated_builds_many_strips():
+    """Many short strips (deep lookback chains), rebuilt repeatedly into the same workspace."""
+    rng = np.random.default_rng(11)
+    img_np = rng.integers(0, 256, (4099, 777)).astype(np.uint8)
+    ref_S = oracle.sat(img_np)
+    img = to_device(img_np)
+    ws = torch.empty(api.build_workspace_bytes(4099, 777, 1, False), dtype=torch.uint8, device="cuda:0")
+    try:
+        api.force_variant(0, 2)            # 16-row strips: 257 strips
+        for it in range(20):
+            S = api.sat_build(img, ws=ws)
+            api.workspace_check(ws)
+            assert np.array_equal(to_host(S), ref_S), it
+    finally:
+        api.force_variant(0, -1)
+
+
+def test_multi_window_matches_single():
+    rng = np.random.default_rng(12)
+    img_np = (rng.random((900, 1300)) < 0.01).astype(np.uint8)
+    S = api.sat_build(to_device(img_np))
+    ref_S = oracle.sat(img_np)
+    wins = [(100, 100), (250, 250), (500, 500), (7, 300)]
+    for s in (1, 3):
+        outs = api.window_sum_multi(S, wins, s, pixel_type="u8")
+        for (h, w), o in zip(wins, outs):
+            assert np.array_equal(to_host(o).astype(np.uint64), oracle.window_sum_sat(ref_S, h, w, s)), (h, w, s)
+
+
+def test_batched_build_and_mean_std():
+    from paper_2410_16291_amd import batch
+    imgs_np = synth.uneven_batch(9, lo=70, hi=900, seed=13)
+    imgs = [to_device(i) for i in imgs_np]
+    tables = batch.build_batched(imgs, squares=True)
+    outs = batch.mean_std_batched(tables, 64, 64, 4)
+    torch.cuda.synchronize()
+    for i, img_np in enumerate(imgs_np):
+        ref_S, ref_Q = oracle.sat(img_np, squares=True)
+        assert np.array_equal(to_host(tables[i][0]), ref_S), i
+        assert np.array_equal(to_host(tables[i][1]), ref_Q), i
+        sums = oracle.window_sum_sat(ref_S, 64, 64, 4)
+        ref_mean, ref_std = oracle.mean_std(sums, oracle.window_sum_sat(ref_Q, 64, 64, 4), 64 * 64)
+        s1, mean, std = outs[i]
+        assert np.array_equal(to_host(s1), sums), i
+        assert np.array_equal(to_host(mean), ref_mean), i
+        check_std(to_host(std), ref_std)
