@@ -56,16 +56,30 @@ __device__ __forceinline__ uint32_t dpp(uint32_t v) {
         __builtin_amdgcn_update_dpp(0, static_cast<int>(v), CTRL, ROW_MASK, 0xf, BOUND_ZERO));
 }
 
+// One step of a 64-bit scan as two 32-bit DPP moves and a 32-bit add with carry.  The step is
+// kept in 32-bit operations on purpose: with a fused 64-bit add the compiler placed the next DPP
+// read of the sum one instruction after its write, below the two wait states a DPP source
+// needs, and the upper lanes of each row read stale values.
 template <int CTRL, int ROW_MASK, bool BOUND_ZERO>
-__device__ __forceinline__ uint64_t dpp(uint64_t v) {
-    const uint32_t lo = dpp<CTRL, ROW_MASK, BOUND_ZERO>(static_cast<uint32_t>(v));
-    const uint32_t hi = dpp<CTRL, ROW_MASK, BOUND_ZERO>(static_cast<uint32_t>(v >> 32));
-    return (static_cast<uint64_t>(hi) << 32) | lo;
+__device__ __forceinline__ void dpp_add64(uint32_t &lo, uint32_t &hi) {
+    const uint32_t dlo = dpp<CTRL, ROW_MASK, BOUND_ZERO>(lo);
+    const uint32_t dhi = dpp<CTRL, ROW_MASK, BOUND_ZERO>(hi);
+    const uint32_t nlo = lo + dlo;
+    hi = hi + dhi + (nlo < lo ? 1u : 0u);
+    lo = nlo;
 }
 
+// 64-bit sum in 32-bit operations, for values that feed a DPP scan (see dpp_add64).
+__device__ __forceinline__ uint64_t add64(uint64_t a, uint64_t b) {
+    const uint32_t lo = static_cast<uint32_t>(a) + static_cast<uint32_t>(b);
+    const uint32_t hi = static_cast<uint32_t>(a >> 32) + static_cast<uint32_t>(b >> 32) +
+                        (lo < static_cast<uint32_t>(a) ? 1u : 0u);
+    return (static_cast<uint64_t>(hi) << 32) | lo;
+}
+__device__ __forceinline__ uint32_t add64(uint32_t a, uint32_t b) { return a + b; }
+
 // Inclusive prefix sum across the 64 lanes of a wave.
-template <typename U>
-__device__ __forceinline__ U wave_scan(U v) {
+__device__ __forceinline__ uint32_t wave_scan(uint32_t v) {
     v += dpp<0x111, 0xf, true>(v);   // row_shr:1
     v += dpp<0x112, 0xf, true>(v);   // row_shr:2
     v += dpp<0x114, 0xf, true>(v);   // row_shr:4
@@ -73,6 +87,17 @@ __device__ __forceinline__ U wave_scan(U v) {
     v += dpp<0x142, 0xa, false>(v);  // row_bcast:15 -> rows 1 and 3 add lane 15 / 47
     v += dpp<0x143, 0xc, false>(v);  // row_bcast:31 -> rows 2 and 3 add lane 31
     return v;
+}
+
+__device__ __forceinline__ uint64_t wave_scan(uint64_t v) {
+    uint32_t lo = static_cast<uint32_t>(v), hi = static_cast<uint32_t>(v >> 32);
+    dpp_add64<0x111, 0xf, true>(lo, hi);
+    dpp_add64<0x112, 0xf, true>(lo, hi);
+    dpp_add64<0x114, 0xf, true>(lo, hi);
+    dpp_add64<0x118, 0xf, true>(lo, hi);
+    dpp_add64<0x142, 0xa, false>(lo, hi);
+    dpp_add64<0x143, 0xc, false>(lo, hi);
+    return (static_cast<uint64_t>(hi) << 32) | lo;
 }
 
 __device__ __forceinline__ uint32_t readlane(uint32_t v, int l) {
@@ -94,17 +119,43 @@ __device__ __forceinline__ uint64_t load_state(const uint64_t *p) {
 
 constexpr int kRsrcWord3 = 0x00020000;   // raw buffer resource, 32-bit data format (gfx9 family)
 
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+
+// Raw buffer resource (base, stride 0, num_records bytes) as four scalar dwords.
+__device__ __forceinline__ i32x4 make_rsrc(const void *base, uint32_t num_records) {
+    const uint64_t a = reinterpret_cast<uint64_t>(base);
+    return i32x4{static_cast<int>(static_cast<uint32_t>(a)), static_cast<int>(static_cast<uint32_t>(a >> 32) & 0xffffu),
+                 static_cast<int>(num_records), kRsrcWord3};
+}
+
+// 16-byte buffer store with the two wait states the hardware needs before any VALU may
+// overwrite the store's data VGPRs (a store of more than 8 bytes reads its data after issue).
+// The compiler does not insert them for gfx950: an overwrite in the next cycle was seen to
+// corrupt lanes 12-15 of every 16-lane group.  Keeping the s_nop inside the same asm block
+// makes the gap independent of scheduling and register allocation.  The asm has no outputs.
+__device__ __forceinline__ void store16_rsrc(u32x4 data, i32x4 rsrc, uint32_t voff, uint32_t soff) {
+    asm volatile("buffer_store_dwordx4 %0, %1, %2, %3 offen\n\ts_nop 1"
+                 :
+                 : "v"(data), "v"(voff), "s"(rsrc), "s"(soff)
+                 : "memory");
+}
+
 template <typename T, bool SQ, int PX, int RW, int NW, int MODE>
 struct Build {
     static constexpr int TH = RW * NW;                       // strip height
     static constexpr int BW = 64 * PX;                       // block width
     static constexpr int NT = NW * 64;                       // threads per workgroup
+    static constexpr int NS = PX / 2;                        // 128-column sub-blocks per block
     static constexpr int PXB = PX * static_cast<int>(sizeof(T));   // bytes a lane owns in a row
-    static constexpr int NWORDS = PXB / 4;
     static constexpr int ROWB = BW * static_cast<int>(sizeof(T));  // bytes of one tile row
     static constexpr int TILEB = TH * ROWB;                  // bytes of one image tile
     static constexpr int PFW = TILEB / NT / 4;               // prefetch dwords per thread
-    static_assert(NWORDS >= 1 && PFW >= 4 && PFW % 4 == 0, "tile split into whole 16-byte chunks");
+    static_assert(PX % 2 == 0 && PFW >= 4 && PFW % 4 == 0, "lanes own column pairs; 16-byte chunks");
+
+    // Lane l owns, in every 128-column sub-block s of a block, the adjacent columns 2l and 2l+1;
+    // its p-th pixel (p = 2s + j) is column 128s + 2l + j of the block.  A table row segment of
+    // a sub-block is then one contiguous 1 KiB wave store (16 bytes per lane).
+    static __device__ __forceinline__ int col(int lane, int p) { return (p >> 1) * 128 + 2 * lane + (p & 1); }
     // Squared partial sums: 8-bit squares fit 32 bits for a whole block, 16-bit ones do not.
     using QT = typename std::conditional<sizeof(T) == 1, uint32_t, uint64_t>::type;
 
@@ -117,29 +168,19 @@ struct Build {
         long long ticket;
     };
 
-    static __device__ __forceinline__ uint32_t pix(const uint32_t (&raw)[NWORDS], int p) {
-        if (sizeof(T) == 1) return (raw[p >> 2] >> (8 * (p & 3))) & 0xffu;
+    // raw[s] holds the lane's pixel pair of sub-block s (two bytes or two halves).
+    static __device__ __forceinline__ uint32_t pix(const uint32_t (&raw)[NS], int p) {
+        if (sizeof(T) == 1) return (raw[p >> 1] >> (8 * (p & 1))) & 0xffu;
         return (raw[p >> 1] >> (16 * (p & 1))) & 0xffffu;
     }
 
     // This lane's PX pixels of tile row `row` (LDS).
-    static __device__ __forceinline__ void tile_px(const Smem &sm, int row, int lane, uint32_t (&raw)[NWORDS]) {
-        const uint32_t *src = sm.tile + (row * ROWB + lane * PXB) / 4;
-        if (NWORDS == 1) {
-            raw[0] = src[0];
-        } else if (NWORDS == 2) {
-            const u32x2 t = *reinterpret_cast<const u32x2 *>(src);
-            raw[0] = t.x;
-            raw[NWORDS > 1 ? 1 : 0] = t.y;
-        } else {
+    static __device__ __forceinline__ void tile_px(const Smem &sm, int row, int lane, uint32_t (&raw)[NS]) {
+        const T *src = reinterpret_cast<const T *>(sm.tile) + row * BW + 2 * lane;
 #pragma unroll
-            for (int i = 0; i < NWORDS; i += 4) {
-                const u32x4 t = *reinterpret_cast<const u32x4 *>(src + i);
-                raw[i] = t.x;
-                raw[(i + 1) % NWORDS] = t.y;
-                raw[(i + 2) % NWORDS] = t.z;
-                raw[(i + 3) % NWORDS] = t.w;
-            }
+        for (int s = 0; s < NS; ++s) {
+            if (sizeof(T) == 1) raw[s] = *reinterpret_cast<const uint16_t *>(src + 128 * s);
+            else raw[s] = *reinterpret_cast<const uint32_t *>(src + 128 * s);
         }
     }
 
@@ -221,34 +262,37 @@ struct Build {
 
     // Column totals of all strips above `strip` for this lane's PX columns (decoupled lookback),
     // after publishing this strip's own totals a / aq.  Run by one full wave.
-    static __device__ void lookback(const BuildDesc &d, int strip, int64_t xcol,
+    // Offset of the lane's p-th column from its first column (2 * lane) inside a block.
+    static __device__ __forceinline__ int soff(int p) { return (p >> 1) * 128 + (p & 1); }
+
+    static __device__ void lookback(const BuildDesc &d, int strip, int64_t xb, int lane,
                                     const uint64_t (&a)[PX], const uint64_t (&aq)[PX],
                                     uint64_t (&v)[PX], uint64_t (&vq)[PX], uint64_t *state,
                                     unsigned int *fault) {
-        uint64_t *mine = state + d.state_off + static_cast<int64_t>(strip) * d.Wp + xcol;
-        uint64_t *mine_q = state + d.state_q_off + static_cast<int64_t>(strip) * d.Wp + xcol;
+        uint64_t *mine = state + d.state_off + static_cast<int64_t>(strip) * d.Wp + xb + 2 * lane;
+        uint64_t *mine_q = state + d.state_q_off + static_cast<int64_t>(strip) * d.Wp + xb + 2 * lane;
 #pragma unroll
         for (int p = 0; p < PX; ++p) { v[p] = 0; vq[p] = 0; }
         if (strip == 0) {
 #pragma unroll
             for (int p = 0; p < PX; ++p) {
-                store_state(mine + p, kStPrefix | a[p]);
-                if (SQ) store_state(mine_q + p, kStPrefix | aq[p]);
+                store_state(mine + soff(p), kStPrefix | a[p]);
+                if (SQ) store_state(mine_q + soff(p), kStPrefix | aq[p]);
             }
             return;
         }
 #pragma unroll
         for (int p = 0; p < PX; ++p) {
-            store_state(mine + p, kStAggregate | a[p]);
-            if (SQ) store_state(mine_q + p, kStAggregate | aq[p]);
+            store_state(mine + soff(p), kStAggregate | a[p]);
+            if (SQ) store_state(mine_q + soff(p), kStAggregate | aq[p]);
         }
         constexpr uint32_t kAll = SQ ? ((1u << (2 * PX)) - 1u) : ((1u << PX) - 1u);
         uint32_t done = 0;
         uint32_t spins = 0;
         int j = strip - 1;
         for (;;) {
-            const uint64_t *up = state + d.state_off + static_cast<int64_t>(j) * d.Wp + xcol;
-            const uint64_t *up_q = state + d.state_q_off + static_cast<int64_t>(j) * d.Wp + xcol;
+            const uint64_t *up = state + d.state_off + static_cast<int64_t>(j) * d.Wp + xb + 2 * lane;
+            const uint64_t *up_q = state + d.state_q_off + static_cast<int64_t>(j) * d.Wp + xb + 2 * lane;
             uint64_t w[PX], wq[PX];
             bool ready = true;
 #pragma unroll
@@ -256,11 +300,11 @@ struct Build {
                 w[p] = 0;
                 wq[p] = 0;
                 if (!(done & (1u << p))) {
-                    w[p] = load_state(up + p);
+                    w[p] = load_state(up + soff(p));
                     ready = ready && (w[p] >> 62) != 0;
                 }
                 if (SQ && !(done & (1u << (PX + p)))) {
-                    wq[p] = load_state(up_q + p);
+                    wq[p] = load_state(up_q + soff(p));
                     ready = ready && (wq[p] >> 62) != 0;
                 }
             }
@@ -288,18 +332,21 @@ struct Build {
         }
 #pragma unroll
         for (int p = 0; p < PX; ++p) {
-            store_state(mine + p, kStPrefix | (v[p] + a[p]));
-            if (SQ) store_state(mine_q + p, kStPrefix | (vq[p] + aq[p]));
+            store_state(mine + soff(p), kStPrefix | (v[p] + a[p]));
+            if (SQ) store_state(mine_q + soff(p), kStPrefix | (vq[p] + aq[p]));
         }
     }
 
     // One table's rows of the block for this wave; returns the row totals (lane r holds row r's)
-    // to add to the left carries.  Stores go through buffer resources so that the hardware range
-    // check, not a branch per row, drops what lies outside the image:
+    // to add to the left carries.  Per row and sub-block: the lane's pixel pair, a DPP scan of
+    // pair sums across the wave, then one 16-byte store per lane (contiguous across the wave).
+    // Stores go through buffer resources so that the hardware range check, not a branch per
+    // row, drops what lies outside the image:
     //   VEC (block wholly inside the image width, 16-byte aligned rows): one resource spanning
     //     the wave's rows from the block start, records ending at the last valid row's width;
     //     row r is addressed by the scalar offset r * pitch.
-    //   ragged: one resource per row covering exactly [block start, W) of that row.
+    //   ragged: one resource per row covering exactly [block start, W) of that row, 8-byte
+    //     stores.
     template <typename ST, bool SQUARE, bool VEC>
     static __device__ __forceinline__ uint64_t rows_pass(const Smem &sm, int wave, int lane, const uint64_t (&u)[PX],
                                                          uint64_t lcarry, uint64_t *blk0, int rows_ok,
@@ -308,52 +355,44 @@ struct Build {
 #pragma unroll
         for (int p = 0; p < PX; ++p) acc[p] = 0;
         uint64_t tvec = 0;
-        const uint32_t voff = static_cast<uint32_t>(lane) * PX * 8;
+        const uint32_t voff = static_cast<uint32_t>(lane) * 16;
         const int nvalid = rows_ok > 0 ? rows_ok : 0;
         const uint32_t blk_recs = nvalid > 0 ? (nvalid - 1) * pitch_bytes + row_recs : 0;
-        const __amdgpu_buffer_rsrc_t rs_blk =
-            __builtin_amdgcn_make_buffer_rsrc(blk0, 0, VEC ? static_cast<int>(blk_recs) : 0, kRsrcWord3);
+        const i32x4 rs_blk = make_rsrc(blk0, VEC ? blk_recs : 0);
         const char *rowp = reinterpret_cast<const char *>(blk0);
         uint32_t roff = 0;
 #pragma unroll 1
         for (int r = 0; r < RW; ++r) {
-            uint32_t raw[NWORDS];
+            uint32_t raw[NS];
             tile_px(sm, wave * RW + r, lane, raw);
-            ST pre[PX];
-            ST s = 0;
+            uint64_t base = readlane(lcarry, r);      // row total left of this sub-block
+            const __amdgpu_buffer_rsrc_t rs_row = __builtin_amdgcn_make_buffer_rsrc(
+                const_cast<char *>(rowp), 0, (!VEC && r < rows_ok) ? static_cast<int>(row_recs) : 0, kRsrcWord3);
 #pragma unroll
-            for (int p = 0; p < PX; ++p) {
-                const ST v = pix(raw, p);
-                s += SQUARE ? v * v : v;
-                pre[p] = s;
+            for (int sb = 0; sb < NS; ++sb) {
+                const ST v0 = pix(raw, 2 * sb), v1 = pix(raw, 2 * sb + 1);
+                const ST a0 = SQUARE ? v0 * v0 : v0;
+                const ST a1 = SQUARE ? v1 * v1 : v1;
+                const ST pair = add64(a0, a1);
+                const ST incl = wave_scan(pair);
+                const uint64_t b = base + (incl - pair);
+                acc[2 * sb] += b + a0;
+                acc[2 * sb + 1] += b + pair;
+                const uint64_t o0 = u[2 * sb] + acc[2 * sb], o1 = u[2 * sb + 1] + acc[2 * sb + 1];
+                if (VEC) {
+                    store16_rsrc(u32x4{static_cast<uint32_t>(o0), static_cast<uint32_t>(o0 >> 32),
+                                       static_cast<uint32_t>(o1), static_cast<uint32_t>(o1 >> 32)},
+                                 rs_blk, voff + sb * 1024, roff);
+                } else {
+                    __builtin_amdgcn_raw_buffer_store_b64(u32x2{static_cast<uint32_t>(o0), static_cast<uint32_t>(o0 >> 32)},
+                                                          rs_row, voff + sb * 1024, 0, 0);
+                    __builtin_amdgcn_raw_buffer_store_b64(u32x2{static_cast<uint32_t>(o1), static_cast<uint32_t>(o1 >> 32)},
+                                                          rs_row, voff + sb * 1024 + 8, 0, 0);
+                }
+                base += readlane(incl, 63);
             }
-            const ST incl = wave_scan(s);
-            const uint64_t base = readlane(lcarry, r) + (incl - s);
-            const ST row_total = readlane(incl, 63);
-            if (lane == r) tvec = row_total;
-            uint64_t out[PX];
-#pragma unroll
-            for (int p = 0; p < PX; ++p) {
-                acc[p] += base + pre[p];
-                out[p] = u[p] + acc[p];
-            }
-            if (VEC) {
-#pragma unroll
-                for (int p = 0; p < PX; p += 2)
-                    __builtin_amdgcn_raw_buffer_store_b128(
-                        u32x4{static_cast<uint32_t>(out[p]), static_cast<uint32_t>(out[p] >> 32),
-                              static_cast<uint32_t>(out[p + 1]), static_cast<uint32_t>(out[p + 1] >> 32)},
-                        rs_blk, voff + 8 * p, static_cast<int>(roff), 0);
-            } else {
-                const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-                    const_cast<char *>(rowp), 0, r < rows_ok ? static_cast<int>(row_recs) : 0, kRsrcWord3);
-#pragma unroll
-                for (int p = 0; p < PX; ++p)
-                    __builtin_amdgcn_raw_buffer_store_b64(
-                        u32x2{static_cast<uint32_t>(out[p]), static_cast<uint32_t>(out[p] >> 32)}, rs,
-                        voff + 8 * p, 0, 0);
-                rowp += pitch_bytes;
-            }
+            if (lane == r) tvec = base - readlane(lcarry, r);
+            rowp += pitch_bytes;
             roff += pitch_bytes;
         }
         return tvec;
@@ -385,7 +424,6 @@ struct Build {
         for (int b = 0; b < d.nblocks; ++b) {
             const int buf = b & 1;
             const int64_t xb = static_cast<int64_t>(b) * BW;
-            const int64_t xcol = xb + lane * PX;
 
             // Column sums of this wave's rows.
             {
@@ -395,7 +433,7 @@ struct Build {
                 for (int p = 0; p < PX; ++p) { cs[p] = 0; csq[p] = 0; }
 #pragma unroll 2
                 for (int r = 0; r < RW; ++r) {
-                    uint32_t raw[NWORDS];
+                    uint32_t raw[NS];
                     tile_px(sm, wave * RW + r, lane, raw);
 #pragma unroll
                     for (int p = 0; p < PX; ++p) {
@@ -428,14 +466,14 @@ struct Build {
                     }
                 }
                 if (MODE == MODE_LOOKBACK) {
-                    lookback(d, strip_idx, xcol, a, aq, v, vq, state, fault);
+                    lookback(d, strip_idx, xb, lane, a, aq, v, vq, state, fault);
                 } else {
-                    const uint64_t *tot = state + d.state_off + static_cast<int64_t>(strip_idx) * d.Wp + xcol;
-                    const uint64_t *tot_q = state + d.state_q_off + static_cast<int64_t>(strip_idx) * d.Wp + xcol;
+                    const uint64_t *tot = state + d.state_off + static_cast<int64_t>(strip_idx) * d.Wp + xb + 2 * lane;
+                    const uint64_t *tot_q = state + d.state_q_off + static_cast<int64_t>(strip_idx) * d.Wp + xb + 2 * lane;
 #pragma unroll
                     for (int p = 0; p < PX; ++p) {
-                        v[p] = tot[p];
-                        vq[p] = SQ ? tot_q[p] : 0;
+                        v[p] = tot[soff(p)];
+                        vq[p] = SQ ? tot_q[soff(p)] : 0;
                     }
                 }
 #pragma unroll
@@ -461,22 +499,23 @@ struct Build {
                         c[p] += sm.cs[buf][w][lane * PX + p];
                         if (SQ) cq[p] += sm.csq[buf][w][lane * PX + p];
                     }
+                // Sub-block by sub-block: pair prefix in the lane, DPP scan of pair totals.
 #pragma unroll
-                for (int p = 1; p < PX; ++p) {
-                    c[p] += c[p - 1];
-                    if (SQ) cq[p] += cq[p - 1];
-                }
-                const uint64_t incl = wave_scan(c[PX - 1]);
-                const uint64_t base = ucarry + (incl - c[PX - 1]);
-#pragma unroll
-                for (int p = 0; p < PX; ++p) u[p] = base + c[p];
-                ucarry += readlane(incl, 63);
-                if (SQ) {
-                    const uint64_t incl_q = wave_scan(cq[PX - 1]);
-                    const uint64_t base_q = ucarry_q + (incl_q - cq[PX - 1]);
-#pragma unroll
-                    for (int p = 0; p < PX; ++p) uq[p] = base_q + cq[p];
-                    ucarry_q += readlane(incl_q, 63);
+                for (int sb = 0; sb < NS; ++sb) {
+                    const uint64_t pair = add64(c[2 * sb], c[2 * sb + 1]);
+                    const uint64_t incl = wave_scan(pair);
+                    const uint64_t b = ucarry + (incl - pair);
+                    u[2 * sb] = b + c[2 * sb];
+                    u[2 * sb + 1] = b + pair;
+                    ucarry += readlane(incl, 63);
+                    if (SQ) {
+                        const uint64_t pair_q = add64(cq[2 * sb], cq[2 * sb + 1]);
+                        const uint64_t incl_q = wave_scan(pair_q);
+                        const uint64_t b_q = ucarry_q + (incl_q - pair_q);
+                        uq[2 * sb] = b_q + cq[2 * sb];
+                        uq[2 * sb + 1] = b_q + pair_q;
+                        ucarry_q += readlane(incl_q, 63);
+                    }
                 }
             }
 
@@ -540,8 +579,10 @@ __global__ void clear_kernel(uint64_t *state, long long nwords, BuildCtrl *ctrl,
         if (slot) *slot = one;
     }
     const long long step = static_cast<long long>(gridDim.x) * blockDim.x;
-    for (long long i = i0; 2 * i < nwords; i += step)
-        *reinterpret_cast<u64x2 *>(state + 2 * i) = u64x2{0, 0};
+    for (long long i = i0; 2 * i < nwords; i += step) {   // 8-byte stores: see store16_rsrc
+        state[2 * i] = 0;
+        state[2 * i + 1] = 0;
+    }
 }
 
 // Reduce-then-scan ablation, phase 1: column totals of every strip (TH rows) of one image.

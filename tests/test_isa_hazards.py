@@ -1,0 +1,133 @@
+"""Guards on the gfx950 assembly of this library's own kernels (compiled here with hipcc -S).
+
+Two instruction-ordering hazards were found on the GPU that the compiler does not mitigate for
+gfx950; both corrupted results silently in lanes 12-15 of 16-lane groups:
+  1. a vector-memory store of more than 8 bytes (dwordx3/x4) whose data VGPRs are overwritten by
+     the very next VALU instruction: the store reads its data after issue;
+  2. a DPP read of a VGPR written shortly before by a 64-bit VALU operation (v_lshl_add_u64 and
+     kin), at the minimum distance the compiler allows.
+The kernels avoid both by construction (an asm store carrying its own s_nop, 32-bit carry adds
+in front of every DPP scan).  This test fails if a change reintroduces either pattern.
+"""
+import os
+import re
+import subprocess
+import tempfile
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_2410_16291_amd", "csrc")
+SOURCES = ["sat_build.hip", "sat_gather.hip"]
+
+
+def compile_asm(src, out):
+    from paper_2410_16291_amd import build
+    cmd = [build.hipcc(), "--offload-arch=gfx950", "-O3", "-std=c++17", "-S", "--cuda-device-only",
+           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-ffp-contract=off",
+           "-I" + os.path.join(ROOT, "include"), "-I" + CSRC, os.path.join(CSRC, src), "-o", out]
+    subprocess.run(cmd, check=True, capture_output=True)
+    return open(out).read()
+
+
+def instructions(text):
+    out = []
+    for line in text.splitlines():
+        t = line.strip()
+        if not t or t.startswith((".", ";")) or t.endswith(":"):
+            continue
+        out.append(t)
+    return out
+
+
+def vregs(op):
+    op = op.strip().split()[0] if op.strip() else ""
+    m = re.match(r"v\[(\d+):(\d+)\]$", op)
+    if m:
+        return set(range(int(m.group(1)), int(m.group(2)) + 1))
+    m = re.match(r"v(\d+)$", op)
+    return {int(m.group(1))} if m else set()
+
+
+def operands(inst):
+    parts = inst.split(None, 1)
+    return [o.strip() for o in parts[1].split(",")] if len(parts) > 1 else []
+
+
+def wait_states(inst):
+    mnem = inst.split()[0]
+    if mnem == "s_nop":
+        return int(inst.split()[1], 0) + 1
+    return 1
+
+
+def store_data_hazards(insts):
+    bad = []
+    for i, t in enumerate(insts):
+        mnem = t.split()[0]
+        if not re.match(r"(buffer|global|flat)_store_dwordx[34]$", mnem):
+            continue
+        ops = operands(t)
+        data = vregs(ops[1] if mnem.startswith(("global", "flat")) else ops[0])
+        ws = 0
+        for j in range(i + 1, min(len(insts), i + 4)):
+            nxt = insts[j]
+            if ws >= 1:
+                break
+            if nxt.split()[0].startswith("v_") and operands(nxt):
+                if vregs(operands(nxt)[0]) & data:
+                    bad.append((t, nxt))
+            ws += wait_states(nxt)
+    return bad
+
+
+WIDE_VALU = re.compile(r"v_(lshl_add_u64|mad_u64_u32|mad_i64_i32|\w+_f64|mov_b64|\w+_u64|\w+_i64)")
+
+
+def dpp_hazards(insts, window=5):
+    bad = []
+    for i, t in enumerate(insts):
+        if "_dpp" not in t.split()[0]:
+            continue
+        ops = operands(t)
+        srcs = set()
+        for o in ops[1:3]:
+            srcs |= vregs(o)
+        ws = 0
+        for j in range(i - 1, max(-1, i - 16), -1):
+            prev = insts[j]
+            if ws >= window:
+                break
+            if WIDE_VALU.match(prev.split()[0]) and operands(prev) and vregs(operands(prev)[0]) & srcs:
+                bad.append((prev, t))
+            ws += wait_states(prev)
+    return bad
+
+
+@pytest.fixture(scope="module")
+def asm():
+    texts = {}
+    with tempfile.TemporaryDirectory() as d:
+        for src in SOURCES:
+            texts[src] = instructions(compile_asm(src, os.path.join(d, src + ".s")))
+    return texts
+
+
+def test_detectors_flag_known_bad_sequences():
+    seq = instructions("\tbuffer_store_dwordx4 v[58:61], v98, s[8:11], s62 offen\n\tv_and_b32_e32 v58, 0xffff, v63\n")
+    assert store_data_hazards(seq)
+    ok = instructions("\tbuffer_store_dwordx4 v[58:61], v98, s[8:11], s62 offen\n\ts_nop 1\n\tv_and_b32_e32 v58, 0xffff, v63\n")
+    assert not store_data_hazards(ok)
+    seq = instructions("\tv_lshl_add_u64 v[46:47], v[16:17], 0, v[46:47]\n\tv_mov_b32_e32 v2, s9\n"
+                       "\tv_mov_b32_dpp v17, v47 row_shr:8 row_mask:0xf bank_mask:0xf bound_ctrl:1\n")
+    assert dpp_hazards(seq)
+
+
+def test_no_wide_store_data_overwrite(asm):
+    for src, insts in asm.items():
+        assert not store_data_hazards(insts), (src, store_data_hazards(insts)[:3])
+
+
+def test_no_dpp_read_of_fresh_64bit_result(asm):
+    for src, insts in asm.items():
+        assert not dpp_hazards(insts), (src, dpp_hazards(insts)[:3])
