@@ -69,9 +69,11 @@ sat_status window_out_shape(int64_t H, int64_t W, int64_t win_h, int64_t win_w, 
                             int64_t *out_h, int64_t *out_w);
 
 /* Bytes of device workspace sat_build needs for an H x W image (with_sq != 0: also the squared
- * table).  Returns 0 for invalid sizes.  The workspace holds the per-strip lookback words of the
- * column scan and two control words; its contents need no initialisation and are scratch after
- * the call returns, but the workspace must not be shared by two builds in flight. */
+ * table), for the kernel variant a sat_build on the calling thread would use (the built-in choice
+ * for this size, or the one sat_force_variant set).  Returns 0 for invalid sizes.  The workspace
+ * holds one lookback word per column per strip of rows for the column scan and a control block;
+ * its contents need no initialisation and are scratch after the call returns, but the workspace
+ * must not be shared by two builds in flight. */
 size_t sat_build_workspace_bytes(int64_t H, int64_t W, sat_dtype pixel_type, int with_sq);
 
 /* Integral image of an H x W image (Sec. II-B, Sec. III-B):

@@ -117,32 +117,52 @@ int device_cus() {
 int choose_build_variant(int64_t total_rows, int n_images) {
     const int v = g_force[0];
     if (v >= 0) return v;
+    // Each work item is one strip swept across the full width, so the number of strips is the
+    // parallelism: the widest-block variant once there are two strips per CU, else shorter
+    // strips.
     const int64_t want = 2ll * device_cus();
     const int64_t strips64 = (total_rows + 63 * n_images) / 64;
     if (strips64 >= want) return 0;
-    const int64_t strips32 = (total_rows + 31 * n_images) / 32;
-    if (strips32 >= want) return 1;
     return 2;
 }
 
-int64_t state_words_for(const satk::BuildVariant &v, int64_t H, int64_t W, bool sq) {
-    const int64_t strips = (H + v.th() - 1) / v.th();
+// Strip height for one image: the variant's full height unless the strips would not fit the
+// resident workgroups in whole rounds; then the height that spreads them evenly over the fewest
+// rounds (a last round with few strips costs a whole strip sweep).
+int choose_strip_h(int v, int64_t H, int bpp, bool sq) {
+    const satk::BuildVariant &var = satk::build_variant(v);
+    const int th = var.th();
+    if (!satk::build_variant_adaptive(v)) return th;
+    const int64_t cap = satk::build_variant_capacity(v, bpp, sq);
+    const int64_t strips = (H + th - 1) / th;
+    if (cap < 1 || strips <= cap) return th;
+    const int64_t rounds = (strips + cap - 1) / cap;
+    int64_t h = (H + rounds * cap - 1) / (rounds * cap);
+    if (h < 1) h = 1;
+    return static_cast<int>(h < th ? h : th);
+}
+
+// Lower bound of the strip height any variant may pick (for workspace sizing): with at least two
+// rounds the balanced height exceeds half the full height.
+int min_strip_h(const satk::BuildVariant &v, int adaptive) {
+    return adaptive ? (v.th() + 1) / 2 : v.th();
+}
+
+int64_t state_words_for(const satk::BuildVariant &v, int64_t H, int64_t W, bool sq, int strip_h) {
+    const int64_t strips = (H + strip_h - 1) / strip_h;
     const int64_t wp = (W + v.bw() - 1) / v.bw() * v.bw();
     int64_t words = strips * wp * (sq ? 2 : 1);
     return (words + 1) & ~1ll;
 }
 
-int64_t max_state_words(int64_t H, int64_t W, bool sq) {
-    int64_t m = 0;
-    for (int i = 0; i < satk::build_variant_count(); ++i) {
-        const int64_t w = state_words_for(satk::build_variant(i), H, W, sq);
-        if (w > m) m = w;
-    }
-    return m;
+// Lookback words a build of one image with variant v may need (any strip height it may pick).
+int64_t build_state_words(int v, int64_t H, int64_t W, bool sq) {
+    const satk::BuildVariant &var = satk::build_variant(v);
+    return state_words_for(var, H, W, sq, min_strip_h(var, satk::build_variant_adaptive(v)));
 }
 
 void fill_desc(satk::BuildDesc &d, const satk::BuildVariant &v, const void *image, int bpp, int64_t H,
-               int64_t W, int64_t ipitch, uint64_t *sat, uint64_t *sat_sq, int64_t spitch) {
+               int64_t W, int64_t ipitch, uint64_t *sat, uint64_t *sat_sq, int64_t spitch, int strip_h) {
     d.img = image;
     d.S = sat;
     d.Q = sat_sq;
@@ -150,7 +170,9 @@ void fill_desc(satk::BuildDesc &d, const satk::BuildVariant &v, const void *imag
     d.W = W;
     d.ipitch = ipitch;
     d.spitch = spitch;
-    d.nstrips = static_cast<int32_t>((H + v.th() - 1) / v.th());
+    d.strip_h = strip_h;
+    d.wave_rows = (strip_h + v.nw - 1) / v.nw;
+    d.nstrips = static_cast<int32_t>((H + strip_h - 1) / strip_h);
     d.nblocks = static_cast<int32_t>((W + v.bw() - 1) / v.bw());
     d.Wp = static_cast<int64_t>(d.nblocks) * v.bw();
     const uintptr_t ia = reinterpret_cast<uintptr_t>(image);
@@ -249,7 +271,9 @@ sat_status window_out_shape(int64_t H, int64_t W, int64_t win_h, int64_t win_w, 
 size_t sat_build_workspace_bytes(int64_t H, int64_t W, sat_dtype pixel_type, int with_sq) {
     if (H < 1 || W < 1 || H > kMaxDim || W > kMaxDim) return 0;
     if (pixel_type != SAT_U8 && pixel_type != SAT_U16) return 0;
-    return sizeof(satk::BuildCtrl) + 8 * static_cast<size_t>(max_state_words(H, W, with_sq != 0));
+    const int v = choose_build_variant(H, 1);
+    if (v < 0 || v >= satk::build_variant_count()) return 0;
+    return sizeof(satk::BuildCtrl) + 8 * static_cast<size_t>(build_state_words(v, H, W, with_sq != 0));
 }
 
 sat_status sat_build(const void *image, sat_dtype pixel_type, int64_t H, int64_t W, int64_t image_pitch,
@@ -273,11 +297,12 @@ sat_status sat_build(const void *image, sat_dtype pixel_type, int64_t H, int64_t
     if (v < 0 || v >= satk::build_variant_count()) return fail(SAT_ERR_ARG, "%s: forced variant out of range", who);
     const satk::BuildVariant &var = satk::build_variant(v);
     satk::BuildDesc d{};
-    fill_desc(d, var, image, bpp, H, W, image_pitch, sat, sat_sq, sat_pitch);
+    const int strip_h = choose_strip_h(v, H, bpp, sat_sq != nullptr);
+    fill_desc(d, var, image, bpp, H, W, image_pitch, sat, sat_sq, sat_pitch, strip_h);
     d.state_off = 0;
     d.state_q_off = static_cast<int64_t>(d.nstrips) * d.Wp;
     d.first_item = 0;
-    const int64_t words = state_words_for(var, H, W, sat_sq != nullptr);
+    const int64_t words = state_words_for(var, H, W, sat_sq != nullptr, strip_h);
     hipError_t e = satk::launch_build(v, bpp, sat_sq != nullptr, &d, 1, nullptr, d.nstrips, workspace, words,
                                       static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, who);
@@ -387,10 +412,16 @@ size_t sat_batch_workspace_bytes(const sat_batch_item *items, int32_t n, sat_dty
     if (!items || n < 1) return 0;
     if (pixel_type != SAT_U8 && pixel_type != SAT_U16) return 0;
     size_t words = 0;
+    int64_t rows = 0;
     for (int i = 0; i < n; ++i) {
         if (items[i].H < 1 || items[i].W < 1 || items[i].H > kMaxDim || items[i].W > kMaxDim) return 0;
-        words += static_cast<size_t>(max_state_words(items[i].H, items[i].W, with_sq != 0));
+        rows += items[i].H;
     }
+    const int v = choose_build_variant(rows, n);
+    if (v < 0 || v >= satk::build_variant_count()) return 0;
+    const satk::BuildVariant &var = satk::build_variant(v);
+    for (int i = 0; i < n; ++i)
+        words += static_cast<size_t>(state_words_for(var, items[i].H, items[i].W, with_sq != 0, var.th()));
     const size_t descs = round256(static_cast<size_t>(n) *
                                   (sizeof(satk::BuildDesc) > sizeof(satk::GatherDesc) ? sizeof(satk::BuildDesc)
                                                                                       : sizeof(satk::GatherDesc)));
@@ -444,7 +475,7 @@ sat_status sat_build_batched(const sat_batch_item *items, int32_t n, sat_dtype p
     int64_t off = 0, items_total = 0;
     for (int i = 0; i < n; ++i) {
         const sat_batch_item &it = items[i];
-        fill_desc(d[i], var, it.image, bpp, it.H, it.W, it.image_pitch, it.sat, it.sat_sq, it.sat_pitch);
+        fill_desc(d[i], var, it.image, bpp, it.H, it.W, it.image_pitch, it.sat, it.sat_sq, it.sat_pitch, var.th());
         const int64_t plane = static_cast<int64_t>(d[i].nstrips) * d[i].Wp;
         d[i].state_off = off;
         d[i].state_q_off = off + plane;

@@ -188,7 +188,8 @@ struct Build {
     // VB-byte loads; every thread loads PFW dwords of it as VB-byte chunks (consecutive threads,
     // consecutive chunks of a row) into registers, committed to LDS later.
     template <int VB>
-    static __device__ __forceinline__ void fetch(const BuildDesc &d, int64_t ys, int64_t xb, uint32_t (&pf)[PFW]) {
+    static __device__ __forceinline__ void fetch(const BuildDesc &d, int64_t ys, int64_t xb, int nvalid,
+                                                 uint32_t (&pf)[PFW]) {
         constexpr int CPR = ROWB / VB;                       // chunks per tile row
         constexpr int WPC = VB / 4;                          // dwords per chunk
         constexpr int NCH = PFW / WPC;                       // chunks per thread
@@ -197,9 +198,10 @@ struct Build {
         const int64_t pitchb = d.ipitch * static_cast<int64_t>(sizeof(T));
         const unsigned char *base = static_cast<const unsigned char *>(d.img) +
                                     (ys * d.ipitch + xb) * static_cast<int64_t>(sizeof(T));
-        // The tile lies wholly inside the image here; the resource only carries the addressing.
+        // The resource ends after the strip's last valid row: rows past it read as zero.
+        const uint32_t recs = static_cast<uint32_t>(nvalid - 1) * static_cast<uint32_t>(pitchb) + ROWB;
         const __amdgpu_buffer_rsrc_t rs =
-            __builtin_amdgcn_make_buffer_rsrc(const_cast<unsigned char *>(base), 0, 0x7fffffff, kRsrcWord3);
+            __builtin_amdgcn_make_buffer_rsrc(const_cast<unsigned char *>(base), 0, static_cast<int>(recs), kRsrcWord3);
         const uint32_t voff = static_cast<uint32_t>((threadIdx.x / CPR) * pitchb + (threadIdx.x % CPR) * VB);
         const uint32_t step = static_cast<uint32_t>(RPI * pitchb);
 #pragma unroll
@@ -233,14 +235,15 @@ struct Build {
         }
     }
 
-    static __device__ __forceinline__ bool fast_tile(const BuildDesc &d, int64_t ys, int64_t xb) {
-        return d.img_vb != 0 && xb + BW <= d.W && ys + TH <= d.H;
+    static __device__ __forceinline__ bool fast_tile(const BuildDesc &d, int64_t xb) {
+        return d.img_vb != 0 && xb + BW <= d.W;
     }
 
-    static __device__ __forceinline__ void fetch_any(const BuildDesc &d, int64_t ys, int64_t xb, uint32_t (&pf)[PFW]) {
-        if (d.img_vb == 16) fetch<16>(d, ys, xb, pf);
-        else if (d.img_vb == 8) fetch<8>(d, ys, xb, pf);
-        else fetch<4>(d, ys, xb, pf);
+    static __device__ __forceinline__ void fetch_any(const BuildDesc &d, int64_t ys, int64_t xb, int nvalid,
+                                                     uint32_t (&pf)[PFW]) {
+        if (d.img_vb == 16) fetch<16>(d, ys, xb, nvalid, pf);
+        else if (d.img_vb == 8) fetch<8>(d, ys, xb, nvalid, pf);
+        else fetch<4>(d, ys, xb, nvalid, pf);
     }
     static __device__ __forceinline__ void commit_any(const BuildDesc &d, Smem &sm, const uint32_t (&pf)[PFW]) {
         if (d.img_vb == 16) commit<16>(sm, pf);
@@ -248,15 +251,16 @@ struct Build {
         else commit<4>(sm, pf);
     }
 
-    // Slow path (ragged or unaligned tiles): element by element, zeros outside the image.
-    static __device__ void load_tile_slow(const BuildDesc &d, Smem &sm, int64_t ys, int64_t xb) {
+    // Slow path (ragged or unaligned tiles): element by element, zeros outside the strip's
+    // valid rows and the image width.
+    static __device__ void load_tile_slow(const BuildDesc &d, Smem &sm, int64_t ys, int64_t xb, int nvalid) {
         const T *img = static_cast<const T *>(d.img);
         T *tile = reinterpret_cast<T *>(sm.tile);
 #pragma unroll 4
         for (int e = threadIdx.x; e < TH * BW; e += NT) {
             const int row = e / BW, col = e % BW;
             const int64_t y = ys + row, x = xb + col;
-            tile[e] = (y < d.H && x < d.W) ? img[y * d.ipitch + x] : static_cast<T>(0);
+            tile[e] = (row < nvalid && x < d.W) ? img[y * d.ipitch + x] : static_cast<T>(0);
         }
     }
 
@@ -337,6 +341,99 @@ struct Build {
         }
     }
 
+    // Decoupled lookback that reads the states of WIN strips per round trip (j, j-1, ...,
+    // j-WIN+1) and consumes them in order while every still-open column of the wave is ready:
+    // aggregates are added and the walk goes on, an inclusive prefix (or strip 0) closes the
+    // column.  When all strips are in flight together, prefixes propagate one strip per memory
+    // round trip; the window lets a walk cover WIN strips per round trip instead.
+    template <int WIN>
+    static __device__ void lookback_win(const BuildDesc &d, int strip, int64_t xb, int lane,
+                                        const uint64_t (&a)[PX], const uint64_t (&aq)[PX],
+                                        uint64_t (&v)[PX], uint64_t (&vq)[PX], uint64_t *state,
+                                        unsigned int *fault) {
+        const int64_t col0 = xb + 2 * lane;
+        uint64_t *mine = state + d.state_off + static_cast<int64_t>(strip) * d.Wp + col0;
+        uint64_t *mine_q = state + d.state_q_off + static_cast<int64_t>(strip) * d.Wp + col0;
+#pragma unroll
+        for (int p = 0; p < PX; ++p) { v[p] = 0; vq[p] = 0; }
+        if (strip == 0) {
+#pragma unroll
+            for (int p = 0; p < PX; ++p) {
+                store_state(mine + soff(p), kStPrefix | a[p]);
+                if (SQ) store_state(mine_q + soff(p), kStPrefix | aq[p]);
+            }
+            return;
+        }
+#pragma unroll
+        for (int p = 0; p < PX; ++p) {
+            store_state(mine + soff(p), kStAggregate | a[p]);
+            if (SQ) store_state(mine_q + soff(p), kStAggregate | aq[p]);
+        }
+        constexpr uint32_t kAll = SQ ? ((1u << (2 * PX)) - 1u) : ((1u << PX) - 1u);
+        uint32_t done = 0;
+        uint32_t spins = 0;
+        int j = strip - 1;
+        for (;;) {
+            uint64_t w[WIN][PX], wq[WIN][PX];
+#pragma unroll
+            for (int k = 0; k < WIN; ++k) {
+                const int jj = j - k;
+                const uint64_t *up = state + d.state_off + static_cast<int64_t>(jj) * d.Wp + col0;
+                const uint64_t *up_q = state + d.state_q_off + static_cast<int64_t>(jj) * d.Wp + col0;
+#pragma unroll
+                for (int p = 0; p < PX; ++p) {
+                    w[k][p] = 0;
+                    wq[k][p] = 0;
+                    if (jj >= 0 && !(done & (1u << p))) w[k][p] = load_state(up + soff(p));
+                    if (SQ && jj >= 0 && !(done & (1u << (PX + p)))) wq[k][p] = load_state(up_q + soff(p));
+                }
+            }
+            int consumed = 0;
+            bool stalled = false;
+#pragma unroll
+            for (int k = 0; k < WIN; ++k) {
+                const int jj = j - k;
+                if (stalled || jj < 0 || __all(done == kAll)) break;
+                bool ready = true;
+#pragma unroll
+                for (int p = 0; p < PX; ++p) {
+                    if (!(done & (1u << p))) ready = ready && (w[k][p] >> 62) != 0;
+                    if (SQ && !(done & (1u << (PX + p)))) ready = ready && (wq[k][p] >> 62) != 0;
+                }
+                if (!__all(ready)) {
+                    stalled = true;
+                    break;
+                }
+#pragma unroll
+                for (int p = 0; p < PX; ++p) {
+                    if (!(done & (1u << p))) {
+                        v[p] += w[k][p] & kValueMask;
+                        if ((w[k][p] >> 62) == 2 || jj == 0) done |= 1u << p;
+                    }
+                    if (SQ && !(done & (1u << (PX + p)))) {
+                        vq[p] += wq[k][p] & kValueMask;
+                        if ((wq[k][p] >> 62) == 2 || jj == 0) done |= 1u << (PX + p);
+                    }
+                }
+                ++consumed;
+            }
+            if (__all(done == kAll)) break;
+            j -= consumed;
+            if (stalled) {
+                if (++spins > kSpinLimit) {
+                    atomicOr(fault, 1u);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+        }
+#pragma unroll
+        for (int p = 0; p < PX; ++p) {
+            store_state(mine + soff(p), kStPrefix | (v[p] + a[p]));
+            if (SQ) store_state(mine_q + soff(p), kStPrefix | (vq[p] + aq[p]));
+        }
+    }
+
     // One table's rows of the block for this wave; returns the row totals (lane r holds row r's)
     // to add to the left carries.  Per row and sub-block: the lane's pixel pair, a DPP scan of
     // pair sums across the wave, then one 16-byte store per lane (contiguous across the wave).
@@ -348,7 +445,7 @@ struct Build {
     //   ragged: one resource per row covering exactly [block start, W) of that row, 8-byte
     //     stores.
     template <typename ST, bool SQUARE, bool VEC>
-    static __device__ __forceinline__ uint64_t rows_pass(const Smem &sm, int wave, int lane, const uint64_t (&u)[PX],
+    static __device__ __forceinline__ uint64_t rows_pass(const Smem &sm, int row0, int lane, const uint64_t (&u)[PX],
                                                          uint64_t lcarry, uint64_t *blk0, int rows_ok,
                                                          uint32_t row_recs, uint32_t pitch_bytes) {
         uint64_t acc[PX];
@@ -362,9 +459,9 @@ struct Build {
         const char *rowp = reinterpret_cast<const char *>(blk0);
         uint32_t roff = 0;
 #pragma unroll 1
-        for (int r = 0; r < RW; ++r) {
+        for (int r = 0; r < rows_ok; ++r) {
             uint32_t raw[NS];
-            tile_px(sm, wave * RW + r, lane, raw);
+            tile_px(sm, row0 + r, lane, raw);
             uint64_t base = readlane(lcarry, r);      // row total left of this sub-block
             const __amdgpu_buffer_rsrc_t rs_row = __builtin_amdgcn_make_buffer_rsrc(
                 const_cast<char *>(rowp), 0, (!VEC && r < rows_ok) ? static_cast<int>(row_recs) : 0, kRsrcWord3);
@@ -401,9 +498,12 @@ struct Build {
     static __device__ void strip(const BuildDesc &d, int strip_idx, uint64_t *state, unsigned int *fault, Smem &sm) {
         const int lane = threadIdx.x & 63;
         const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
-        const int64_t ys = static_cast<int64_t>(strip_idx) * TH;       // first row of the strip
-        const int64_t yw = ys + wave * RW;                                // first row of this wave
-        const int rows_ok = static_cast<int>(d.H - yw < RW ? d.H - yw : RW);   // may be <= 0
+        const int th = d.strip_h, rw = d.wave_rows;                      // th <= TH, rw <= RW
+        const int64_t ys = static_cast<int64_t>(strip_idx) * th;       // first row of the strip
+        const int nvalid = static_cast<int>(d.H - ys < th ? d.H - ys : th);
+        const int row0 = wave * rw;                                       // first strip row of this wave
+        const int64_t yw = ys + row0;
+        const int rows_ok = nvalid - row0 < rw ? (nvalid - row0 > 0 ? nvalid - row0 : 0) : rw;
         uint64_t *S_w = d.S + yw * d.spitch;
         uint64_t *Q_w = SQ ? d.Q + yw * d.spitch : nullptr;
         const uint32_t pitch_bytes = static_cast<uint32_t>(d.spitch * 8);
@@ -413,11 +513,11 @@ struct Build {
 
         // Stage block 0.
         uint32_t pf[PFW];
-        if (fast_tile(d, ys, 0)) {
-            fetch_any(d, ys, 0, pf);
+        if (fast_tile(d, 0)) {
+            fetch_any(d, ys, 0, nvalid, pf);
             commit_any(d, sm, pf);
         } else {
-            load_tile_slow(d, sm, ys, 0);
+            load_tile_slow(d, sm, ys, 0, nvalid);
         }
         __syncthreads();
 
@@ -432,9 +532,9 @@ struct Build {
 #pragma unroll
                 for (int p = 0; p < PX; ++p) { cs[p] = 0; csq[p] = 0; }
 #pragma unroll 2
-                for (int r = 0; r < RW; ++r) {
+                for (int r = 0; r < rows_ok; ++r) {
                     uint32_t raw[NS];
-                    tile_px(sm, wave * RW + r, lane, raw);
+                    tile_px(sm, row0 + r, lane, raw);
 #pragma unroll
                     for (int p = 0; p < PX; ++p) {
                         const uint32_t v = pix(raw, p);
@@ -449,8 +549,8 @@ struct Build {
                 }
             }
             // Prefetch the next block's tile while this block's lookback and rows run.
-            const bool next_fast = b + 1 < d.nblocks && fast_tile(d, ys, xb + BW);
-            if (next_fast) fetch_any(d, ys, xb + BW, pf);
+            const bool next_fast = b + 1 < d.nblocks && fast_tile(d, xb + BW);
+            if (next_fast) fetch_any(d, ys, xb + BW, nvalid, pf);
             __syncthreads();
 
             if (wave == 0) {
@@ -525,23 +625,336 @@ struct Build {
             const bool vec = d.sat_vec && xb + BW <= d.W;
             const uint32_t row_recs = static_cast<uint32_t>((d.W - xb) * 8);   // bytes from block start to W
             if (vec) {
-                lrow += rows_pass<uint32_t, false, true>(sm, wave, lane, u, lrow, S_w + xb, rows_ok, row_recs, pitch_bytes);
-                if (SQ) lrow_q += rows_pass<QT, true, true>(sm, wave, lane, uq, lrow_q, Q_w + xb, rows_ok, row_recs, pitch_bytes);
+                lrow += rows_pass<uint32_t, false, true>(sm, row0, lane, u, lrow, S_w + xb, rows_ok, row_recs, pitch_bytes);
+                if (SQ) lrow_q += rows_pass<QT, true, true>(sm, row0, lane, uq, lrow_q, Q_w + xb, rows_ok, row_recs, pitch_bytes);
             } else {
-                lrow += rows_pass<uint32_t, false, false>(sm, wave, lane, u, lrow, S_w + xb, rows_ok, row_recs, pitch_bytes);
-                if (SQ) lrow_q += rows_pass<QT, true, false>(sm, wave, lane, uq, lrow_q, Q_w + xb, rows_ok, row_recs, pitch_bytes);
+                lrow += rows_pass<uint32_t, false, false>(sm, row0, lane, u, lrow, S_w + xb, rows_ok, row_recs, pitch_bytes);
+                if (SQ) lrow_q += rows_pass<QT, true, false>(sm, row0, lane, uq, lrow_q, Q_w + xb, rows_ok, row_recs, pitch_bytes);
             }
 
             // Replace the tile with the next block's.
             if (b + 1 < d.nblocks) {
                 __syncthreads();
                 if (next_fast) commit_any(d, sm, pf);
-                else load_tile_slow(d, sm, ys, xb + BW);
+                else load_tile_slow(d, sm, ys, xb + BW, nvalid);
                 __syncthreads();
             }
         }
     }
 };
+
+// ------------------------------------------------------------------ helper-wave strip worker
+//
+// Same arithmetic and lookback protocol as Build, organised around the single in-order vector
+// memory counter of gfx9 (loads and stores retire in issue order, so waiting for a load also waits
+// for every store issued before it).  A workgroup has NW compute waves and one helper wave:
+//   - the helper issues every global load: the next image tile goes straight into a double-
+//     buffered LDS tile (global_load_lds, no VGPRs), then it forms the strip's column sums of that
+//     tile and runs the decoupled lookback for it, one block ahead of the compute waves;
+//   - the compute waves only read LDS, scan and store, so they never wait on memory.
+// One workgroup barrier per block separates "helper prepared block b+1" from "compute waves
+// finished block b".
+template <typename T, bool SQ, int PX, int RW, int NW, int WIN>
+struct Build2 {
+    using B1 = Build<T, SQ, PX, RW, NW, MODE_LOOKBACK>;   // shared helpers (column map, lookback)
+    static constexpr int TH = RW * NW;
+    static constexpr int BW = 64 * PX;
+    static constexpr int NS = PX / 2;
+    static constexpr int NT = (NW + 1) * 64;
+    static constexpr int HELPER = NW;                     // wave index of the helper
+    static constexpr int ROWB = BW * static_cast<int>(sizeof(T));
+    static constexpr int TILEB = TH * ROWB;
+    static_assert(TILEB % 1024 == 0, "tile is a whole number of 1 KiB wave loads");
+    using QT = typename B1::QT;
+
+    struct Smem {
+        uint32_t tile[2][TILEB / 4];                      // image tiles of blocks b and b+1
+        uint32_t cs[2][NW][BW];                           // per compute wave column sums
+        QT csq[SQ ? 2 : 1][SQ ? NW : 1][SQ ? BW : 1];
+        uint64_t v[2][BW];                                // column totals above the strip
+        uint64_t vq[SQ ? 2 : 1][SQ ? BW : 1];
+        long long ticket;
+    };
+
+    // LDS-only workgroup barrier: orders LDS accesses, leaves this wave's global stores in flight.
+    static __device__ __forceinline__ void barrier() {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+        __builtin_amdgcn_s_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+    }
+
+    // Helper wave: bring the tile at columns [xb, xb+BW) of the strip's rows [ys, ys+nvalid) into
+    // LDS buffer `buf`.  Fast path (tile inside the image width, rows 4- or 16-byte aligned): wave
+    // loads of 256 B (a dword per lane) or 1 KiB (dwordx4 per lane) from a buffer resource
+    // straight into LDS.  The resource ends after the last valid row, so rows past the image read
+    // as zero without a branch; the lane part of the address is one VGPR, the chunk part a scalar
+    // offset.  Otherwise element by element, zeros outside the image.
+    template <int VB>
+    static __device__ __forceinline__ void load_tile_dma(const BuildDesc &d, Smem &sm, int buf, int64_t ys, int64_t xb,
+                                                         int nvalid, int lane) {
+        constexpr int CB = 64 * VB;                         // bytes per wave load
+        const unsigned char *base = static_cast<const unsigned char *>(d.img) +
+                                    (ys * d.ipitch + xb) * static_cast<int64_t>(sizeof(T));
+        const uint32_t pitchb = static_cast<uint32_t>(d.ipitch * static_cast<int64_t>(sizeof(T)));
+        const uint32_t recs = static_cast<uint32_t>(nvalid - 1) * pitchb + ROWB;
+        const __amdgpu_buffer_rsrc_t rs =
+            __builtin_amdgcn_make_buffer_rsrc(const_cast<unsigned char *>(base), 0, static_cast<int>(recs), kRsrcWord3);
+        const uint32_t lb = static_cast<uint32_t>(lane) * VB;
+        const uint32_t voff = (lb / ROWB) * pitchb + lb % ROWB;
+#pragma unroll 4
+        for (int c = 0; c < TILEB / CB; ++c) {
+            const uint32_t cb = static_cast<uint32_t>(c) * CB;
+            const uint32_t so = (cb / ROWB) * pitchb + cb % ROWB;
+            auto *dst = (__attribute__((address_space(3))) void *)(sm.tile[buf] + c * (CB / 4));
+            if constexpr (VB == 16)
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, dst, 16, voff, static_cast<int>(so), 0, 0);
+            else
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, dst, 4, voff, static_cast<int>(so), 0, 0);
+        }
+    }
+
+    static __device__ void load_tile(const BuildDesc &d, Smem &sm, int buf, int64_t ys, int64_t xb, int nvalid,
+                                     int lane) {
+        if (d.img_vb >= 4 && xb + BW <= d.W) {
+            if (d.img_vb >= 16) load_tile_dma<16>(d, sm, buf, ys, xb, nvalid, lane);
+            else load_tile_dma<4>(d, sm, buf, ys, xb, nvalid, lane);
+        } else {
+            const T *img = static_cast<const T *>(d.img);
+            T *tile = reinterpret_cast<T *>(sm.tile[buf]);
+#pragma unroll 4
+            for (int e = lane; e < TH * BW; e += 64) {
+                const int row = e / BW, col = e % BW;
+                const int64_t y = ys + row, x = xb + col;
+                tile[e] = (row < nvalid && x < d.W) ? img[y * d.ipitch + x] : static_cast<T>(0);
+            }
+        }
+    }
+
+    // Wait for this wave's outstanding global loads (the tile DMA) and LDS traffic.
+    static __device__ __forceinline__ void wait_loads() { __builtin_amdgcn_s_waitcnt(0x0070); }
+
+    // Helper wave: column sums of tile `buf` per compute wave and for the strip, the lookback for
+    // this block, and the results in LDS buffer `buf` for the compute waves.
+    static __device__ void prepare(const BuildDesc &d, Smem &sm, int buf, int64_t xb, int strip, int nvalid,
+                                   int lane, uint64_t *state, unsigned int *fault) {
+        uint64_t a[PX], aq[PX];
+#pragma unroll
+        for (int p = 0; p < PX; ++p) { a[p] = 0; aq[p] = 0; }
+        const T *tile = reinterpret_cast<const T *>(sm.tile[buf]) + 2 * lane;
+        for (int w = 0; w < NW; ++w) {
+            uint32_t cs[PX];
+            QT csq[PX];
+#pragma unroll
+            for (int p = 0; p < PX; ++p) { cs[p] = 0; csq[p] = 0; }
+            const int r_end = nvalid - w * RW < RW ? nvalid - w * RW : RW;
+#pragma unroll 2
+            for (int r = 0; r < r_end; ++r) {
+                const T *row = tile + (w * RW + r) * BW;
+#pragma unroll
+                for (int sb = 0; sb < NS; ++sb) {
+                    uint32_t pair;
+                    if (sizeof(T) == 1) pair = *reinterpret_cast<const uint16_t *>(row + 128 * sb);
+                    else pair = *reinterpret_cast<const uint32_t *>(row + 128 * sb);
+                    const uint32_t v0 = sizeof(T) == 1 ? (pair & 0xffu) : (pair & 0xffffu);
+                    const uint32_t v1 = sizeof(T) == 1 ? ((pair >> 8) & 0xffu) : (pair >> 16);
+                    cs[2 * sb] += v0;
+                    cs[2 * sb + 1] += v1;
+                    if (SQ) {
+                        csq[2 * sb] += static_cast<QT>(v0) * v0;
+                        csq[2 * sb + 1] += static_cast<QT>(v1) * v1;
+                    }
+                }
+            }
+#pragma unroll
+            for (int p = 0; p < PX; ++p) {
+                sm.cs[buf][w][lane * PX + p] = cs[p];
+                a[p] += cs[p];
+                if (SQ) {
+                    sm.csq[buf][w][lane * PX + p] = csq[p];
+                    aq[p] += csq[p];
+                }
+            }
+        }
+        uint64_t v[PX], vq[PX];
+        if constexpr (WIN > 0) {
+            B1::template lookback_win<WIN>(d, strip, xb, lane, a, aq, v, vq, state, fault);
+        } else {
+            const uint64_t *tot = state + d.state_off + static_cast<int64_t>(strip) * d.Wp + xb + 2 * lane;
+            const uint64_t *tot_q = state + d.state_q_off + static_cast<int64_t>(strip) * d.Wp + xb + 2 * lane;
+#pragma unroll
+            for (int p = 0; p < PX; ++p) {
+                v[p] = tot[B1::soff(p)];
+                vq[p] = SQ ? tot_q[B1::soff(p)] : 0;
+            }
+        }
+#pragma unroll
+        for (int p = 0; p < PX; ++p) {
+            sm.v[buf][lane * PX + p] = v[p];
+            if (SQ) sm.vq[buf][lane * PX + p] = vq[p];
+        }
+    }
+
+    // Compute wave: the rows of block (buf, xb).
+    static __device__ void compute(const BuildDesc &d, const Smem &sm, int buf, int64_t xb, int wave, int lane,
+                                   int rows_ok, uint64_t *S_w, uint64_t *Q_w, uint32_t pitch_bytes,
+                                   uint64_t &lrow, uint64_t &lrow_q, uint64_t &ucarry, uint64_t &ucarry_q) {
+        uint64_t u[PX], uq[PX];
+        {
+            uint64_t c[PX], cq[PX];
+#pragma unroll
+            for (int p = 0; p < PX; ++p) {
+                c[p] = sm.v[buf][lane * PX + p];
+                cq[p] = SQ ? sm.vq[buf][lane * PX + p] : 0;
+            }
+            for (int w = 0; w < wave; ++w)
+#pragma unroll
+                for (int p = 0; p < PX; ++p) {
+                    c[p] += sm.cs[buf][w][lane * PX + p];
+                    if (SQ) cq[p] += sm.csq[buf][w][lane * PX + p];
+                }
+#pragma unroll
+            for (int sb = 0; sb < NS; ++sb) {
+                const uint64_t pair = add64(c[2 * sb], c[2 * sb + 1]);
+                const uint64_t incl = wave_scan(pair);
+                const uint64_t b = ucarry + (incl - pair);
+                u[2 * sb] = b + c[2 * sb];
+                u[2 * sb + 1] = b + pair;
+                ucarry += readlane(incl, 63);
+                if (SQ) {
+                    const uint64_t pair_q = add64(cq[2 * sb], cq[2 * sb + 1]);
+                    const uint64_t incl_q = wave_scan(pair_q);
+                    const uint64_t b_q = ucarry_q + (incl_q - pair_q);
+                    uq[2 * sb] = b_q + cq[2 * sb];
+                    uq[2 * sb + 1] = b_q + pair_q;
+                    ucarry_q += readlane(incl_q, 63);
+                }
+            }
+        }
+        const bool vec = d.sat_vec && xb + BW <= d.W;
+        const uint32_t row_recs = static_cast<uint32_t>((d.W - xb) * 8);
+        const uint32_t *tile = sm.tile[buf];
+        if (vec) {
+            lrow += rows<uint32_t, false, true>(tile, wave, lane, u, lrow, S_w + xb, rows_ok, row_recs, pitch_bytes);
+            if (SQ) lrow_q += rows<QT, true, true>(tile, wave, lane, uq, lrow_q, Q_w + xb, rows_ok, row_recs, pitch_bytes);
+        } else {
+            lrow += rows<uint32_t, false, false>(tile, wave, lane, u, lrow, S_w + xb, rows_ok, row_recs, pitch_bytes);
+            if (SQ) lrow_q += rows<QT, true, false>(tile, wave, lane, uq, lrow_q, Q_w + xb, rows_ok, row_recs, pitch_bytes);
+        }
+    }
+
+    // Rows of one table (same scheme as Build::rows_pass, reading the given LDS tile).
+    template <typename ST, bool SQUARE, bool VEC>
+    static __device__ __forceinline__ uint64_t rows(const uint32_t *tile, int wave, int lane, const uint64_t (&u)[PX],
+                                                    uint64_t lcarry, uint64_t *blk0, int rows_ok, uint32_t row_recs,
+                                                    uint32_t pitch_bytes) {
+        uint64_t acc[PX];
+#pragma unroll
+        for (int p = 0; p < PX; ++p) acc[p] = 0;
+        uint64_t tvec = 0;
+        const uint32_t voff = static_cast<uint32_t>(lane) * 16;
+        const int nvalid = rows_ok > 0 ? rows_ok : 0;
+        const uint32_t blk_recs = nvalid > 0 ? (nvalid - 1) * pitch_bytes + row_recs : 0;
+        const i32x4 rs_blk = make_rsrc(blk0, VEC ? blk_recs : 0);
+        const char *rowp = reinterpret_cast<const char *>(blk0);
+        uint32_t roff = 0;
+        const T *trow = reinterpret_cast<const T *>(tile) + wave * RW * BW + 2 * lane;
+#pragma unroll 1
+        for (int r = 0; r < RW; ++r) {
+            uint64_t base = readlane(lcarry, r);
+            const __amdgpu_buffer_rsrc_t rs_row = __builtin_amdgcn_make_buffer_rsrc(
+                const_cast<char *>(rowp), 0, (!VEC && r < rows_ok) ? static_cast<int>(row_recs) : 0, kRsrcWord3);
+#pragma unroll
+            for (int sb = 0; sb < NS; ++sb) {
+                uint32_t pairv;
+                if (sizeof(T) == 1) pairv = *reinterpret_cast<const uint16_t *>(trow + 128 * sb);
+                else pairv = *reinterpret_cast<const uint32_t *>(trow + 128 * sb);
+                const ST v0 = sizeof(T) == 1 ? (pairv & 0xffu) : (pairv & 0xffffu);
+                const ST v1 = sizeof(T) == 1 ? ((pairv >> 8) & 0xffu) : (pairv >> 16);
+                const ST a0 = SQUARE ? v0 * v0 : v0;
+                const ST a1 = SQUARE ? v1 * v1 : v1;
+                const ST pair = add64(a0, a1);
+                const ST incl = wave_scan(pair);
+                const uint64_t b = base + (incl - pair);
+                acc[2 * sb] += b + a0;
+                acc[2 * sb + 1] += b + pair;
+                const uint64_t o0 = u[2 * sb] + acc[2 * sb], o1 = u[2 * sb + 1] + acc[2 * sb + 1];
+                if (VEC) {
+                    store16_rsrc(u32x4{static_cast<uint32_t>(o0), static_cast<uint32_t>(o0 >> 32),
+                                       static_cast<uint32_t>(o1), static_cast<uint32_t>(o1 >> 32)},
+                                 rs_blk, voff + sb * 1024, roff);
+                } else {
+                    __builtin_amdgcn_raw_buffer_store_b64(u32x2{static_cast<uint32_t>(o0), static_cast<uint32_t>(o0 >> 32)},
+                                                          rs_row, voff + sb * 1024, 0, 0);
+                    __builtin_amdgcn_raw_buffer_store_b64(u32x2{static_cast<uint32_t>(o1), static_cast<uint32_t>(o1 >> 32)},
+                                                          rs_row, voff + sb * 1024 + 8, 0, 0);
+                }
+                base += readlane(incl, 63);
+            }
+            if (lane == r) tvec = base - readlane(lcarry, r);
+            trow += BW;
+            rowp += pitch_bytes;
+            roff += pitch_bytes;
+        }
+        return tvec;
+    }
+
+    static __device__ void strip(const BuildDesc &d, int strip_idx, uint64_t *state, unsigned int *fault, Smem &sm) {
+        const int lane = threadIdx.x & 63;
+        const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+        const bool helper = wave == HELPER;
+        const int64_t ys = static_cast<int64_t>(strip_idx) * TH;
+        const int nvalid = static_cast<int>(d.H - ys < TH ? d.H - ys : TH);
+        const int64_t yw = ys + (helper ? 0 : wave) * RW;
+        const int rows_ok = helper ? 0 : (nvalid - wave * RW < RW ? nvalid - wave * RW : RW);
+        uint64_t *S_w = d.S + yw * d.spitch;
+        uint64_t *Q_w = SQ ? d.Q + yw * d.spitch : nullptr;
+        const uint32_t pitch_bytes = static_cast<uint32_t>(d.spitch * 8);
+        uint64_t lrow = 0, lrow_q = 0, ucarry = 0, ucarry_q = 0;
+
+        if (helper) {
+            load_tile(d, sm, 0, ys, 0, nvalid, lane);
+            wait_loads();
+            prepare(d, sm, 0, 0, strip_idx, nvalid, lane, state, fault);
+        }
+        barrier();
+        if (helper && d.nblocks > 1) load_tile(d, sm, 1, ys, BW, nvalid, lane);
+        for (int b = 0; b < d.nblocks; ++b) {
+            const int buf = b & 1;
+            const int64_t xb = static_cast<int64_t>(b) * BW;
+            if (!helper) {
+                compute(d, sm, buf, xb, wave, lane, rows_ok, S_w, Q_w, pitch_bytes, lrow, lrow_q, ucarry, ucarry_q);
+            } else if (b + 1 < d.nblocks) {
+                wait_loads();
+                prepare(d, sm, buf ^ 1, xb + BW, strip_idx, nvalid, lane, state, fault);
+            }
+            barrier();
+            if (helper && b + 2 < d.nblocks) load_tile(d, sm, buf, ys, xb + 2 * BW, nvalid, lane);
+        }
+    }
+};
+
+template <typename T, bool SQ, int PX, int RW, int NW, int WIN>
+__global__ __launch_bounds__((NW + 1) * 64) void build2_kernel(const BuildDesc *__restrict__ many, int n,
+                                                               long long total_items, uint64_t *state, BuildCtrl *ctrl) {
+    using B = Build2<T, SQ, PX, RW, NW, WIN>;
+    __shared__ typename B::Smem sm;
+    for (;;) {
+        if (threadIdx.x == 0) sm.ticket = static_cast<long long>(atomicAdd(&ctrl->ticket, 1ull));
+        __syncthreads();
+        const long long t = static_cast<long long>(__builtin_amdgcn_readfirstlane(static_cast<int>(sm.ticket))) |
+                            (static_cast<long long>(__builtin_amdgcn_readfirstlane(static_cast<int>(sm.ticket >> 32))) << 32);
+        __syncthreads();
+        if (t >= total_items) return;
+        int lo = 0, hi = n - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (many[mid].first_item <= t) lo = mid;
+            else hi = mid - 1;
+        }
+        const BuildDesc &d = many[lo];
+        B::strip(d, __builtin_amdgcn_readfirstlane(static_cast<int>(t - d.first_item)), state, &ctrl->fault, sm);
+    }
+}
 
 // Persistent strip kernel: each workgroup takes strips (of one image, or of a batch) from the
 // ticket counter until none are left.
@@ -630,15 +1043,29 @@ __global__ __launch_bounds__(256) void colscan_kernel(uint64_t *state, long long
 
 // ------------------------------------------------------------------ variants and launch
 
+// Compiled variants: index, name, pixels per lane, rows per wave, waves, mode, lookback window
+// (helper mode; 0 = column totals precomputed), adaptive strip height.
+#define SAT_BUILD_VARIANTS(X)                                                   \
+    X(0, "lookback_px8_rw16_nw4", 8, 16, 4, MODE_LOOKBACK, 1, 1)                \
+    X(1, "lookback_px4_rw16_nw4", 4, 16, 4, MODE_LOOKBACK, 1, 1)                \
+    X(2, "lookback_px4_rw8_nw4", 4, 8, 4, MODE_LOOKBACK, 1, 1)                  \
+    X(3, "lookback_px4_rw8_nw8", 4, 8, 8, MODE_LOOKBACK, 1, 1)                  \
+    X(4, "reduce_scan_px4_rw16_nw4", 4, 16, 4, MODE_REDUCE_SCAN, 1, 0)          \
+    X(5, "helper_px2_rw16_nw4", 2, 16, 4, MODE_HELPER, 1, 0)                    \
+    X(6, "helper_px4_rw16_nw4", 4, 16, 4, MODE_HELPER, 1, 0)                    \
+    X(7, "helper_reduce_scan_px4_rw16_nw4", 4, 16, 4, MODE_HELPER, 0, 0)
+
 const BuildVariant kVariants[] = {
-    {"lookback_px4_rw16_nw4", 4, 16, 4, MODE_LOOKBACK},
-    {"lookback_px4_rw8_nw4", 4, 8, 4, MODE_LOOKBACK},
-    {"lookback_px4_rw4_nw4", 4, 4, 4, MODE_LOOKBACK},
-    {"lookback_px8_rw16_nw4", 8, 16, 4, MODE_LOOKBACK},
-    {"lookback_px4_rw8_nw8", 4, 8, 8, MODE_LOOKBACK},
-    {"reduce_scan_px4_rw16_nw4", 4, 16, 4, MODE_REDUCE_SCAN},
+#define SAT_X(i, name, px, rw, nw, mode, win, adapt) {name, px, rw, nw, mode},
+    SAT_BUILD_VARIANTS(SAT_X)
+#undef SAT_X
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
+const int kAdaptive[] = {
+#define SAT_X(i, name, px, rw, nw, mode, win, adapt) adapt,
+    SAT_BUILD_VARIANTS(SAT_X)
+#undef SAT_X
+};
 
 int resident_capacity(const void *kernel, int threads) {
     int dev = 0, cus = 0, per_cu = 0;
@@ -649,7 +1076,19 @@ int resident_capacity(const void *kernel, int threads) {
     return cus * per_cu;
 }
 
-template <typename T, bool SQ, int PX, int RW, int NW, int MODE>
+template <typename T, bool SQ, int PX, int RW, int NW, int MODE, int WIN>
+int capacity_typed() {
+    static int cap = 0;   // per instantiation; the library drives one device model
+    if (cap == 0) {
+        if constexpr (MODE == MODE_HELPER)
+            cap = resident_capacity(reinterpret_cast<const void *>(&build2_kernel<T, SQ, PX, RW, NW, WIN>), (NW + 1) * 64);
+        else
+            cap = resident_capacity(reinterpret_cast<const void *>(&build_kernel<T, SQ, PX, RW, NW, MODE>), NW * 64);
+    }
+    return cap;
+}
+
+template <typename T, bool SQ, int PX, int RW, int NW, int MODE, int WIN>
 hipError_t launch_typed(const BuildDesc *descs, int n, const BuildDesc *dev_descs, int64_t total_items,
                         void *workspace, int64_t state_words, hipStream_t stream) {
     BuildCtrl *ctrl = static_cast<BuildCtrl *>(workspace);
@@ -657,7 +1096,8 @@ hipError_t launch_typed(const BuildDesc *descs, int n, const BuildDesc *dev_desc
     BuildDesc *slot = n == 1 ? &ctrl->one : nullptr;
     const BuildDesc *table = n == 1 ? slot : dev_descs;
     constexpr int TH = RW * NW;
-    if (MODE == MODE_LOOKBACK) {
+    constexpr bool kPrepass = MODE == MODE_REDUCE_SCAN || (MODE == MODE_HELPER && WIN == 0);
+    if (!kPrepass) {
         const long long pairs = (state_words + 1) / 2;
         const long long blocks = pairs > 0 ? (pairs + 255) / 256 : 1;
         const unsigned grid = static_cast<unsigned>(blocks < 8192 ? blocks : 8192);
@@ -681,12 +1121,14 @@ hipError_t launch_typed(const BuildDesc *descs, int n, const BuildDesc *dev_desc
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const void *kfn = reinterpret_cast<const void *>(&build_kernel<T, SQ, PX, RW, NW, MODE>);
-    static int cap = 0;   // per instantiation; the library drives one device model
-    if (cap == 0) cap = resident_capacity(kfn, NW * 64);
+    const int cap = capacity_typed<T, SQ, PX, RW, NW, MODE, WIN>();
     const int64_t grid = total_items < cap ? total_items : cap;
-    hipLaunchKernelGGL((build_kernel<T, SQ, PX, RW, NW, MODE>), dim3(static_cast<unsigned>(grid)),
-                       dim3(NW * 64), 0, stream, table, n, static_cast<long long>(total_items), state, ctrl);
+    if constexpr (MODE == MODE_HELPER)
+        hipLaunchKernelGGL((build2_kernel<T, SQ, PX, RW, NW, WIN>), dim3(static_cast<unsigned>(grid)),
+                           dim3((NW + 1) * 64), 0, stream, table, n, static_cast<long long>(total_items), state, ctrl);
+    else
+        hipLaunchKernelGGL((build_kernel<T, SQ, PX, RW, NW, MODE>), dim3(static_cast<unsigned>(grid)),
+                           dim3(NW * 64), 0, stream, table, n, static_cast<long long>(total_items), state, ctrl);
     return hipGetLastError();
 }
 
@@ -694,13 +1136,22 @@ template <typename T, bool SQ>
 hipError_t launch_variant(int v, const BuildDesc *descs, int n, const BuildDesc *dev_descs, int64_t total,
                           void *ws, int64_t words, hipStream_t s) {
     switch (v) {
-        case 0: return launch_typed<T, SQ, 4, 16, 4, MODE_LOOKBACK>(descs, n, dev_descs, total, ws, words, s);
-        case 1: return launch_typed<T, SQ, 4, 8, 4, MODE_LOOKBACK>(descs, n, dev_descs, total, ws, words, s);
-        case 2: return launch_typed<T, SQ, 4, 4, 4, MODE_LOOKBACK>(descs, n, dev_descs, total, ws, words, s);
-        case 3: return launch_typed<T, SQ, 8, 16, 4, MODE_LOOKBACK>(descs, n, dev_descs, total, ws, words, s);
-        case 4: return launch_typed<T, SQ, 4, 8, 8, MODE_LOOKBACK>(descs, n, dev_descs, total, ws, words, s);
-        case 5: return launch_typed<T, SQ, 4, 16, 4, MODE_REDUCE_SCAN>(descs, n, dev_descs, total, ws, words, s);
+#define SAT_X(i, name, px, rw, nw, mode, win, adapt) \
+        case i: return launch_typed<T, SQ, px, rw, nw, mode, win>(descs, n, dev_descs, total, ws, words, s);
+        SAT_BUILD_VARIANTS(SAT_X)
+#undef SAT_X
         default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T, bool SQ>
+int capacity_variant(int v) {
+    switch (v) {
+#define SAT_X(i, name, px, rw, nw, mode, win, adapt) \
+        case i: return capacity_typed<T, SQ, px, rw, nw, mode, win>();
+        SAT_BUILD_VARIANTS(SAT_X)
+#undef SAT_X
+        default: return 1;
     }
 }
 
@@ -708,6 +1159,12 @@ hipError_t launch_variant(int v, const BuildDesc *descs, int n, const BuildDesc 
 
 int build_variant_count() { return kNumVariants; }
 const BuildVariant &build_variant(int v) { return kVariants[v]; }
+int build_variant_adaptive(int v) { return (v >= 0 && v < kNumVariants) ? kAdaptive[v] : 0; }
+
+int build_variant_capacity(int v, int bpp, bool sq) {
+    if (bpp == 1) return sq ? capacity_variant<uint8_t, true>(v) : capacity_variant<uint8_t, false>(v);
+    return sq ? capacity_variant<uint16_t, true>(v) : capacity_variant<uint16_t, false>(v);
+}
 
 hipError_t launch_build(int variant, int bpp, bool sq, const BuildDesc *descs, int n,
                         const BuildDesc *dev_descs, int64_t total_items, void *workspace,

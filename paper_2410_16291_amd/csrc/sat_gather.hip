@@ -40,16 +40,34 @@ __device__ __forceinline__ ItemMap map_item(int64_t item, int64_t oh, int64_t ch
     return m;
 }
 
-__device__ __forceinline__ uint64_t corner_sum(const uint64_t *__restrict__ top,
-                                               const uint64_t *__restrict__ bot, int64_t x0,
-                                               int64_t x1, bool has_top) {
-    uint64_t r = bot[x1];
-    if (x0 > 0) r -= bot[x0 - 1];
-    if (has_top) {
-        r -= top[x1];
-        if (x0 > 0) r += top[x0 - 1];
-    }
-    return r;
+// The four corner values of output l of an output row: bottom-right, bottom-left-outside,
+// top-right-outside, top-left-outside.  Loads are issued for every l (indices clamped into the
+// row) so that all of a thread's loads are in flight before the first use; terms that fall
+// outside the table (row y0-1 < 0 or column x0-1 < 0) are masked to zero afterwards.
+struct Corners {
+    uint64_t b1, b0, t1, t0;
+};
+
+__device__ __forceinline__ Corners load_corners(const uint64_t *__restrict__ top, const uint64_t *__restrict__ bot,
+                                                int64_t l, const GatherDesc &d) {
+    const int64_t lc = l < d.ow ? l : d.ow - 1;
+    const int64_t x0 = lc * d.stride;
+    const int64_t x1 = x0 + d.win_w - 1;
+    const int64_t xm = x0 > 0 ? x0 - 1 : 0;
+    Corners c;
+    c.b1 = bot[x1];
+    c.b0 = bot[xm];
+    c.t1 = top[x1];
+    c.t0 = top[xm];
+    return c;
+}
+
+__device__ __forceinline__ uint64_t corner_sum(const Corners &c, int64_t l, const GatherDesc &d, bool has_top) {
+    const bool has_left = l * d.stride > 0;
+    const uint64_t b0 = has_left ? c.b0 : 0;
+    const uint64_t t1 = has_top ? c.t1 : 0;
+    const uint64_t t0 = (has_top && has_left) ? c.t0 : 0;
+    return c.b1 - t1 - b0 + t0;
 }
 
 template <typename OutT, int V>
@@ -62,14 +80,13 @@ __global__ __launch_bounds__(256) void window_sum_kernel(GatherDesc d, int64_t b
     const uint64_t *top = d.S + (has_top ? y0 - 1 : 0) * d.spitch;
     OutT *out = static_cast<OutT *>(d.out) + m.k * d.opitch;
     const int64_t l0 = m.c * (256 * V) + threadIdx.x;
+    Corners c[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) c[v] = load_corners(top, bot, l0 + v * 256, d);
 #pragma unroll
     for (int v = 0; v < V; ++v) {
         const int64_t l = l0 + v * 256;
-        if (l < d.ow) {
-            const int64_t x0 = l * d.stride;
-            const int64_t x1 = x0 + d.win_w - 1;
-            out[l] = static_cast<OutT>(corner_sum(top, bot, x0, x1, has_top));
-        }
+        if (l < d.ow) out[l] = static_cast<OutT>(corner_sum(c[v], l, d, has_top));
     }
 }
 
@@ -100,13 +117,13 @@ __global__ __launch_bounds__(256) void window_sum_multi_kernel(MultiArgs a, int6
         if (m.k >= d.oh) continue;
         const uint64_t *bot = S + (y0 + d.win_h - 1) * spitch;
         OutT *out = static_cast<OutT *>(d.out) + m.k * d.opitch;
+        Corners c[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) c[v] = load_corners(top, bot, l0 + v * 256, d);
 #pragma unroll
         for (int v = 0; v < V; ++v) {
             const int64_t l = l0 + v * 256;
-            if (l < d.ow) {
-                const int64_t x0 = l * stride;
-                out[l] = static_cast<OutT>(corner_sum(top, bot, x0, x0 + d.win_w - 1, has_top));
-            }
+            if (l < d.ow) out[l] = static_cast<OutT>(corner_sum(c[v], l, d, has_top));
         }
     }
 }
@@ -136,14 +153,18 @@ __device__ __forceinline__ void mean_std_row(const GatherDesc &d, int64_t k, int
     const double dn = static_cast<double>(n);
     uint64_t *sum = static_cast<uint64_t *>(d.out);
     const int64_t l0 = c * (256 * V) + threadIdx.x;
+    Corners cs[V], cq[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        cs[v] = load_corners(topS, botS, l0 + v * 256, d);
+        cq[v] = load_corners(topQ, botQ, l0 + v * 256, d);
+    }
 #pragma unroll
     for (int v = 0; v < V; ++v) {
         const int64_t l = l0 + v * 256;
         if (l < d.ow) {
-            const int64_t x0 = l * d.stride;
-            const int64_t x1 = x0 + d.win_w - 1;
-            const uint64_t s1 = corner_sum(topS, botS, x0, x1, has_top);
-            const uint64_t q1 = corner_sum(topQ, botQ, x0, x1, has_top);
+            const uint64_t s1 = corner_sum(cs[v], l, d, has_top);
+            const uint64_t q1 = corner_sum(cq[v], l, d, has_top);
             // n*q1 - s1*s1 exactly, in 128 bits (non-negative by Cauchy-Schwarz).
             const uint64_t a_lo = n * q1, a_hi = __umul64hi(n, q1);
             const uint64_t b_lo = s1 * s1, b_hi = __umul64hi(s1, s1);

@@ -21,6 +21,8 @@ struct BuildDesc {
     int64_t state_q_off;  // first lookback word of the squared table's state (Q part)
     int64_t first_item;   // first work item (strip) of this image in the batch
     int32_t nstrips, nblocks;
+    int32_t strip_h;      // rows per strip (<= the variant's strip height; chosen to balance rounds)
+    int32_t wave_rows;    // rows per wave: ceil(strip_h / waves)
     int32_t img_vb;       // widest load (16, 8 or 4 bytes) that every image row start allows; 0: none
     int32_t sat_vec;      // 1: table rows allow 16-byte vector stores
 };
@@ -35,7 +37,7 @@ struct BuildCtrl {
 };
 static_assert(sizeof(BuildCtrl) == 256, "control header is 256 bytes");
 
-enum BuildMode { MODE_LOOKBACK = 0, MODE_REDUCE_SCAN = 1 };
+enum BuildMode { MODE_LOOKBACK = 0, MODE_REDUCE_SCAN = 1, MODE_HELPER = 2 };
 
 struct BuildVariant {
     const char *name;
@@ -49,6 +51,10 @@ struct BuildVariant {
 
 int build_variant_count();
 const BuildVariant &build_variant(int v);
+// Workgroups of variant v that can be resident on the current device at once (pixel type, squares).
+int build_variant_capacity(int v, int bpp, bool sq);
+// 1 if variant v accepts a strip height below its maximum (strip_h / wave_rows at run time).
+int build_variant_adaptive(int v);
 
 // Enqueue the whole build (state clear + kernels) of n images sharing pixel type and squared
 // flag.  `dev_descs` is a device copy of `descs` when n > 1 (nullptr when n == 1: the single

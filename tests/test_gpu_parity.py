@@ -232,3 +232,25 @@ def test_batched_build_and_mean_std():
         assert np.array_equal(to_host(s1), sums), i
         assert np.array_equal(to_host(mean), ref_mean), i
         check_std(to_host(std), ref_std)
+
+
+def test_balanced_strip_heights_tall_image():
+    """More strips than resident workgroups: adaptive variants shorten the strips so they fill
+    whole rounds; every variant must stay bit-exact, including a ragged last strip."""
+    rng = np.random.default_rng(14)
+    for dtype, hi in [(np.uint8, 256), (np.uint16, 65536)]:
+        img_np = rng.integers(0, hi, (33001, 523)).astype(dtype)
+        ref_S = oracle.sat(img_np)
+        img = to_device(img_np)
+        names = api.variants(0)
+        try:
+            for v, name in enumerate(names):
+                print("case: tall image", np.dtype(dtype).name, name, flush=True)
+                api.force_variant(0, v)
+                ws = torch.empty(api.build_workspace_bytes(33001, 523, 1 if dtype == np.uint8 else 2, False),
+                                 dtype=torch.uint8, device="cuda:0")
+                S = api.sat_build(img, ws=ws)
+                api.workspace_check(ws)
+                assert np.array_equal(to_host(S), ref_S), name
+        finally:
+            api.force_variant(0, -1)
