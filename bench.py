@@ -1,21 +1,25 @@
 """Throughput of the integral-image hot path on one MI355X.
 
 One step = the whole path over one synthetic full-scale image: build the uint64 integral image of
-a 70000 x 85000 uint8 cell-centroid mask (Thomas cluster process), then the window sums of
-100x100, 250x250 and 500x500 windows at stride 1 from that one table (uint32 outputs).  The
-image, the table and the outputs stay resident in HBM; the timed region contains only the
-kernels.  Prints ONE JSON line.
+a 70000 x 85000 uint8 cell-centroid mask (Thomas cluster process), then the sums of every
+100x100, 250x250 and 500x500 window at stride 1 from that one table (uint32 outputs), all three
+window sizes in one pass over the table.  The image, the table and the outputs stay resident in
+HBM; the timed region contains only the kernels.  Prints ONE JSON line.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--rows H --cols W]
 
 `value` is Gpixels/s of image processed per second of whole-step time.  `roofline` reports the
-dominant kernel's algorithmic bytes over its measured average duration (HIP events on the
-launch stream) against the 8 TB/s HBM peak; `cpu_baseline` times the oracle (serial C, one
-core) on a bounded band of the same image and scales it to the same unit.
+dominant kernel's algorithmic bytes over its average launch duration (HIP events around each
+launch, on the launch stream, inside the timed region) against the 8 TB/s HBM peak, and the HBM
+traffic rocprofv3 counted for that kernel when the committed counter summary was taken from the
+current kernel source.  `cpu_baseline` times the oracle (serial C, one core) on a bounded band of
+the same image and scales it to the same unit.
 """
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -25,6 +29,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 METRIC = "Gpix/s SAT+window sums at 70k×85k, % HBM peak; served p50/p99 latency"
 WINDOWS = (100, 250, 500)
+GATHER_SRC = os.path.join(ROOT, "paper_2410_16291_amd", "csrc", "sat_gather.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "window_sum_multi_70000x85000_traffic.md")
 
 
 def parse():
@@ -35,11 +41,13 @@ def parse():
     ap.add_argument("--rows", type=int, default=70000)
     ap.add_argument("--cols", type=int, default=85000)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-separate", action="store_true",
+                    help="skip the context timing of one window size per call")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the baseline sample")
     ap.add_argument("--json-out", default=None)
     ap.add_argument("--calibrate-copy", action="store_true",
-                    help="run one plain 4 GiB device copy before timing (a known-size kernel for "
-                         "scaling rocprofv3 FETCH_SIZE / WRITE_SIZE counters)")
+                    help="first run plain int64 copies of known size (1 GiB read + 1 GiB written, "
+                         "contiguous and row-strided) for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE")
     return ap.parse_args()
 
 
@@ -48,12 +56,36 @@ def alg_bytes_build(H, W):
     return H * W * (1 + 8)
 
 
-def alg_bytes_window(H, W, h, w, out_bytes=4):
-    """Every table entry the corner lookups touch, read once, plus every output written once."""
-    oh, ow = H - h + 1, W - w + 1
-    rows = min(H, (oh - 1) + (H - (h - 1))) if oh > 1 else (2 if h < H else 1)
-    cols = min(W, (ow - 1) + (W - (w - 1))) if ow > 1 else (2 if w < W else 1)
-    return rows * cols * 8 + oh * ow * out_bytes
+def alg_bytes_windows(H, W, hs, out_bytes=4):
+    """Every table entry the corner lookups of all windows touch, read once, plus every output
+    written once (stride 1, square windows)."""
+    rows = cols = 0
+    for h in hs:
+        oh, ow = H - h + 1, W - h + 1
+        rows = max(rows, min(H, (oh - 1) + (H - (h - 1))) if oh > 1 else (2 if h < H else 1))
+        cols = max(cols, min(W, (ow - 1) + (W - (h - 1))) if ow > 1 else (2 if h < W else 1))
+    return rows * cols * 8 + sum((H - h + 1) * (W - h + 1) * out_bytes for h in hs)
+
+
+def source_digest(path):
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def committed_traffic(H, W):
+    """HBM bytes per launch of the fused gather from the committed counter summary, if that
+    summary was taken from the current kernel source at this size; else None."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    text = open(TRAFFIC_FILE).read()
+    m_src = re.search(r"kernel_source_sha256:\s*([0-9a-f]{64})", text)
+    m_val = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    m_size = re.search(r"workload_rows_cols:\s*(\d+)x(\d+)", text)
+    if not (m_src and m_val and m_size):
+        return None
+    if m_src.group(1) != source_digest(GATHER_SRC) or (int(m_size.group(1)), int(m_size.group(2))) != (H, W):
+        return None
+    return float(m_val.group(1))
 
 
 def cpu_baseline(H, W, seconds_target):
@@ -87,11 +119,25 @@ def cpu_baseline(H, W, seconds_target):
                                                                        "/".join(map(str, WINDOWS)), t2)}
 
 
+def calibrate_copy(torch, dev):
+    """Plain copies of known size for the counter scale: 1 GiB read and 1 GiB written each."""
+    n = 1 << 27
+    a = torch.ones(n, dtype=torch.int64, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)                                   # contiguous: the runtime's copy kernel
+    cols = 1 << 14
+    a2 = torch.ones((n // cols, cols + 16), dtype=torch.int64, device=dev)[:, :cols]
+    b2 = torch.empty((n // cols, cols), dtype=torch.int64, device=dev)
+    b2.copy_(a2)                                 # row-strided: one 8-byte load per lane
+    torch.cuda.synchronize()
+    del a, b, a2, b2
+
+
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(how the path would shard is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the path has no multi-GPU implementation (how it would "
+              "shard is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
@@ -103,6 +149,7 @@ def main():
         sys.exit(1)
     dev = torch.device("cuda:0")
     H, W = args.rows, args.cols
+    wins = [(h, h) for h in WINDOWS]
 
     # --- synthetic input, made resident in HBM before any timing
     ys, xs = synth.thomas_points(H, W, seed=2)
@@ -112,88 +159,88 @@ def main():
     del idx
     S = api.empty_table(H, W, dev)
     ws = torch.empty(api.build_workspace_bytes(H, W, 1, False), dtype=torch.uint8, device=dev)
-    outs = {h: torch.empty(api.out_shape(H, W, h, h, 1), dtype=torch.uint32, device=dev) for h in WINDOWS}
+    outs = [api.empty_out(*api.out_shape(H, W, h, w, 1), torch.uint32, dev) for h, w in wins]
     torch.cuda.synchronize()
-
-    stream = torch.cuda.current_stream(dev)
     if args.calibrate_copy:
-        a = torch.ones(4 << 30, dtype=torch.uint8, device=dev)
-        b = torch.empty_like(a)
-        b.copy_(a)
-        torch.cuda.synchronize()
-        del a, b
+        calibrate_copy(torch, dev)
+    stream = torch.cuda.current_stream(dev)
 
-    def step(events=None):
-        if events is not None:
-            events["build"][0].append(torch.cuda.Event(enable_timing=True))
-            events["build"][0][-1].record(stream)
+    def ev():
+        e = torch.cuda.Event(enable_timing=True)
+        e.record(stream)
+        return e
+
+    def step(marks=None):
+        if marks is not None:
+            marks["build"].append(ev())
         api.sat_build(img, sat=S, ws=ws)
-        if events is not None:
-            events["build"][1].append(torch.cuda.Event(enable_timing=True))
-            events["build"][1][-1].record(stream)
-        for h in WINDOWS:
-            if events is not None:
-                events[h][0].append(torch.cuda.Event(enable_timing=True))
-                events[h][0][-1].record(stream)
-            api.window_sum(S, h, h, 1, pixel_type="u8", out=outs[h])
-            if events is not None:
-                events[h][1].append(torch.cuda.Event(enable_timing=True))
-                events[h][1][-1].record(stream)
+        if marks is not None:
+            marks["build"].append(ev())
+        api.window_sum_multi(S, wins, 1, pixel_type="u8", outs=outs)
+        if marks is not None:
+            marks["gather"].append(ev())
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
     api.workspace_check(ws)
 
-    # --- timed region: exactly K steps, whole-step clock
+    # --- timed region: exactly K steps; events around every launch on the launch stream
+    marks = {"build": [], "gather": []}
     torch.cuda.synchronize()
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
-    t0.record(stream)
+    t0 = ev()
     for _ in range(args.steps):
-        step()
-    t1.record(stream)
+        step(marks)
+    t1 = ev()
     torch.cuda.synchronize()
     total_ms = t0.elapsed_time(t1)
     api.workspace_check(ws)
-
-    # --- per-kernel durations (a second pass with an event around every call)
-    ev = {k: ([], []) for k in ("build",) + WINDOWS}
-    for _ in range(args.steps):
-        step(ev)
-    torch.cuda.synchronize()
-    per = {k: float(np.mean([a.elapsed_time(b) for a, b in zip(*ev[k])])) for k in ev}
+    b = marks["build"]
+    build_ms = float(np.mean([b[2 * i].elapsed_time(b[2 * i + 1]) for i in range(args.steps)]))
+    gather_ms = float(np.mean([b[2 * i + 1].elapsed_time(marks["gather"][i]) for i in range(args.steps)]))
 
     ms_step = total_ms / args.steps
     value = H * W / (ms_step * 1e-3) / 1e9
-    alg = {"build": alg_bytes_build(H, W)}
-    for h in WINDOWS:
-        alg[h] = alg_bytes_window(H, W, h, h)
-    step_bytes = sum(alg.values())
-    kernels = {}
-    for k in per:
-        name = "sat_build" if k == "build" else "window_sum_%dx%d" % (k, k)
-        kernels[name] = {"ms": round(per[k], 4), "alg_GB": round(alg[k] / 1e9, 3),
-                         "GB_s": round(alg[k] / (per[k] * 1e-3) / 1e9, 1),
-                         "frac_hbm_peak": round(alg[k] / (per[k] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    alg = {"sat_build": alg_bytes_build(H, W), "window_sum_multi": alg_bytes_windows(H, W, WINDOWS)}
+    per = {"sat_build": build_ms, "window_sum_multi": gather_ms}
+    kernels = {k: {"ms": round(per[k], 4), "alg_GB": round(alg[k] / 1e9, 3),
+                   "GB_s": round(alg[k] / (per[k] * 1e-3) / 1e9, 1),
+                   "frac_hbm_peak": round(alg[k] / (per[k] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)} for k in per}
     dom = max(per, key=lambda k: per[k])
-    dom_name = "sat_build" if dom == "build" else "window_sum_%dx%d" % (dom, dom)
     achieved = alg[dom] / (per[dom] * 1e-3) / 1e9
+    traffic = committed_traffic(H, W) if dom == "window_sum_multi" else None
+
+    # --- context: the same window sums as one call per window size (not part of the step)
+    separate = None
+    if not args.no_separate:
+        separate = {}
+        for (h, w), o in zip(wins, outs):
+            api.window_sum(S, h, w, 1, pixel_type="u8", out=o)
+            ts = []
+            for _ in range(3):
+                a = ev()
+                api.window_sum(S, h, w, 1, pixel_type="u8", out=o)
+                ts.append((a, ev()))
+            torch.cuda.synchronize()
+            separate["window_sum_%dx%d" % (h, w)] = round(float(np.mean([x.elapsed_time(y) for x, y in ts])), 4)
 
     res = {
         "metric": METRIC, "value": round(value, 3), "unit": "Gpix/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "u64", "data": "synthetic",
         "config": {"workload": "%dx%d uint8 Thomas-cluster centroid mask (parent density 2e-6/px, 200 "
-                               "children, sigma 40 px, seed 2); uint64 integral image; window sums "
-                               "100x100, 250x250, 500x500 at stride 1 from one table, uint32 outputs"
-                               % (H, W), "rows": H, "cols": W, "windows": list(WINDOWS), "stride": 1},
-        "hbm_frac_step": round(step_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-        "step_alg_GB": round(step_bytes / 1e9, 3),
+                               "children, sigma 40 px, seed 2); uint64 integral image; sums of every "
+                               "100x100, 250x250 and 500x500 window at stride 1 from one table in one "
+                               "pass, uint32 outputs" % (H, W), "rows": H, "cols": W,
+                   "windows": list(WINDOWS), "stride": 1},
+        "hbm_frac_step": round(sum(alg.values()) / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "step_alg_GB": round(sum(alg.values()) / 1e9, 3),
         "kernels": kernels,
-        "roofline": {"bound": "hbm", "kernel": dom_name, "achieved": round(achieved, 1),
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None},
+        "separate_window_calls_ms": separate,
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None if traffic is None else round(traffic / 1e9, 3),
+                     "traffic_unit": "GB per launch (HBM reads + writes)"},
     }
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(H, W, args.cpu_seconds)

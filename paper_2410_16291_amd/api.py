@@ -56,6 +56,18 @@ def empty_table(H: int, W: int, device, pitch: Optional[int] = None) -> torch.Te
     return torch.empty((H, pitch), dtype=torch.uint64, device=device)[:, :W]
 
 
+def out_pitch(ow: int, dtype: torch.dtype) -> int:
+    """Row pitch (elements) of outputs allocated here: a whole number of 128-byte lines, so that
+    no two output rows share a cache line (a partly written line costs HBM a read-modify-write)."""
+    per_line = 128 // dtype.itemsize
+    return (ow + per_line - 1) // per_line * per_line
+
+
+def empty_out(oh: int, ow: int, dtype: torch.dtype, device) -> torch.Tensor:
+    """An oh x ow output with the line-aligned row pitch of out_pitch (a view of a wider buffer)."""
+    return torch.empty((oh, out_pitch(ow, dtype)), dtype=dtype, device=device)[:, :ow]
+
+
 def build_workspace_bytes(H: int, W: int, pixel_type: int, squares: bool) -> int:
     n = _lib.load().sat_build_workspace_bytes(H, W, pixel_type, int(squares))
     if n == 0:
@@ -110,8 +122,10 @@ def window_sum(S: torch.Tensor, h: int, w: int, stride: int = 1, pixel_type: str
     oh, ow = out_shape(H, W, h, w, stride)
     if out is None:
         out_dtype = out_dtype or default_out_dtype(h, w, pixel_type)
-        out = torch.empty((oh, ow), dtype=out_dtype, device=S.device)
+        out = empty_out(oh, ow, out_dtype, S.device)
     _require_cuda(out, "out")
+    if tuple(out.shape) != (oh, ow) or out.stride(1) != 1:
+        raise ValueError("out must be %d x %d with unit column stride" % (oh, ow))
     code = {torch.uint32: SAT_U32, torch.uint64: SAT_U64}.get(out.dtype)
     if code is None:
         raise ValueError("out dtype must be uint32 or uint64")
@@ -122,15 +136,28 @@ def window_sum(S: torch.Tensor, h: int, w: int, stride: int = 1, pixel_type: str
 
 def window_sum_multi(S: torch.Tensor, windows: Sequence[Tuple[int, int]], stride: int = 1,
                      pixel_type: str = "u16", out_dtype: Optional[torch.dtype] = None,
+                     outs: Optional[Sequence[torch.Tensor]] = None,
                      stream: Optional[torch.cuda.Stream] = None) -> List[torch.Tensor]:
-    """window_sum for several (h, w) windows in one pass over S."""
+    """window_sum for several (h, w) windows in one pass over S (`outs`: preallocated outputs,
+    one per window, all of one dtype)."""
     _require_cuda(S, "sat")
     H, W = S.shape
     n = len(windows)
-    if out_dtype is None:
-        big = any(default_out_dtype(h, w, pixel_type) == torch.uint64 for h, w in windows)
-        out_dtype = torch.uint64 if big else torch.uint32
-    outs = [torch.empty(out_shape(H, W, h, w, stride), dtype=out_dtype, device=S.device) for h, w in windows]
+    if outs is not None:
+        outs = list(outs)
+        if len(outs) != n:
+            raise ValueError("one output per window")
+        out_dtype = outs[0].dtype
+        for o, (h, w) in zip(outs, windows):
+            _require_cuda(o, "out")
+            if o.dtype != out_dtype or tuple(o.shape) != out_shape(H, W, h, w, stride) or o.stride(1) != 1:
+                raise ValueError("outs must match the windows' output shapes, share one dtype and have unit "
+                                 "column stride")
+    else:
+        if out_dtype is None:
+            big = any(default_out_dtype(h, w, pixel_type) == torch.uint64 for h, w in windows)
+            out_dtype = torch.uint64 if big else torch.uint32
+        outs = [empty_out(*out_shape(H, W, h, w, stride), out_dtype, S.device) for h, w in windows]
     hs = (ctypes.c_int64 * n)(*[h for h, _ in windows])
     ws = (ctypes.c_int64 * n)(*[w for _, w in windows])
     ptrs = (ctypes.c_void_p * n)(*[o.data_ptr() for o in outs])
@@ -150,10 +177,10 @@ def window_mean_std(S: torch.Tensor, Q: torch.Tensor, h: int, w: int, stride: in
         raise ValueError("sat and sat_sq must have the same shape and pitch")
     H, W = S.shape
     oh, ow = out_shape(H, W, h, w, stride)
-    pitch = ow
-    s1 = torch.empty((oh, pitch), dtype=torch.uint64, device=S.device) if with_sum else None
-    mean = torch.empty((oh, pitch), dtype=torch.float64, device=S.device)
-    std = torch.empty((oh, pitch), dtype=torch.float64, device=S.device)
+    s1 = empty_out(oh, ow, torch.uint64, S.device) if with_sum else None
+    mean = empty_out(oh, ow, torch.float64, S.device)
+    std = empty_out(oh, ow, torch.float64, S.device)
+    pitch = mean.stride(0)
     check(_lib.load().window_mean_std(S.data_ptr(), Q.data_ptr(), H, W, S.stride(0), h, w, stride,
                                       s1.data_ptr() if s1 is not None else None, mean.data_ptr(), std.data_ptr(),
                                       pitch, _stream_handle(S.device, stream)))

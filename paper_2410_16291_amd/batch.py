@@ -10,7 +10,7 @@ from typing import List, Optional, Sequence, Tuple
 import torch
 
 from . import _lib
-from .api import _PIXEL, _require_cuda, _stream_handle, empty_table, out_shape, workspace
+from .api import _PIXEL, _require_cuda, _stream_handle, empty_out, empty_table, out_shape, workspace
 from ._lib import check
 
 
@@ -52,9 +52,8 @@ def mean_std_batched(tables: Sequence[Tuple[torch.Tensor, torch.Tensor]], h: int
         _require_cuda(S, "sat")
         _require_cuda(Q, "sat_sq")
         oh, ow = out_shape(S.shape[0], S.shape[1], h, w, stride)
-        s1 = torch.empty((oh, ow), dtype=torch.uint64, device=dev) if with_sum else None
-        outs.append((s1, torch.empty((oh, ow), dtype=torch.float64, device=dev),
-                     torch.empty((oh, ow), dtype=torch.float64, device=dev)))
+        s1 = empty_out(oh, ow, torch.uint64, dev) if with_sum else None
+        outs.append((s1, empty_out(oh, ow, torch.float64, dev), empty_out(oh, ow, torch.float64, dev)))
     from .api import batch_items
     items = batch_items(None, tables, outs)
     lib = _lib.load()

@@ -114,6 +114,13 @@ int device_cus() {
 }
 
 // Tallest strips that still give every compute unit about two strips to work on.
+// Gather variant of a call on this thread: the forced one, else the chain walk with two outputs
+// per thread (it falls back to row pairs by itself where chains do not apply).
+int gather_variant() {
+    const int v = g_force[1];
+    return v >= 0 && v < satk::gather_variant_count() ? v : 0;
+}
+
 int choose_build_variant(int64_t total_rows, int n_images) {
     const int v = g_force[0];
     if (v >= 0) return v;
@@ -249,7 +256,6 @@ satk::GatherDesc gather_desc(const uint64_t *sat, const uint64_t *sat_sq, int64_
     return d;
 }
 
-constexpr int64_t kMeanStdChunk = 512;   // outputs per mean/std work item (256 threads x 2)
 
 }  // namespace
 
@@ -331,9 +337,7 @@ sat_status window_sum(const uint64_t *sat, sat_dtype pixel_type, int64_t H, int6
     if ((st = check_pitch(out_pitch, ow, oh, bytes_of(out_type), who, "output"))) return st;
     if (overlap(span(out, oh, out_pitch, ow, bytes_of(out_type)), span(sat, H, sat_pitch, W, 8)))
         return fail(SAT_ERR_ARG, "%s: out overlaps the table", who);
-    int v = g_force[1];
-    if (v < 0) v = 0;
-    if (v >= satk::gather_variant_count()) return fail(SAT_ERR_ARG, "%s: forced variant out of range", who);
+    const int v = gather_variant();
     satk::GatherDesc d = gather_desc(sat, nullptr, sat_pitch, oh, ow, win_h, win_w, stride, out, nullptr, nullptr,
                                      out_pitch);
     hipError_t e = satk::launch_window_sum(v, d, out_type == SAT_U64, static_cast<hipStream_t>(stream));
@@ -373,7 +377,8 @@ sat_status window_sum_multi(const uint64_t *sat, sat_dtype pixel_type, int64_t H
         d[i] = gather_desc(sat, nullptr, sat_pitch, oh, ow, win_h[i], win_w[i], stride, outs[i], nullptr, nullptr,
                            out_pitch[i]);
     }
-    hipError_t e = satk::launch_window_sum_multi(d, n_windows, out_type == SAT_U64, static_cast<hipStream_t>(stream));
+    hipError_t e = satk::launch_window_sum_multi(gather_variant(), d, n_windows, out_type == SAT_U64,
+                                                 static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, who);
     return ok();
 }
@@ -399,7 +404,10 @@ sat_status window_mean_std(const uint64_t *sat, const uint64_t *sat_sq, int64_t 
     }
     satk::GatherDesc d = gather_desc(sat, sat_sq, sat_pitch, oh, ow, win_h, win_w, stride, sum_out, mean_out,
                                      std_out, out_pitch);
-    hipError_t e = satk::launch_mean_std(&d, 1, nullptr, 0, static_cast<hipStream_t>(stream));
+    const int v = gather_variant();
+    const int64_t items = satk::plan_mean_std(v, &d, 1);
+    if (items > 0xffffffffll) return fail(SAT_ERR_ARG, "%s: too many work items", who);
+    hipError_t e = satk::launch_mean_std(v, &d, 1, nullptr, items, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, who);
     return ok();
 }
@@ -514,7 +522,6 @@ sat_status window_mean_std_batched(const sat_batch_item *items, int32_t n, int64
         return fail(SAT_ERR_WORKSPACE, "%s: workspace of %zu bytes is below the %zu needed", who, workspace_bytes,
                     desc_bytes);
     std::vector<satk::GatherDesc> d(n);
-    int64_t total = 0;
     const Span sw{reinterpret_cast<uintptr_t>(workspace), reinterpret_cast<uintptr_t>(workspace) + workspace_bytes};
     std::vector<Span> outs;
     for (int i = 0; i < n; ++i) {
@@ -538,10 +545,9 @@ sat_status window_mean_std_batched(const sat_batch_item *items, int32_t n, int64
             if (so[a].lo != so[a].hi) outs.push_back(so[a]);
         d[i] = gather_desc(it.sat, it.sat_sq, it.sat_pitch, oh, ow, win_h, win_w, stride, it.sum_out, it.mean_out,
                            it.std_out, it.out_pitch);
-        d[i].chunks = (ow + kMeanStdChunk - 1) / kMeanStdChunk;
-        d[i].first_item = total;
-        total += oh * d[i].chunks;
     }
+    const int v = gather_variant();
+    const int64_t total = satk::plan_mean_std(v, d.data(), n);
     for (int i = 0; i < n; ++i) {
         const Span a = span(items[i].sat, items[i].H, items[i].sat_pitch, items[i].W, 8);
         const Span b = span(items[i].sat_sq, items[i].H, items[i].sat_pitch, items[i].W, 8);
@@ -553,7 +559,7 @@ sat_status window_mean_std_batched(const sat_batch_item *items, int32_t n, int64
     hipError_t e = hipMemcpyAsync(workspace, d.data(), static_cast<size_t>(n) * sizeof(satk::GatherDesc),
                                   hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return hip_fail(e, who);
-    e = satk::launch_mean_std(d.data(), n, static_cast<satk::GatherDesc *>(workspace), total, s);
+    e = satk::launch_mean_std(v, d.data(), n, static_cast<satk::GatherDesc *>(workspace), total, s);
     if (e != hipSuccess) return hip_fail(e, who);
     return ok();
 }

@@ -5,12 +5,22 @@
 // value diagonally above-left (Sec. II-B); one output per window position of the valid region
 // (Sec. II-A, Sec. III-A), four lookups each (the 4(r*c) term of Sec. III-B).
 //
-// The kernels are bound by HBM bandwidth.  A work item is one output row segment of `chunk`
-// consecutive outputs; a thread handles V outputs spaced 256 apart so that every load and store
-// instruction of a wave touches 64 consecutive elements.  Of the two table rows an output row
-// reads, the upper one was the lower one of the output row win_h/stride rows earlier; items are
-// ordered row by row inside column bands so that this reuse distance stays inside the
-// memory-side cache (band width chosen by the host from win_h).
+// The kernels are bound by HBM bandwidth, and what they cost is how often each table row is
+// read.  Two families:
+//
+//   chain gathers (the default): output rows k and k + q of a window of height h share a table
+//     row when q * stride == h -- the row just above output row k + q is the bottom row of
+//     output row k.  For windows of heights h_1..h_n that are all multiples of the stride and
+//     q = gcd(h_i / stride), every row that output rows r, r + q, r + 2q, ... of ANY of the
+//     windows read is one of the rows (r + jq) * stride - 1.  A work item walks one such chain
+//     down a chunk of output columns and reads each of those rows once; per row t and window i
+//     it forms the difference of the window's two corner columns
+//         D_i(t)[l] = T(t, l*stride + w_i - 1) - T(t, l*stride - 1),
+//     and the sum of the window at chain position p is D_i at step p + L_i minus D_i at step
+//     p, L_i = h_i / (q * stride).  The table is read about once per gather, for all windows
+//     together, instead of twice per window.
+//   row-pair gathers: one output row segment per work item, reading its two table rows; used
+//     when a window height is not a multiple of the stride (no two output rows share a row).
 #include "sat_internal.h"
 
 namespace satk {
@@ -140,6 +150,20 @@ __device__ __forceinline__ double u128_to_double(uint64_t hi, uint64_t lo) {
     return ldexp(static_cast<double>(top), 64 - lz);
 }
 
+// Sum, mean and population standard deviation of one window from its exact sums S1, Q1.
+__device__ __forceinline__ void stats_store(const GatherDesc &d, int64_t o, uint64_t s1, uint64_t q1, uint64_t n,
+                                            double dn) {
+    // n*q1 - s1*s1 exactly, in 128 bits (non-negative by Cauchy-Schwarz).
+    const uint64_t a_lo = n * q1, a_hi = __umul64hi(n, q1);
+    const uint64_t b_lo = s1 * s1, b_hi = __umul64hi(s1, s1);
+    const uint64_t num_lo = a_lo - b_lo;
+    const uint64_t num_hi = a_hi - b_hi - (a_lo < b_lo ? 1u : 0u);
+    uint64_t *sum = static_cast<uint64_t *>(d.out);
+    if (sum) __builtin_nontemporal_store(s1, sum + o);
+    __builtin_nontemporal_store(static_cast<double>(s1) / dn, d.mean + o);
+    __builtin_nontemporal_store(sqrt(u128_to_double(num_hi, num_lo)) / dn, d.stdv + o);
+}
+
 template <int V>
 __device__ __forceinline__ void mean_std_row(const GatherDesc &d, int64_t k, int64_t c) {
     const int64_t y0 = k * d.stride;
@@ -151,7 +175,6 @@ __device__ __forceinline__ void mean_std_row(const GatherDesc &d, int64_t k, int
     const uint64_t *topQ = d.Q + (has_top ? y0 - 1 : 0) * d.spitch;
     const uint64_t n = static_cast<uint64_t>(d.win_h) * static_cast<uint64_t>(d.win_w);
     const double dn = static_cast<double>(n);
-    uint64_t *sum = static_cast<uint64_t *>(d.out);
     const int64_t l0 = c * (256 * V) + threadIdx.x;
     Corners cs[V], cq[V];
 #pragma unroll
@@ -163,17 +186,8 @@ __device__ __forceinline__ void mean_std_row(const GatherDesc &d, int64_t k, int
     for (int v = 0; v < V; ++v) {
         const int64_t l = l0 + v * 256;
         if (l < d.ow) {
-            const uint64_t s1 = corner_sum(cs[v], l, d, has_top);
-            const uint64_t q1 = corner_sum(cq[v], l, d, has_top);
-            // n*q1 - s1*s1 exactly, in 128 bits (non-negative by Cauchy-Schwarz).
-            const uint64_t a_lo = n * q1, a_hi = __umul64hi(n, q1);
-            const uint64_t b_lo = s1 * s1, b_hi = __umul64hi(s1, s1);
-            const uint64_t num_lo = a_lo - b_lo;
-            const uint64_t num_hi = a_hi - b_hi - (a_lo < b_lo ? 1u : 0u);
-            const int64_t o = k * d.opitch + l;
-            if (sum) sum[o] = s1;
-            d.mean[o] = static_cast<double>(s1) / dn;
-            d.stdv[o] = sqrt(u128_to_double(num_hi, num_lo)) / dn;
+            stats_store(d, k * d.opitch + l, corner_sum(cs[v], l, d, has_top), corner_sum(cq[v], l, d, has_top), n,
+                        dn);
         }
     }
 }
@@ -199,18 +213,242 @@ __global__ __launch_bounds__(256) void mean_std_kernel(GatherDesc one, const Gat
     mean_std_row<V>(d, k, r - k * d.chunks);
 }
 
+// ------------------------------------------------------------------ chain gathers
+
+constexpr int kChainMaxWin = 4;       // windows per chain launch (more are split into groups)
+constexpr int kRingBytes = 48 << 10;  // LDS ring budget per workgroup
+
+// Work item -> (XCD slice, position): workgroup b is dispatched to XCD b mod 8, so consecutive
+// work items are given to consecutive workgroups of one XCD; neighbouring column chunks, which
+// read overlapping table columns of the same rows at the same time, then share that XCD's L2.
+__device__ __forceinline__ int64_t xcd_item(int64_t per_xcd) {
+    const int64_t b = blockIdx.x;
+    return per_xcd > 0 ? (b & 7) * per_xcd + (b >> 3) : b;
+}
+
+struct ChainWin {
+    void *out;
+    int64_t opitch;
+    int64_t oh, ow;
+    int32_t w;        // window width
+    int32_t L;        // chain steps from a window's top row to its bottom row
+    int32_t ring0;    // first ring slot of this window
+    int32_t pad;
+};
+
+struct ChainArgs {
+    const uint64_t *S;
+    int64_t spitch;
+    int64_t stride;
+    int64_t q, seg, chunks, items, per_xcd;
+    int64_t ow_max;
+    ChainWin win[kChainMaxWin];
+};
+
+// Position of one work item: column chunk c, chain residue r, chain positions [j0, j0 + seg).
+struct ChainItem {
+    int64_t c, r, j0;
+};
+
+__device__ __forceinline__ ChainItem chain_item(int64_t item, int64_t chunks, int64_t q, int64_t seg) {
+    ChainItem it;
+    it.c = item % chunks;
+    const int64_t rs = item / chunks;
+    it.r = rs % q;
+    it.j0 = (rs / q) * seg;
+    return it;
+}
+
+// Last chain position of residue r inside [j0, j0 + seg) with an output row below oh, or -1.
+__device__ __forceinline__ int64_t chain_end(int64_t oh, int64_t r, int64_t q, int64_t j0, int64_t seg) {
+    const int64_t lastk = oh - 1 - r;
+    if (lastk < 0) return -1;
+    const int64_t pm = lastk / q;
+    return pm < j0 + seg - 1 ? pm : j0 + seg - 1;
+}
+
+template <int V, int N>
+struct ChainRow {
+    uint64_t left[V];
+    uint64_t right[N][V];
+};
+
+template <typename OutT, int V, int N>
+__global__ __launch_bounds__(256) void chain_sum_kernel(ChainArgs a) {
+    extern __shared__ __align__(16) unsigned char ring_raw[];   // N > 1: sum(L_i) slots x V x 256 OutT
+    OutT *ring = reinterpret_cast<OutT *>(ring_raw);
+    const int64_t item = xcd_item(a.per_xcd);
+    if (item >= a.items) return;
+    const ChainItem it = chain_item(item, a.chunks, a.q, a.seg);
+    int64_t pend[N];
+    int64_t jlast = -1;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        pend[i] = chain_end(a.win[i].oh, it.r, a.q, it.j0, a.seg);
+        if (pend[i] >= it.j0 && pend[i] + a.win[i].L > jlast) jlast = pend[i] + a.win[i].L;
+    }
+    if (jlast < it.j0) return;
+
+    const int tid = threadIdx.x;
+    const int32_t s = static_cast<int32_t>(a.stride);
+    int32_t lx[V], xl[V], xr[N][V];
+    bool has_left[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        lx[v] = static_cast<int32_t>(it.c * (256 * V)) + v * 256 + tid;
+        const int32_t lc = lx[v] < a.ow_max ? lx[v] : static_cast<int32_t>(a.ow_max) - 1;
+        has_left[v] = lc > 0;
+        xl[v] = lc > 0 ? lc * s - 1 : 0;
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            const int32_t li = lx[v] < a.win[i].ow ? lx[v] : static_cast<int32_t>(a.win[i].ow) - 1;
+            xr[i][v] = li * s + a.win[i].w - 1;
+        }
+    }
+    auto load = [&](int64_t j, ChainRow<V, N> &row) {
+        const int64_t t = (it.r + j * a.q) * a.stride - 1;
+        const uint64_t *p = a.S + (t > 0 ? t : 0) * a.spitch;
+#pragma unroll
+        for (int v = 0; v < V; ++v) row.left[v] = p[xl[v]];
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+#pragma unroll
+            for (int v = 0; v < V; ++v) row.right[i][v] = p[xr[i][v]];
+    };
+
+    ChainRow<V, N> cur, nxt;
+    OutT prev[V];
+    int slot[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) slot[i] = 0;
+    load(it.j0, cur);
+#pragma unroll 1
+    for (int64_t j = it.j0; j <= jlast; ++j) {
+        if (j < jlast) load(j + 1, nxt);
+        const bool row_ok = it.r + j * a.q > 0;     // row (r + jq) * stride - 1 exists
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            const ChainWin &cw = a.win[i];
+            OutT D[V];
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                const uint64_t lv = has_left[v] ? cur.left[v] : 0;
+                D[v] = row_ok ? static_cast<OutT>(cur.right[i][v] - lv) : OutT(0);
+            }
+            const int64_t p = j - cw.L;
+            OutT *rs = N > 1 ? ring + static_cast<int64_t>(cw.ring0 + slot[i]) * (V * 256) : nullptr;
+            if (p >= it.j0 && p <= pend[i]) {
+                OutT *o = static_cast<OutT *>(cw.out) + (it.r + p * a.q) * cw.opitch;
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    const OutT top = N > 1 ? rs[v * 256 + tid] : prev[v];
+                    if (lx[v] < cw.ow) __builtin_nontemporal_store(static_cast<OutT>(D[v] - top), o + lx[v]);
+                }
+            }
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                if (N > 1) rs[v * 256 + tid] = D[v];
+                else prev[v] = D[v];
+            }
+            if (N > 1) slot[i] = slot[i] + 1 == cw.L ? 0 : slot[i] + 1;
+        }
+        cur = nxt;
+    }
+}
+
+// Mean and standard deviation (single image, or a batch through a descriptor table) by chain
+// walks over both tables: one read of each table row of S and Q per gather.
+template <int V>
+__global__ __launch_bounds__(256) void chain_stats_kernel(GatherDesc one, const GatherDesc *__restrict__ many,
+                                                          int n, int64_t total, int64_t per_xcd) {
+    int64_t item = xcd_item(per_xcd);
+    if (item >= total) return;
+    GatherDesc d;
+    if (many == nullptr) {
+        d = one;
+    } else {
+        int lo = 0, hi = n - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (many[mid].first_item <= item) lo = mid;
+            else hi = mid - 1;
+        }
+        d = many[lo];
+        item -= d.first_item;
+    }
+    const ChainItem it = chain_item(item, d.chunks, d.q, d.seg);
+    const int64_t pend = chain_end(d.oh, it.r, d.q, it.j0, d.seg);
+    if (pend < it.j0) return;
+    const int64_t jlast = pend + 1;
+    const int tid = threadIdx.x;
+    const int32_t s = static_cast<int32_t>(d.stride);
+    int32_t lx[V], xl[V], xr[V];
+    bool has_left[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        lx[v] = static_cast<int32_t>(it.c * (256 * V)) + v * 256 + tid;
+        const int32_t lc = lx[v] < d.ow ? lx[v] : static_cast<int32_t>(d.ow) - 1;
+        has_left[v] = lc > 0;
+        xl[v] = lc > 0 ? lc * s - 1 : 0;
+        xr[v] = lc * s + static_cast<int32_t>(d.win_w) - 1;
+    }
+    const uint64_t nn = static_cast<uint64_t>(d.win_h) * static_cast<uint64_t>(d.win_w);
+    const double dn = static_cast<double>(nn);
+    auto load = [&](int64_t j, uint64_t (&rows)[4][V]) {
+        const int64_t t = (it.r + j * d.q) * d.stride - 1;
+        const int64_t off = (t > 0 ? t : 0) * d.spitch;
+        const uint64_t *ps = d.S + off, *pq = d.Q + off;
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            rows[0][v] = ps[xl[v]];
+            rows[1][v] = ps[xr[v]];
+            rows[2][v] = pq[xl[v]];
+            rows[3][v] = pq[xr[v]];
+        }
+    };
+    uint64_t cur[4][V], nxt[4][V], prev_s[V], prev_q[V];
+    load(it.j0, cur);
+#pragma unroll 1
+    for (int64_t j = it.j0; j <= jlast; ++j) {
+        if (j < jlast) load(j + 1, nxt);
+        const bool row_ok = it.r + j * d.q > 0;
+        const int64_t orow = (it.r + (j - 1) * d.q) * d.opitch;
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            const uint64_t ds = row_ok ? cur[1][v] - (has_left[v] ? cur[0][v] : 0) : 0;
+            const uint64_t dq = row_ok ? cur[3][v] - (has_left[v] ? cur[2][v] : 0) : 0;
+            if (j > it.j0 && lx[v] < d.ow) stats_store(d, orow + lx[v], ds - prev_s[v], dq - prev_q[v], nn, dn);
+            prev_s[v] = ds;
+            prev_q[v] = dq;
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int v = 0; v < V; ++v) cur[k][v] = nxt[k][v];
+    }
+}
+
+// ------------------------------------------------------------------ variants and launch
+
+enum GatherKind { G_CHAIN = 0, G_ROWPAIR = 1 };
 struct GatherVariant {
     const char *name;
-    int v;          // outputs per thread
-    int banded;     // 1: column bands sized to the window height; 0: plain row-major
+    int kind;       // GatherKind
+    int v;          // outputs per thread per step
+    int banded;     // row-pair: 1 = column bands sized to the window height; 0 = row-major
 };
 const GatherVariant kGather[] = {
-    {"v4_banded", 4, 1},
-    {"v2_banded", 2, 1},
-    {"v8_banded", 8, 1},
-    {"v4_rowmajor", 4, 0},
+    {"chain_auto", G_CHAIN, 0, 0},     // one output per thread for one window, two when windows share a ring
+    {"chain_v2", G_CHAIN, 2, 0},
+    {"chain_v1", G_CHAIN, 1, 0},
+    {"chain_v4", G_CHAIN, 4, 0},
+    {"rowpair_v4_banded", G_ROWPAIR, 4, 1},
+    {"rowpair_v2_banded", G_ROWPAIR, 2, 1},
+    {"rowpair_v8_banded", G_ROWPAIR, 8, 1},
+    {"rowpair_v4_rowmajor", G_ROWPAIR, 4, 0},
 };
 constexpr int kNumGather = sizeof(kGather) / sizeof(kGather[0]);
+constexpr int kRowPairFallback = 4;
 
 // Column band (in chunks) such that win_h table rows of the band stay within a budget of the
 // memory-side cache: rows * band_columns * 8 B <= budget.
@@ -225,8 +463,110 @@ int64_t band_chunks(const GatherDesc &d, int v, bool banded, int64_t rows_reused
     return band;
 }
 
+int device_cus() {
+    static int cus = 0;
+    if (cus == 0) {
+        int dev = 0, v = 0;
+        cus = (hipGetDevice(&dev) == hipSuccess &&
+               hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+                  ? v
+                  : 256;
+    }
+    return cus;
+}
+
+int64_t gcd64(int64_t a, int64_t b) {
+    while (b) {
+        const int64_t t = a % b;
+        a = b;
+        b = t;
+    }
+    return a;
+}
+
+// Split of a chain gather into work items: `base` = residues x column chunks of the launch, P =
+// chain positions of the longest chain.  Chains are cut into segments only as far as needed for
+// about 32 workgroups per CU, and never below 16 steps per slowest-window lag (a segment re-reads
+// the L rows before its first output).
+int64_t chain_segments(int64_t base, int64_t P, int Lmax) {
+    const int64_t target = 32ll * device_cus();
+    int64_t nseg = (target + base - 1) / base;
+    const int64_t min_seg = 16ll * (Lmax > 1 ? Lmax : 1);
+    int64_t cap = P / min_seg;
+    if (cap < 1) cap = 1;
+    if (nseg > cap) nseg = cap;
+    if (nseg < 1) nseg = 1;
+    return (P + nseg - 1) / nseg;    // segment length
+}
+
+void xcd_grid(int64_t items, int64_t *grid, int64_t *per_xcd) {
+    const int64_t per = (items + 7) / 8;
+    *grid = per * 8;
+    *per_xcd = per;
+}
+
+template <typename OutT, int V, int N>
+hipError_t launch_chain_typed(ChainArgs &a, size_t lds, hipStream_t s) {
+    int64_t grid = 0;
+    xcd_grid(a.items, &grid, &a.per_xcd);
+    hipLaunchKernelGGL((chain_sum_kernel<OutT, V, N>), dim3(static_cast<unsigned>(grid)), dim3(256), lds, s, a);
+    return hipGetLastError();
+}
+
+template <typename OutT, int V>
+hipError_t launch_chain_n(ChainArgs &a, int n, size_t lds, hipStream_t s) {
+    switch (n) {
+        case 1: return launch_chain_typed<OutT, V, 1>(a, 0, s);
+        case 2: return launch_chain_typed<OutT, V, 2>(a, lds, s);
+        case 3: return launch_chain_typed<OutT, V, 3>(a, lds, s);
+        default: return launch_chain_typed<OutT, V, 4>(a, lds, s);
+    }
+}
+
+// Outputs per thread of a chain launch: the variant's, or for the automatic variant one per
+// thread without a lag ring and two with one (measured fastest on 70000 x 85000 tables).
+int chain_v(const GatherVariant &g, int n_windows) { return g.v > 0 ? g.v : (n_windows > 1 ? 2 : 1); }
+
+// One chain launch over windows idx[0..n) of d (all heights multiples of the stride, ring fits).
+hipError_t launch_chain_group(int V, const GatherDesc *d, const int *idx, int n, bool out64, hipStream_t s) {
+    ChainArgs a{};
+    a.S = d[idx[0]].S;
+    a.spitch = d[idx[0]].spitch;
+    a.stride = d[idx[0]].stride;
+    int64_t q = 0, oh_max = 0, ow_max = 0;
+    for (int i = 0; i < n; ++i) q = gcd64(q, d[idx[i]].win_h / a.stride);
+    int slots = 0, Lmax = 1;
+    for (int i = 0; i < n; ++i) {
+        const GatherDesc &g = d[idx[i]];
+        ChainWin &w = a.win[i];
+        w.out = g.out;
+        w.opitch = g.opitch;
+        w.oh = g.oh;
+        w.ow = g.ow;
+        w.w = static_cast<int32_t>(g.win_w);
+        w.L = static_cast<int32_t>(g.win_h / (a.stride * q));
+        w.ring0 = slots;
+        slots += w.L;
+        if (w.L > Lmax) Lmax = w.L;
+        if (g.oh > oh_max) oh_max = g.oh;
+        if (g.ow > ow_max) ow_max = g.ow;
+    }
+    a.q = q;
+    a.ow_max = ow_max;
+    a.chunks = (ow_max + 256 * V - 1) / (256 * V);
+    const int64_t P = (oh_max + q - 1) / q;
+    a.seg = chain_segments(q * a.chunks, P, Lmax);
+    a.items = q * a.chunks * ((P + a.seg - 1) / a.seg);
+    const size_t lds = static_cast<size_t>(slots) * V * 256 * (out64 ? 8 : 4);
+    switch (V) {
+        case 1: return out64 ? launch_chain_n<uint64_t, 1>(a, n, lds, s) : launch_chain_n<uint32_t, 1>(a, n, lds, s);
+        case 4: return out64 ? launch_chain_n<uint64_t, 4>(a, n, lds, s) : launch_chain_n<uint32_t, 4>(a, n, lds, s);
+        default: return out64 ? launch_chain_n<uint64_t, 2>(a, n, lds, s) : launch_chain_n<uint32_t, 2>(a, n, lds, s);
+    }
+}
+
 template <typename OutT>
-hipError_t launch_sum_typed(int v, const GatherDesc &d0, bool banded, hipStream_t s) {
+hipError_t launch_rowpair_typed(int v, const GatherDesc &d0, bool banded, hipStream_t s) {
     GatherDesc d = d0;
     d.chunks = (d.ow + 256 * v - 1) / (256 * v);
     const int64_t band = band_chunks(d, v, banded, d.win_h);
@@ -240,32 +580,22 @@ hipError_t launch_sum_typed(int v, const GatherDesc &d0, bool banded, hipStream_
     return hipGetLastError();
 }
 
-}  // namespace
-
-int gather_variant_count() { return kNumGather; }
-const char *gather_variant_name(int v) { return kGather[v].name; }
-int64_t gather_chunk_outputs(int v) { return 256ll * kGather[v].v; }
-
-hipError_t launch_window_sum(int variant, const GatherDesc &d, bool out64, hipStream_t stream) {
-    const GatherVariant &g = kGather[variant];
-    return out64 ? launch_sum_typed<uint64_t>(g.v, d, g.banded != 0, stream)
-                 : launch_sum_typed<uint32_t>(g.v, d, g.banded != 0, stream);
-}
-
-hipError_t launch_window_sum_multi(const GatherDesc *descs, int n, bool out64, hipStream_t stream) {
+// Row-pair pass over several windows sharing the upper row (any heights).
+hipError_t launch_rowpair_multi(const GatherDesc *descs, const int *idx, int n, bool out64, hipStream_t stream) {
     constexpr int V = 4;
     MultiArgs a{};
     a.n = n;
     a.oh_max = 0;
     int64_t ow_max = 0, h_max = 0;
     for (int i = 0; i < n; ++i) {
-        a.d[i] = descs[i];
-        if (descs[i].oh > a.oh_max) a.oh_max = descs[i].oh;
-        if (descs[i].ow > ow_max) ow_max = descs[i].ow;
-        if (descs[i].win_h > h_max) h_max = descs[i].win_h;
+        const GatherDesc &g = descs[idx[i]];
+        a.d[i] = g;
+        if (g.oh > a.oh_max) a.oh_max = g.oh;
+        if (g.ow > ow_max) ow_max = g.ow;
+        if (g.win_h > h_max) h_max = g.win_h;
     }
     a.chunks = (ow_max + 256 * V - 1) / (256 * V);
-    GatherDesc shape = descs[0];
+    GatherDesc shape = descs[idx[0]];
     shape.chunks = a.chunks;
     const int64_t band = band_chunks(shape, V, true, h_max);
     const dim3 grid(static_cast<unsigned>(a.oh_max * a.chunks));
@@ -274,12 +604,112 @@ hipError_t launch_window_sum_multi(const GatherDesc *descs, int n, bool out64, h
     return hipGetLastError();
 }
 
-hipError_t launch_mean_std(const GatherDesc *descs, int n, const GatherDesc *dev_descs, int64_t total_items,
-                           hipStream_t stream) {
+bool chain_ok(const GatherDesc &d) { return d.win_h % d.stride == 0; }
+
+}  // namespace
+
+int gather_variant_count() { return kNumGather; }
+const char *gather_variant_name(int v) { return kGather[v].name; }
+
+hipError_t launch_window_sum(int variant, const GatherDesc &d, bool out64, hipStream_t stream) {
+    const GatherVariant *g = &kGather[variant];
+    if (g->kind == G_CHAIN && chain_ok(d)) {
+        const int idx = 0;
+        return launch_chain_group(chain_v(*g, 1), &d, &idx, 1, out64, stream);
+    }
+    if (g->kind == G_CHAIN) g = &kGather[kRowPairFallback];
+    return out64 ? launch_rowpair_typed<uint64_t>(g->v, d, g->banded != 0, stream)
+                 : launch_rowpair_typed<uint32_t>(g->v, d, g->banded != 0, stream);
+}
+
+hipError_t launch_window_sum_multi(int variant, const GatherDesc *descs, int n, bool out64, hipStream_t stream) {
+    const GatherVariant &g = kGather[variant];
+    int order[8], nc = 0, rest[8], nr = 0;
+    for (int i = 0; i < n; ++i) {
+        if (g.kind == G_CHAIN && chain_ok(descs[i])) order[nc++] = i;
+        else rest[nr++] = i;
+    }
+    // chain groups: windows by height, greedily while the lag rings fit the LDS budget
+    for (int a = 1; a < nc; ++a)
+        for (int b = a; b > 0 && descs[order[b]].win_h < descs[order[b - 1]].win_h; --b) {
+            const int t = order[b];
+            order[b] = order[b - 1];
+            order[b - 1] = t;
+        }
+    const int64_t slot_bytes = static_cast<int64_t>(chain_v(g, 2)) * 256 * (out64 ? 8 : 4);
+    int i = 0;
+    while (i < nc) {
+        int m = 1;
+        while (i + m < nc && m < kChainMaxWin) {
+            const int64_t s = descs[order[i]].stride;
+            int64_t q = 0;
+            for (int k = 0; k <= m; ++k) q = gcd64(q, descs[order[i + k]].win_h / s);
+            int64_t slots = 0;
+            for (int k = 0; k <= m; ++k) slots += descs[order[i + k]].win_h / (s * q);
+            if (slots * slot_bytes > kRingBytes) break;
+            ++m;
+        }
+        hipError_t e = launch_chain_group(chain_v(g, m), descs, order + i, m, out64, stream);
+        if (e != hipSuccess) return e;
+        i += m;
+    }
+    if (nr > 0) return launch_rowpair_multi(descs, rest, nr, out64, stream);
+    return hipSuccess;
+}
+
+int64_t plan_mean_std(int variant, GatherDesc *descs, int n) {
+    const GatherVariant &g = kGather[variant];
+    const bool chain = g.kind == G_CHAIN && chain_ok(descs[0]);
+    int64_t total = 0;
+    if (!chain) {
+        for (int i = 0; i < n; ++i) {
+            descs[i].chunks = (descs[i].ow + 511) / 512;
+            descs[i].q = 0;
+            descs[i].seg = 0;
+            descs[i].first_item = total;
+            total += descs[i].oh * descs[i].chunks;
+        }
+        return total;
+    }
+    const int V = chain_v(g, 1);
+    const int64_t q = descs[0].win_h / descs[0].stride;
+    int64_t base = 0, P = 0;
+    for (int i = 0; i < n; ++i) {
+        descs[i].chunks = (descs[i].ow + 256 * V - 1) / (256 * V);
+        base += q * descs[i].chunks;
+        const int64_t Pi = (descs[i].oh + q - 1) / q;
+        if (Pi > P) P = Pi;
+    }
+    const int64_t seg = chain_segments(base, P, 1);
+    for (int i = 0; i < n; ++i) {
+        const int64_t Pi = (descs[i].oh + q - 1) / q;
+        descs[i].q = q;
+        descs[i].seg = seg;
+        descs[i].first_item = total;
+        total += q * descs[i].chunks * ((Pi + seg - 1) / seg);
+    }
+    return total;
+}
+
+hipError_t launch_mean_std(int variant, const GatherDesc *descs, int n, const GatherDesc *dev_descs,
+                           int64_t total_items, hipStream_t stream) {
+    const GatherVariant &g = kGather[variant];
+    const bool chain = descs[0].q > 0;
+    if (chain) {
+        int64_t grid = 0, per = 0;
+        xcd_grid(total_items, &grid, &per);
+        const dim3 gr(static_cast<unsigned>(grid));
+        const GatherDesc *many = n == 1 ? nullptr : dev_descs;
+        switch (chain_v(g, 1)) {
+            case 1: hipLaunchKernelGGL((chain_stats_kernel<1>), gr, dim3(256), 0, stream, descs[0], many, n, total_items, per); break;
+            case 4: hipLaunchKernelGGL((chain_stats_kernel<4>), gr, dim3(256), 0, stream, descs[0], many, n, total_items, per); break;
+            default: hipLaunchKernelGGL((chain_stats_kernel<2>), gr, dim3(256), 0, stream, descs[0], many, n, total_items, per); break;
+        }
+        return hipGetLastError();
+    }
     constexpr int V = 2;
     if (n == 1) {
         GatherDesc d = descs[0];
-        d.chunks = (d.ow + 256 * V - 1) / (256 * V);
         const int64_t band = band_chunks(d, V, true, d.win_h);
         hipLaunchKernelGGL((mean_std_kernel<V>), dim3(static_cast<unsigned>(d.oh * d.chunks)), dim3(256), 0,
                            stream, d, nullptr, 1, band);

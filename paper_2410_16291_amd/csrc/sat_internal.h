@@ -77,16 +77,23 @@ struct GatherDesc {
     int64_t opitch;
     int64_t chunks;          // column chunks per output row
     int64_t first_item;      // batched: first work item of this image
+    int64_t q;               // chain gathers: output rows between two reads of one table row
+    int64_t seg;             // chain gathers: chain positions per work item
 };
 
 int gather_variant_count();
 const char *gather_variant_name(int v);
 
+// Window sums of one window (variant: a gather variant; chain variants fall back to the row-pair
+// kernel when the window height is not a multiple of the stride).
 hipError_t launch_window_sum(int variant, const GatherDesc &d, bool out64, hipStream_t stream);
-hipError_t launch_window_sum_multi(const GatherDesc *d, int n, bool out64, hipStream_t stream);
-hipError_t launch_mean_std(const GatherDesc *descs, int n, const GatherDesc *dev_descs,
+// Window sums of n <= 8 windows of one table, sharing table reads where the windows allow.
+hipError_t launch_window_sum_multi(int variant, const GatherDesc *d, int n, bool out64, hipStream_t stream);
+// Mean/std of one image (n == 1, dev_descs == nullptr) or of a batch: `descs` (host) and
+// `dev_descs` (device copy made by the caller after this plans them) hold one descriptor per
+// image; plan_mean_std fills the work split of every descriptor and returns the total items.
+int64_t plan_mean_std(int variant, GatherDesc *descs, int n);
+hipError_t launch_mean_std(int variant, const GatherDesc *descs, int n, const GatherDesc *dev_descs,
                            int64_t total_items, hipStream_t stream);
-
-int64_t gather_chunk_outputs(int variant);   // outputs per work item along a row
 
 }  // namespace satk

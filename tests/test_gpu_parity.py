@@ -194,7 +194,7 @@ def test_lookback_repeated_builds_many_strips():
     img = to_device(img_np)
     ws = torch.empty(api.build_workspace_bytes(4099, 777, 1, False), dtype=torch.uint8, device="cuda:0")
     try:
-        api.force_variant(0, 2)            # 16-row strips: 257 strips
+        api.force_variant(0, api.variants(0).index("lookback_px4_rw8_nw4"))   # 32-row strips: 129 strips
         for it in range(20):
             S = api.sat_build(img, ws=ws)
             api.workspace_check(ws)
@@ -254,3 +254,124 @@ def test_balanced_strip_heights_tall_image():
                 assert np.array_equal(to_host(S), ref_S), name
         finally:
             api.force_variant(0, -1)
+
+
+# ------------------------------------------------------------------ chain gathers
+
+CHAIN_CASES = [(1, 1, 1), (2, 5, 1), (301, 1111, 1), (64, 64, 4), (12, 7, 3), (300, 2, 1), (5, 517, 5),
+               (100, 100, 1), (7, 300, 3)]      # the last: height not a multiple of the stride (row pairs)
+
+
+@pytest.mark.parametrize("out64", [False, True])
+def test_chain_gather_every_variant(out64):
+    rng = np.random.default_rng(15)
+    img_np = rng.integers(0, 65536, (301, 1111)).astype(np.uint16)
+    S = api.sat_build(to_device(img_np))
+    ref_S = oracle.sat(img_np)
+    odt = torch.uint64 if out64 else torch.uint32
+    try:
+        for v, name in enumerate(api.variants(1)):
+            if not name.startswith("chain"):
+                continue
+            api.force_variant(1, v)
+            for (h, w, s) in CHAIN_CASES:
+                if not out64 and h * w * 65535 > 0xFFFFFFFF:
+                    continue
+                print("case: chain", name, h, w, s, "u64" if out64 else "u32", flush=True)
+                out = api.window_sum(S, h, w, s, pixel_type="u16", out_dtype=odt)
+                assert np.array_equal(to_host(out).astype(np.uint64), oracle.window_sum_sat(ref_S, h, w, s)), \
+                    (name, h, w, s)
+    finally:
+        api.force_variant(1, -1)
+
+
+def test_chain_segments_tall_narrow():
+    """Short windows on a tall image: chains are cut into many segments per residue."""
+    rng = np.random.default_rng(16)
+    img_np = rng.integers(0, 256, (20000, 200)).astype(np.uint8)
+    S = api.sat_build(to_device(img_np))
+    ref_S = oracle.sat(img_np)
+    for (h, w, s) in [(3, 2, 1), (1, 200, 1), (10, 10, 2), (40, 3, 4)]:
+        print("case: chain tall", h, w, s, flush=True)
+        out = api.window_sum(S, h, w, s, pixel_type="u8")
+        assert np.array_equal(to_host(out).astype(np.uint64), oracle.window_sum_sat(ref_S, h, w, s)), (h, w, s)
+    wins = [(10, 5), (20, 20), (30, 1)]            # one lattice: q = 10, lags 1, 2, 3
+    outs = api.window_sum_multi(S, wins, 1, pixel_type="u8")
+    for (h, w), o in zip(wins, outs):
+        assert np.array_equal(to_host(o).astype(np.uint64), oracle.window_sum_sat(ref_S, h, w, 1)), (h, w)
+
+
+@pytest.mark.parametrize("out64", [False, True])
+def test_chain_multi_window_groups(out64):
+    rng = np.random.default_rng(17)
+    img_np = (rng.random((1500, 1700)) < 0.02).astype(np.uint8)
+    S = api.sat_build(to_device(img_np))
+    ref_S = oracle.sat(img_np)
+    odt = torch.uint64 if out64 else torch.uint32
+    sets = [
+        ([(100, 100), (250, 250), (500, 500)], 1),                  # one lattice, lags 2, 5, 10
+        ([(6, 4), (9, 5), (15, 2)], 3),                             # q = 1 in stride units
+        ([(97, 5), (101, 7), (103, 9), (107, 3), (109, 11), (113, 13), (127, 2), (131, 1)], 1),  # rings too big
+        ([(100, 100), (7, 300), (250, 31), (12, 12)], 3),           # mixed: chains and row pairs
+        ([(1500, 1700)], 1),                                        # the whole image
+    ]
+    try:
+        for v, name in enumerate(api.variants(1)):
+            if name not in ("chain_v1", "chain_v2", "chain_v4", "rowpair_v4_banded"):
+                continue
+            api.force_variant(1, v)
+            for wins, s in sets:
+                print("case: multi", name, wins, s, flush=True)
+                outs = api.window_sum_multi(S, wins, s, pixel_type="u8", out_dtype=odt)
+                for (h, w), o in zip(wins, outs):
+                    ref = oracle.window_sum_sat(ref_S, h, w, s)
+                    assert np.array_equal(to_host(o).astype(np.uint64), ref), (name, h, w, s)
+    finally:
+        api.force_variant(1, -1)
+
+
+def test_mean_std_chain_and_rowpair():
+    img_np = synth.lognormal_u16(700, 900, seed=18)
+    S, Q = api.sat_build(to_device(img_np), squares=True)
+    ref_S, ref_Q = oracle.sat(img_np, squares=True)
+    try:
+        for v, name in enumerate(api.variants(1)):
+            if name not in ("chain_v1", "chain_v2", "chain_v4", "rowpair_v4_banded"):
+                continue
+            api.force_variant(1, v)
+            for (h, w, s) in [(64, 64, 1), (64, 64, 4), (3, 700, 1), (50, 9, 5), (7, 11, 3), (700, 900, 1)]:
+                print("case: mean/std", name, h, w, s, flush=True)
+                s1, mean, std = api.window_mean_std(S, Q, h, w, s)
+                sums = oracle.window_sum_sat(ref_S, h, w, s)
+                ref_mean, ref_std = oracle.mean_std(sums, oracle.window_sum_sat(ref_Q, h, w, s), h * w)
+                assert np.array_equal(to_host(s1), sums), (name, h, w, s)
+                assert np.array_equal(to_host(mean), ref_mean), (name, h, w, s)
+                check_std(to_host(std), ref_std)
+    finally:
+        api.force_variant(1, -1)
+
+
+def test_batched_mean_std_every_gather_family():
+    from paper_2410_16291_amd import batch
+    imgs_np = synth.uneven_batch(7, lo=64, hi=700, seed=19)
+    imgs = [to_device(i) for i in imgs_np]
+    tables = batch.build_batched(imgs, squares=True)
+    refs = [oracle.sat(i, squares=True) for i in imgs_np]
+    try:
+        for v, name in enumerate(api.variants(1)):
+            if name not in ("chain_v1", "chain_v2", "chain_v4", "rowpair_v4_banded"):
+                continue
+            api.force_variant(1, v)
+            for (h, w, s) in [(64, 64, 4), (30, 20, 7)]:
+                print("case: batched mean/std", name, h, w, s, flush=True)
+                outs = batch.mean_std_batched(tables, h, w, s)
+                torch.cuda.synchronize()
+                for i, (ref_S, ref_Q) in enumerate(refs):
+                    sums = oracle.window_sum_sat(ref_S, h, w, s)
+                    ref_mean, ref_std = oracle.mean_std(sums, oracle.window_sum_sat(ref_Q, h, w, s), h * w)
+                    s1, mean, std = outs[i]
+                    assert np.array_equal(to_host(s1), sums), (name, i)
+                    assert np.array_equal(to_host(mean), ref_mean), (name, i)
+                    check_std(to_host(std), ref_std)
+    finally:
+        api.force_variant(1, -1)
