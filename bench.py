@@ -43,6 +43,11 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-separate", action="store_true",
                     help="skip the context timing of one window size per call")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-image section")
+    ap.add_argument("--batch-images", type=int, default=64)
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving section")
+    ap.add_argument("--serve-seconds", type=float, default=10.0, help="length of the 50 req/s request stream")
+    ap.add_argument("--burst-seconds", type=float, default=3.0, help="length of the 500 req/s burst")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the baseline sample")
     ap.add_argument("--json-out", default=None)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -117,6 +122,78 @@ def cpu_baseline(H, W, seconds_target):
             "sample": "rows 0..%d of the %dx%d image (%.1f Mpx): serial table build + window sums %s "
                       "by corner lookup, uint64, one thread, %.1f s" % (R2 - 1, H, W, R2 * W / 1e6,
                                                                        "/".join(map(str, WINDOWS)), t2)}
+
+
+def batched_section(torch, dev, n_images):
+    """Many uneven images: one batched build + one batched mean/std launch, against the same
+    work as one build and one mean/std call per image, and against the autotuned variants."""
+    from paper_2410_16291_amd import api, autotune, batch, synth
+
+    sizes = synth.uneven_sizes(n_images, 1000, 12000, seed=3)
+    imgs = [synth.lognormal_u16_device(H, W, 3000 + i, dev) for i, (H, W) in enumerate(sizes)]
+    px = sum(H * W for H, W in sizes)
+    h = w = 64
+    stride = 4
+    tables = batch.alloc_tables(imgs, squares=True)
+    outs = batch.alloc_stats(tables, h, w, stride)
+    ws = api.workspace(max(api.build_workspace_bytes(H, W, 2, True) for H, W in sizes), dev)
+    torch.cuda.synchronize()
+
+    def per_image():
+        for img, (S, Q), o in zip(imgs, tables, outs):
+            api.sat_build(img, sat=S, sat_sq=Q, ws=ws)
+            api.window_mean_std(S, Q, h, w, stride, outs=o)
+
+    def batched(build=None, gather=None):
+        batch.build_batched(imgs, True, tables=tables, variant=build)
+        batch.mean_std_batched(tables, h, w, stride, outs=outs, variant=gather)
+
+    t_per = autotune.time_ms(per_image, reps=3)
+    t_bat = autotune.time_ms(batched, reps=3)
+    tuner = autotune.Tuner(path=None, reps=3)
+    t0 = time.perf_counter()
+    choice = tuner.tune_batch(imgs, squares=True, win=(h, w), stride=stride)
+    tune_s = time.perf_counter() - t0
+    t_tuned = autotune.time_ms(lambda: batched(choice["build"], choice["gather"]), reps=3)
+    alg = px * (2 + 16 + 1) + sum(o[1].numel() * 24 for o in outs)   # image, S+Q, rows read, outputs
+    res = {"workload": "%d uint16 log-normal images (mu 6, sigma 1), sides uniform on 1000..12000 (seed 3); "
+                       "tables of pixels and squares; 64x64 windows at stride 4: sum, mean, std" % n_images,
+           "images": n_images, "gpix": round(px / 1e9, 4),
+           "per_image_calls_ms": round(t_per, 3), "per_image_gpix_s": round(px / t_per / 1e6, 2),
+           "batched_ms": round(t_bat, 3), "batched_gpix_s": round(px / t_bat / 1e6, 2),
+           "tuned": {"build": choice["build"], "gather": choice["gather"], "ms": round(t_tuned, 3),
+                     "gpix_s": round(px / t_tuned / 1e6, 2), "tuning_s": round(tune_s, 2)},
+           "speedup_batched_vs_per_image": round(t_per / t_bat, 3),
+           "speedup_tuned_vs_per_image": round(t_per / t_tuned, 3),
+           "tuned_alg_GB_s": round(alg / (t_tuned * 1e-3) / 1e9, 1)}
+    del imgs, tables, outs
+    torch.cuda.synchronize()
+    return res
+
+
+def serving_section(torch, dev, seconds, burst_seconds):
+    """Poisson request streams against resident tables: the nominal 50 req/s mix, and a burst at
+    500 req/s served with 4 slots (continuous batching) and with 1 slot (one request at a time)."""
+    from paper_2410_16291_amd import serve, synth
+
+    def run(rate, duration, slots):
+        reqs = synth.request_stream(rate=rate, duration=duration, seed=4)
+        srv = serve.Server(serve.GpuExecutor(dev, slots), budget_bytes=200e9, slots=slots)
+        rep = srv.run(reqs, idle=lambda: time.sleep(2e-5))
+        torch.cuda.synchronize()
+        del srv
+        torch.cuda.empty_cache()
+        return rep.as_dict()
+
+    run(50.0, 0.5, 4)                     # warm-up: library load, allocator, first launches
+    out = {"workload": "Poisson arrivals; 20% builds of uint8 Thomas-cluster masks with sides uniform on "
+                       "2000..16000, 80% window queries (sides 16..512, strides 1..8, 25% mean/std) on "
+                       "resident tables; 200 GB admission budget; seed 4",
+           "nominal_50_per_s": dict(run(50.0, seconds, 4), rate=50.0, slots=4)}
+    if burst_seconds > 0:
+        out["burst_500_per_s_4_slots"] = dict(run(500.0, burst_seconds, 4), rate=500.0, slots=4)
+        out["burst_500_per_s_1_slot"] = dict(run(500.0, burst_seconds, 1), rate=500.0, slots=1)
+    return out
 
 
 def calibrate_copy(torch, dev):
@@ -242,6 +319,13 @@ def main():
                      "traffic": None if traffic is None else round(traffic / 1e9, 3),
                      "traffic_unit": "GB per launch (HBM reads + writes)"},
     }
+    del img, S, ws, outs
+    torch.cuda.empty_cache()
+    if not args.no_batched:
+        res["batched"] = batched_section(torch, dev, args.batch_images)
+    if not args.no_serve:
+        torch.cuda.empty_cache()
+        res["serving"] = serving_section(torch, dev, args.serve_seconds, args.burst_seconds)
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(H, W, args.cpu_seconds)
     line = json.dumps(res)

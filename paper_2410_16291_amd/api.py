@@ -169,17 +169,28 @@ def window_sum_multi(S: torch.Tensor, windows: Sequence[Tuple[int, int]], stride
 
 
 def window_mean_std(S: torch.Tensor, Q: torch.Tensor, h: int, w: int, stride: int = 1, with_sum: bool = True,
+                    outs: Optional[Tuple[Optional[torch.Tensor], torch.Tensor, torch.Tensor]] = None,
                     stream: Optional[torch.cuda.Stream] = None):
-    """(sum or None, mean, std) of every window from the tables of pixels and squared pixels."""
+    """(sum or None, mean, std) of every window from the tables of pixels and squared pixels
+    (`outs`: preallocated (sum or None, mean, std) sharing one row pitch)."""
     _require_cuda(S, "sat")
     _require_cuda(Q, "sat_sq")
     if Q.shape != S.shape or Q.stride(0) != S.stride(0):
         raise ValueError("sat and sat_sq must have the same shape and pitch")
     H, W = S.shape
     oh, ow = out_shape(H, W, h, w, stride)
-    s1 = empty_out(oh, ow, torch.uint64, S.device) if with_sum else None
-    mean = empty_out(oh, ow, torch.float64, S.device)
-    std = empty_out(oh, ow, torch.float64, S.device)
+    if outs is None:
+        s1 = empty_out(oh, ow, torch.uint64, S.device) if with_sum else None
+        mean = empty_out(oh, ow, torch.float64, S.device)
+        std = empty_out(oh, ow, torch.float64, S.device)
+    else:
+        s1, mean, std = outs
+        for t in ([s1] if s1 is not None else []) + [mean, std]:
+            _require_cuda(t, "out")
+            if tuple(t.shape) != (oh, ow) or t.stride(0) != mean.stride(0):
+                raise ValueError("outputs must be %d x %d and share one row pitch" % (oh, ow))
+        if (s1 is not None and s1.dtype != torch.uint64) or mean.dtype != torch.float64 or std.dtype != torch.float64:
+            raise ValueError("outputs must be uint64 (sum) and float64 (mean, std)")
     pitch = mean.stride(0)
     check(_lib.load().window_mean_std(S.data_ptr(), Q.data_ptr(), H, W, S.stride(0), h, w, stride,
                                       s1.data_ptr() if s1 is not None else None, mean.data_ptr(), std.data_ptr(),

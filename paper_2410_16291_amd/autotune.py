@@ -1,0 +1,148 @@
+"""Kernel-shape selection by measurement: the tile/scan shapes of the table build and the gather.
+
+The library compiles several build variants (pixels per lane, rows per wave, waves per
+workgroup, lookback / reduce-then-scan / helper-wave column scans) and several gather variants
+(chain walks with 1, 2 or 4 outputs per thread, row-pair kernels).  Which one is fastest depends
+on the image sizes, the pixel type, the squared table and the window, so the tuner times every
+candidate on the caller's own work (one warm-up and `reps` timed runs each, HIP events on the
+launch stream), keeps the fastest, and caches the choice per device and shape class in a JSON
+file.  Later calls in the same shape class reuse the cached choice without timing.
+
+    tuner = Tuner()
+    choice = tuner.tune_batch(images, squares=True, win=(64, 64), stride=4)
+    tables = batch.build_batched(images, squares=True, variant=choice["build"])
+    outs = batch.mean_std_batched(tables, 64, 64, 4, variant=choice["gather"])
+"""
+from __future__ import annotations
+
+import contextlib
+import json
+import math
+import os
+from typing import Callable, Dict, Iterable, List, Optional, Sequence, Tuple
+
+import torch
+
+from . import api
+
+DEFAULT_CACHE = os.environ.get("SAT_TUNE_CACHE",
+                               os.path.join(os.path.expanduser("~"), ".cache", "sat_mi355x_tune.json"))
+
+
+def device_key(device) -> str:
+    p = torch.cuda.get_device_properties(device)
+    return "%s|%s|%d" % (p.name, getattr(p, "gcnArchName", ""), p.multi_processor_count)
+
+
+def shape_class(sizes: Iterable[Tuple[int, int]], pixel_bytes: int, squares: bool,
+                win: Optional[Tuple[int, int]] = None, stride: int = 1) -> str:
+    """Images by count and total pixels (powers of two), pixel type, squared table, window."""
+    sizes = list(sizes)
+    px = sum(h * w for h, w in sizes)
+    rows = sum(h for h, _ in sizes)
+    key = "n%d_px2^%d_rows2^%d_b%d_%s" % (1 << max(0, math.ceil(math.log2(len(sizes)))) if sizes else 0,
+                                         round(math.log2(max(px, 1))), round(math.log2(max(rows, 1))),
+                                         pixel_bytes, "sq" if squares else "s")
+    if win is not None:
+        key += "_w%dx%d_s%d" % (win[0], win[1], stride)
+    return key
+
+
+@contextlib.contextmanager
+def forced(kind: int, name: Optional[str]):
+    """Run the body with variant `name` of `kind` (0 build, 1 gather) forced on this thread."""
+    if name is None:
+        yield
+        return
+    names = api.variants(kind)
+    if name not in names:
+        raise ValueError("unknown %s variant %r" % ("build" if kind == 0 else "gather", name))
+    api.force_variant(kind, names.index(name))
+    try:
+        yield
+    finally:
+        api.force_variant(kind, -1)
+
+
+def time_ms(run: Callable[[], None], reps: int = 3, stream: Optional[torch.cuda.Stream] = None) -> float:
+    """Median event time of `run` on the current stream after one untimed run."""
+    s = stream or torch.cuda.current_stream()
+    run()
+    ts = []
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(s)
+        run()
+        b.record(s)
+        b.synchronize()
+        ts.append(a.elapsed_time(b))
+    ts.sort()
+    return ts[len(ts) // 2]
+
+
+class Tuner:
+    """Times candidate variants and remembers the fastest per device and shape class."""
+
+    def __init__(self, path: Optional[str] = DEFAULT_CACHE, reps: int = 3):
+        self.path = path
+        self.reps = reps
+        self.cache: Dict[str, dict] = {}
+        if path and os.path.exists(path):
+            try:
+                with open(path) as f:
+                    self.cache = json.load(f)
+            except (OSError, ValueError):
+                self.cache = {}
+
+    def _save(self) -> None:
+        if not self.path:
+            return
+        os.makedirs(os.path.dirname(self.path) or ".", exist_ok=True)
+        tmp = self.path + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(self.cache, f, indent=1, sort_keys=True)
+        os.replace(tmp, self.path)
+
+    def lookup(self, kind: int, key: str) -> Optional[str]:
+        entry = self.cache.get("%d|%s" % (kind, key))
+        return entry["best"] if entry else None
+
+    def tune(self, kind: int, key: str, run: Callable[[], None], candidates: Optional[Sequence[str]] = None,
+             retune: bool = False) -> Tuple[str, Dict[str, float]]:
+        """Fastest of `candidates` (default: every compiled variant of `kind`) for `run`."""
+        ck = "%d|%s" % (kind, key)
+        if not retune and ck in self.cache:
+            return self.cache[ck]["best"], self.cache[ck]["ms"]
+        names = list(candidates) if candidates is not None else api.variants(kind)
+        times = {}
+        for name in names:
+            with forced(kind, name):
+                times[name] = round(time_ms(run, self.reps), 4)
+        best = min(times, key=times.get)
+        self.cache[ck] = {"best": best, "ms": times}
+        self._save()
+        return best, times
+
+    def tune_batch(self, images: Sequence[torch.Tensor], squares: bool, win: Tuple[int, int], stride: int,
+                   retune: bool = False) -> dict:
+        """Build and mean/std (or sum) variants for this batch, timed on the batch itself."""
+        from . import batch
+        dev = images[0].device
+        pb = images[0].element_size()
+        sizes = [tuple(i.shape) for i in images]
+        dkey = device_key(dev)
+        bkey = dkey + "|" + shape_class(sizes, pb, squares)
+        tables = batch.alloc_tables(images, squares)
+        build, build_ms = self.tune(0, bkey, lambda: batch.build_batched(images, squares, tables=tables),
+                                    retune=retune)
+        gkey = dkey + "|" + shape_class(sizes, pb, squares, win, stride)
+        if squares:
+            outs = batch.alloc_stats(tables, win[0], win[1], stride)
+            run = lambda: batch.mean_std_batched(tables, win[0], win[1], stride, outs=outs)   # noqa: E731
+        else:
+            run = lambda: [api.window_sum(S, win[0], win[1], stride,                          # noqa: E731
+                                          pixel_type="u8" if pb == 1 else "u16") for S, _ in tables]
+        gather, gather_ms = self.tune(1, gkey, run, retune=retune)
+        return {"build": build, "gather": gather, "build_ms": build_ms, "gather_ms": gather_ms,
+                "build_key": bkey, "gather_key": gkey}

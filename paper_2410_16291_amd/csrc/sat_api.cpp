@@ -121,15 +121,16 @@ int gather_variant() {
     return v >= 0 && v < satk::gather_variant_count() ? v : 0;
 }
 
-int choose_build_variant(int64_t total_rows, int n_images) {
+int choose_build_variant(int64_t total_rows, int n_images, int bpp, bool sq) {
     const int v = g_force[0];
     if (v >= 0) return v;
     // Each work item is one strip swept across the full width, so the number of strips is the
-    // parallelism: the widest-block variant once there are two strips per CU, else shorter
-    // strips.
+    // parallelism: 64-row strips once there are two per CU, else 32-row strips.  Eight pixels
+    // per lane only for 8-bit images without the squared table (with 16-bit pixels or squares
+    // that variant holds one wave per SIMD; four pixels per lane is measured faster there).
     const int64_t want = 2ll * device_cus();
     const int64_t strips64 = (total_rows + 63 * n_images) / 64;
-    if (strips64 >= want) return 0;
+    if (strips64 >= want) return (bpp == 1 && !sq) ? 0 : 1;
     return 2;
 }
 
@@ -277,7 +278,7 @@ sat_status window_out_shape(int64_t H, int64_t W, int64_t win_h, int64_t win_w, 
 size_t sat_build_workspace_bytes(int64_t H, int64_t W, sat_dtype pixel_type, int with_sq) {
     if (H < 1 || W < 1 || H > kMaxDim || W > kMaxDim) return 0;
     if (pixel_type != SAT_U8 && pixel_type != SAT_U16) return 0;
-    const int v = choose_build_variant(H, 1);
+    const int v = choose_build_variant(H, 1, bytes_of(pixel_type), with_sq != 0);
     if (v < 0 || v >= satk::build_variant_count()) return 0;
     return sizeof(satk::BuildCtrl) + 8 * static_cast<size_t>(build_state_words(v, H, W, with_sq != 0));
 }
@@ -299,7 +300,7 @@ sat_status sat_build(const void *image, sat_dtype pixel_type, int64_t H, int64_t
     if (overlap(sw, span(image, H, image_pitch, W, bpp)) || overlap(sw, span(sat, H, sat_pitch, W, 8)) ||
         overlap(sw, span(sat_sq, H, sat_pitch, W, 8)))
         return fail(SAT_ERR_ARG, "%s: workspace overlaps an input or output", who);
-    const int v = choose_build_variant(H, 1);
+    const int v = choose_build_variant(H, 1, bpp, sat_sq != nullptr);
     if (v < 0 || v >= satk::build_variant_count()) return fail(SAT_ERR_ARG, "%s: forced variant out of range", who);
     const satk::BuildVariant &var = satk::build_variant(v);
     satk::BuildDesc d{};
@@ -425,7 +426,7 @@ size_t sat_batch_workspace_bytes(const sat_batch_item *items, int32_t n, sat_dty
         if (items[i].H < 1 || items[i].W < 1 || items[i].H > kMaxDim || items[i].W > kMaxDim) return 0;
         rows += items[i].H;
     }
-    const int v = choose_build_variant(rows, n);
+    const int v = choose_build_variant(rows, n, bytes_of(pixel_type), with_sq != 0);
     if (v < 0 || v >= satk::build_variant_count()) return 0;
     const satk::BuildVariant &var = satk::build_variant(v);
     for (int i = 0; i < n; ++i)
@@ -476,7 +477,7 @@ sat_status sat_build_batched(const sat_batch_item *items, int32_t n, sat_dtype p
         outs.push_back(a);
         if (b.lo != b.hi) outs.push_back(b);
     }
-    const int v = choose_build_variant(rows, n);
+    const int v = choose_build_variant(rows, n, bytes_of(pixel_type), with_sq);
     if (v < 0 || v >= satk::build_variant_count()) return fail(SAT_ERR_ARG, "%s: forced variant out of range", who);
     const satk::BuildVariant &var = satk::build_variant(v);
     std::vector<satk::BuildDesc> d(n);

@@ -527,6 +527,11 @@ hipError_t launch_chain_n(ChainArgs &a, int n, size_t lds, hipStream_t s) {
 // thread without a lag ring and two with one (measured fastest on 70000 x 85000 tables).
 int chain_v(const GatherVariant &g, int n_windows) { return g.v > 0 ? g.v : (n_windows > 1 ? 2 : 1); }
 
+// Outputs per thread of a mean/std chain launch: with a stride above one each output reads a
+// fraction of a cache line, and four outputs per thread keep more lines in flight (measured on
+// 64 uneven 16-bit images at stride 4); one at stride 1.
+int stats_v(const GatherVariant &g, int64_t stride) { return g.v > 0 ? g.v : (stride > 1 ? 4 : 1); }
+
 // One chain launch over windows idx[0..n) of d (all heights multiples of the stride, ring fits).
 hipError_t launch_chain_group(int V, const GatherDesc *d, const int *idx, int n, bool out64, hipStream_t s) {
     ChainArgs a{};
@@ -671,7 +676,7 @@ int64_t plan_mean_std(int variant, GatherDesc *descs, int n) {
         }
         return total;
     }
-    const int V = chain_v(g, 1);
+    const int V = stats_v(g, descs[0].stride);
     const int64_t q = descs[0].win_h / descs[0].stride;
     int64_t base = 0, P = 0;
     for (int i = 0; i < n; ++i) {
@@ -700,7 +705,7 @@ hipError_t launch_mean_std(int variant, const GatherDesc *descs, int n, const Ga
         xcd_grid(total_items, &grid, &per);
         const dim3 gr(static_cast<unsigned>(grid));
         const GatherDesc *many = n == 1 ? nullptr : dev_descs;
-        switch (chain_v(g, 1)) {
+        switch (stats_v(g, descs[0].stride)) {
             case 1: hipLaunchKernelGGL((chain_stats_kernel<1>), gr, dim3(256), 0, stream, descs[0], many, n, total_items, per); break;
             case 4: hipLaunchKernelGGL((chain_stats_kernel<4>), gr, dim3(256), 0, stream, descs[0], many, n, total_items, per); break;
             default: hipLaunchKernelGGL((chain_stats_kernel<2>), gr, dim3(256), 0, stream, descs[0], many, n, total_items, per); break;

@@ -123,3 +123,30 @@ def request_stream(rate: float = 50.0, duration: float = 120.0, seed: int = 4,
                                 stride=int(rng.integers(1, stride_hi + 1)),
                                 op="mean_std" if rng.random() < mean_std_frac else "sum"))
     return reqs
+
+
+# ---------------------------------------------------------------- device-side generators
+# Large inputs are drawn on the GPU with torch's seeded Philox generator (same distributions as
+# above, float32 draws; not the same numbers as the numpy streams).  Tests that compare such an
+# input with the oracle copy the generated image to the host first.
+
+def lognormal_u16_device(H: int, W: int, seed: int, device, mu: float = 6.0, sigma: float = 1.0):
+    """Log-normal intensities rounded to nearest and clipped to 0..65535, as a uint16 tensor."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    z = torch.randn((H, W), generator=g, device=device, dtype=torch.float32)
+    v = torch.exp_(z.mul_(sigma).add_(mu)).round_().clamp_(0, 65535).to(torch.int32)
+    del z
+    v -= (v >= 32768).to(torch.int32) * 65536          # two's-complement wrap into int16 range
+    return v.to(torch.int16).view(torch.uint16)
+
+
+def thomas_mask_device(H: int, W: int, seed: int, device, parent_density: float = 2e-6, children: int = 200,
+                       sigma: float = 40.0):
+    """thomas_mask drawn on the host (the same points) and scattered into a device uint8 image."""
+    import torch
+    ys, xs = thomas_points(H, W, parent_density, children, sigma, seed)
+    img = torch.zeros((H, W), dtype=torch.uint8, device=device)
+    img.view(-1)[torch.from_numpy(ys * W + xs).to(device)] = 1
+    return img

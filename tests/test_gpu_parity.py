@@ -375,3 +375,144 @@ def test_batched_mean_std_every_gather_family():
                     check_std(to_host(std), ref_std)
     finally:
         api.force_variant(1, -1)
+
+
+# ------------------------------------------------------------------ autotuned batches
+
+def test_autotuned_batch_matches_oracle(tmp_path):
+    from paper_2410_16291_amd import autotune, batch
+    imgs_np = synth.uneven_batch(5, lo=100, hi=700, seed=20)
+    imgs = [to_device(i) for i in imgs_np]
+    tuner = autotune.Tuner(path=str(tmp_path / "tune.json"), reps=1)
+    choice = tuner.tune_batch(imgs, squares=True, win=(32, 48), stride=2)
+    print("case: autotune choice", choice["build"], choice["gather"], flush=True)
+    assert choice["build"] in api.variants(0) and choice["gather"] in api.variants(1)
+    assert set(choice["build_ms"]) == set(api.variants(0))
+    again = autotune.Tuner(path=str(tmp_path / "tune.json")).tune_batch(imgs, squares=True, win=(32, 48), stride=2)
+    assert again["build"] == choice["build"] and again["gather_ms"] == choice["gather_ms"]    # from the cache
+    tables = batch.build_batched(imgs, True, variant=choice["build"])
+    outs = batch.mean_std_batched(tables, 32, 48, 2, variant=choice["gather"])
+    torch.cuda.synchronize()
+    for i, img_np in enumerate(imgs_np):
+        ref_S, ref_Q = oracle.sat(img_np, squares=True)
+        assert np.array_equal(to_host(tables[i][0]), ref_S), i
+        assert np.array_equal(to_host(tables[i][1]), ref_Q), i
+        sums = oracle.window_sum_sat(ref_S, 32, 48, 2)
+        ref_mean, ref_std = oracle.mean_std(sums, oracle.window_sum_sat(ref_Q, 32, 48, 2), 32 * 48)
+        assert np.array_equal(to_host(outs[i][0]), sums), i
+        assert np.array_equal(to_host(outs[i][1]), ref_mean), i
+        check_std(to_host(outs[i][2]), ref_std)
+
+
+def test_device_generator_through_the_path():
+    """The device-side log-normal generator's image, built and gathered, matches the oracle run
+    on the same image copied to the host."""
+    img = synth.lognormal_u16_device(777, 1033, 21, "cuda:0")
+    img_np = to_host(img)
+    assert img_np.dtype == np.uint16 and 300 < np.median(img_np) < 520
+    S, Q = api.sat_build(img, squares=True)
+    ref_S, ref_Q = oracle.sat(img_np, squares=True)
+    assert np.array_equal(to_host(S), ref_S)
+    s1, mean, std = api.window_mean_std(S, Q, 64, 64, 4)
+    sums = oracle.window_sum_sat(ref_S, 64, 64, 4)
+    ref_mean, ref_std = oracle.mean_std(sums, oracle.window_sum_sat(ref_Q, 64, 64, 4), 64 * 64)
+    assert np.array_equal(to_host(s1), sums)
+    assert np.array_equal(to_host(mean), ref_mean)
+    check_std(to_host(std), ref_std)
+
+
+# ------------------------------------------------------------------ serving
+
+def test_serving_results_same_alone_and_in_mix():
+    """Requests served concurrently (4 streams, evictions under a tight budget) give exactly the
+    results of the same requests run alone, one at a time; some are checked against the oracle."""
+    import time
+    from paper_2410_16291_amd import serve
+    reqs = synth.request_stream(rate=300.0, duration=0.5, seed=22, side_lo=200, side_hi=1200,
+                                win_lo=8, win_hi=120, stride_hi=4)
+    ex = serve.GpuExecutor("cuda:0", slots=4)
+    srv = serve.Server(ex, budget_bytes=40e6, slots=4, keep_results=True)
+    rep = srv.run(reqs, idle=lambda: time.sleep(2e-5))
+    torch.cuda.synchronize()
+    print("case: serving", rep.as_dict(), flush=True)
+    assert rep.n == len(reqs) and rep.max_in_flight > 1 and rep.peak_bytes <= 40e6
+    tables = {}
+    checked = 0
+    for j in srv.done:
+        if j.req.kind != "query":
+            continue
+        iid = serve.image_id(j.req)
+        b = srv.builds[iid]
+        if iid not in tables:
+            tables[iid] = api.sat_build(synth.thomas_mask_device(b.H, b.W, b.image_seed, "cuda:0"))
+        S = tables[iid]
+        h, w = min(j.req.win_h, b.H), min(j.req.win_w, b.W)
+        if j.req.op == "sum":
+            alone = api.window_sum(S, h, w, j.req.stride, pixel_type="u8")
+            assert np.array_equal(to_host(alone), to_host(j.result)), j.idx
+            if checked < 4:
+                ref = oracle.window_sum_direct(synth.thomas_mask(b.H, b.W, seed=b.image_seed), h, w, j.req.stride)
+                assert np.array_equal(to_host(alone).astype(np.uint64), ref), j.idx
+                checked += 1
+        else:
+            got = j.result
+            alone = api.window_mean_std(S, S, h, w, j.req.stride)
+            for a, g in zip(alone, got):
+                assert np.array_equal(to_host(a), to_host(g)), j.idx
+    assert checked > 0
+
+
+# ------------------------------------------------------------------ full size
+
+@pytest.mark.slow
+def test_full_scale_70000x85000_sampled():
+    """The bench workload in the bench's launch configuration (one build, one fused 100/250/500
+    gather), compared on sampled rows with one streamed pass of the oracle, on random windows
+    with direct summation, and by its total; then mean/std of 250x250 windows at full size."""
+    H, W = 70000, 85000
+    dev = torch.device("cuda:0")
+    print("case: full scale 70000x85000, host mask", flush=True)
+    img_np = synth.thomas_mask(H, W, seed=2)
+    img = torch.from_numpy(img_np).to(dev)
+    S = api.empty_table(H, W, dev)
+    ws = torch.empty(api.build_workspace_bytes(H, W, 1, False), dtype=torch.uint8, device=dev)
+    api.sat_build(img, sat=S, ws=ws)
+    api.workspace_check(ws)
+    del img, ws
+    wins = [(100, 100), (250, 250), (500, 500)]
+    outs = [api.empty_out(*api.out_shape(H, W, h, w, 1), torch.uint32, dev) for h, w in wins]
+    api.window_sum_multi(S, wins, 1, pixel_type="u8", outs=outs)
+    torch.cuda.synchronize()
+
+    rng = np.random.default_rng(23)
+    sat_rows = sorted(set([0, 1, 31, 32, 63, 64, 12345, 34999, 35000, H - 1] + list(rng.integers(0, H, 6))))
+    rows = []
+    for h, w in wins:
+        oh = H - h + 1
+        rows.append(sorted(set([0, 1, 49, 50, 51, oh - 1] + list(rng.integers(0, oh, 6)))))
+    print("case: full scale, streamed oracle", flush=True)
+    ref_outs, ref_sat, total = oracle.stream(img_np, wins, 1, rows, sat_rows)
+    assert total == int(img_np.sum(dtype=np.uint64))
+    for r, ref in zip(sat_rows, ref_sat):
+        assert np.array_equal(to_host(S[r]), ref), r
+    assert int(to_host(S[H - 1])[W - 1]) == total
+    for (h, w), o, rr, ref in zip(wins, outs, rows, ref_outs):
+        for r, ref_row in zip(rr, ref):
+            assert np.array_equal(to_host(o[r]).astype(np.uint64), ref_row), (h, r)
+    print("case: full scale, random windows by direct summation", flush=True)
+    for _ in range(300):
+        i = int(rng.integers(0, 3))
+        h, w = wins[i]
+        k, l = int(rng.integers(0, H - h + 1)), int(rng.integers(0, W - w + 1))
+        got = int(to_host(outs[i][k, l:l + 1])[0])
+        assert got == int(img_np[k:k + h, l:l + w].sum(dtype=np.int64)), (h, k, l)
+    del outs
+    torch.cuda.empty_cache()
+
+    print("case: full scale, mean/std 250x250 (0/1 mask: the table serves as its own squares)", flush=True)
+    _, mean, std = api.window_mean_std(S, S, 250, 250, 1, with_sum=False)
+    torch.cuda.synchronize()
+    ref_mean, ref_std = oracle.mean_std(ref_outs[1], ref_outs[1], 250 * 250)
+    for r, m_ref, s_ref in zip(rows[1], ref_mean, ref_std):
+        assert np.array_equal(to_host(mean[r]), m_ref), r
+        check_std(to_host(std[r]), s_ref)

@@ -1,0 +1,157 @@
+"""Scheduling of the serving loop, driven on the CPU by a simulated executor and clock."""
+import math
+
+import pytest
+
+from paper_2410_16291_amd import synth
+from paper_2410_16291_amd.serve import Server, image_id, percentile
+
+
+class Clock:
+    def __init__(self):
+        self.t = 0.0
+
+    def __call__(self):
+        return self.t
+
+    def idle(self):
+        self.t += 2e-4
+
+
+class FakeExecutor:
+    """Builds take 4 ms per Mpx, queries 1 ms per Mpx of table; slots run concurrently."""
+
+    def __init__(self, clock):
+        self.clock = clock
+        self.tables = {}
+        self.log = []            # (event, image id, request index or None)
+        self.waited = 0
+        self.freed = []
+
+    def table_bytes(self, H, W):
+        return H * W * 8
+
+    def build_transient_bytes(self, H, W):
+        return H * W
+
+    def query_transient_bytes(self, req, r):
+        h, w = min(req.win_h, r.H), min(req.win_w, r.W)
+        return ((r.H - h) // req.stride + 1) * ((r.W - w) // req.stride + 1) * 4
+
+    def start_build(self, req, r, slot):
+        end = self.clock() + 4e-3 * req.H * req.W / 1e6
+        r.tables = ("table", image_id(req))
+        self.log.append(("build", image_id(req), self.clock()))
+        return {"end": end, "req": req}
+
+    def finish_build(self, h):
+        pass
+
+    def start_query(self, req, r, slot, after):
+        assert r.tables == ("table", image_id(req)), "query started on a table that is not there"
+        start = self.clock()
+        if after is not None:
+            self.waited += 1
+            start = max(start, after["end"])
+        end = start + 1e-3 * r.H * r.W / 1e6
+        self.log.append(("query", image_id(req), self.clock()))
+        return {"end": end, "req": req, "after": after}
+
+    def is_done(self, h):
+        return self.clock() >= h["end"] - 1e-12
+
+    def finish_query(self, h, keep):
+        req = h["req"]
+        return (image_id(req), req.win_h, req.win_w, req.stride, req.op) if keep else None
+
+    def free(self, r):
+        self.freed.append(r.image_id)
+        r.tables = None
+
+
+def stream(rate=400.0, duration=1.0, seed=5, lo=200, hi=1500):
+    return synth.request_stream(rate=rate, duration=duration, seed=seed, side_lo=lo, side_hi=hi, win_lo=8, win_hi=64)
+
+
+def serve(reqs, budget=200e9, slots=4, keep=False):
+    clock = Clock()
+    ex = FakeExecutor(clock)
+    srv = Server(ex, budget_bytes=budget, slots=slots, keep_results=keep)
+    rep = srv.run(reqs, clock=clock, idle=clock.idle)
+    return srv, ex, rep
+
+
+def test_percentile():
+    assert percentile([3.0, 1.0, 2.0], 0.5) == 2.0
+    assert percentile([1.0, 2.0], 0.99) == pytest.approx(1.99)
+    assert math.isnan(percentile([], 0.5))
+
+
+def test_every_request_completes_with_sane_latency():
+    reqs = stream()
+    srv, ex, rep = serve(reqs, keep=True)
+    assert rep.n == len(reqs)
+    assert sorted(j.idx for j in srv.done) == list(range(len(reqs)))
+    for j in srv.done:
+        assert j.t_done >= j.t_arrival and j.t_admit >= j.t_arrival
+        if j.req.kind == "query":
+            assert j.result[0] == image_id(j.req)
+    lat = rep.latency_ms
+    assert lat["all"]["n"] == len(reqs)
+    assert lat["query"]["p99"] >= lat["query"]["p50"] > 0
+    assert rep.misses == 0 and rep.evictions == 0
+
+
+def test_builds_are_admitted_in_arrival_order():
+    reqs = stream(rate=2000.0, duration=0.3)
+    srv, ex, rep = serve(reqs, budget=40e6, slots=3)
+    admits = sorted((j.t_admit, j.idx) for j in srv.done if j.req.kind == "build")
+    idxs = [i for _, i in admits]
+    assert idxs == sorted(idxs)
+
+
+def test_budget_is_respected_with_evictions_and_rebuilds():
+    reqs = stream(rate=800.0, duration=1.0)
+    budget = 60e6
+    srv, ex, rep = serve(reqs, budget=budget, slots=4)
+    assert rep.n == len(reqs)
+    assert rep.peak_bytes <= budget
+    assert rep.evictions > 0 and rep.misses > 0
+    assert set(ex.freed) <= {image_id(r) for r in reqs if r.kind == "build"}
+
+
+def test_query_overlaps_the_build_of_its_image():
+    reqs = [synth.Request(0.0, "build", image_seed=1000, H=1000, W=1000),
+            synth.Request(0.0, "query", image_seed=0, win_h=10, win_w=10, stride=1)]
+    srv, ex, rep = serve(reqs)
+    assert ex.waited == 1                                  # admitted while the build was in flight
+    b = next(j for j in srv.done if j.req.kind == "build")
+    q = next(j for j in srv.done if j.req.kind == "query")
+    assert q.t_admit <= b.t_done and q.t_done >= b.t_done
+
+
+def test_slots_bound_concurrency():
+    reqs = [synth.Request(0.0, "build", image_seed=1000 + k, H=500, W=500) for k in range(10)]
+    srv, ex, rep = serve(reqs, slots=3)
+    assert rep.max_in_flight == 3
+    srv, ex, rep = serve(reqs, slots=1)
+    assert rep.max_in_flight == 1
+
+
+def test_tight_budget_does_not_deadlock():
+    # room for one table at a time: every query behind another image's build forces an eviction
+    reqs = []
+    for k in range(4):
+        reqs.append(synth.Request(0.001 * k, "build", image_seed=1000 + k, H=1000, W=1000))
+    for k in range(4):
+        reqs.append(synth.Request(0.01 + 0.001 * k, "query", image_seed=3 - k, win_h=5, win_w=5, stride=1))
+    srv, ex, rep = serve(reqs, budget=1000 * 1000 * 8 + 1000 * 1000 + 4 * 1000 * 1000, slots=2)
+    assert rep.n == len(reqs)
+    assert rep.peak_bytes <= 1000 * 1000 * 8 + 1000 * 1000 + 4 * 1000 * 1000
+    assert rep.misses == 2           # images 1 and 0 were evicted; image 3 waits for its own build
+
+
+def test_oversized_image_is_refused():
+    reqs = [synth.Request(0.0, "build", image_seed=1000, H=2000, W=2000)]
+    with pytest.raises(ValueError):
+        serve(reqs, budget=1e6)
