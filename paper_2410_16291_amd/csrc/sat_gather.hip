@@ -26,6 +26,8 @@
 namespace satk {
 namespace {
 
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
 struct ItemMap {
     int64_t k;    // output row
     int64_t c;    // column chunk
@@ -428,6 +430,109 @@ __global__ __launch_bounds__(256) void chain_stats_kernel(GatherDesc one, const 
     }
 }
 
+// Stride-1 chain walk with the row span staged in LDS.  A work item owns kLdsC consecutive
+// outputs; at every chain step its workgroup loads the table row's span of columns
+// [x0 - 1, x0 + kLdsC + w_max - 1) once, keeps it (in the output type: sums mod 2^32 for 32-bit
+// outputs) in a ring of L_max + 1 rows shared by all windows, and forms each output as
+//     (T_j[l + w - 1] - T_{j-L}[l + w - 1]) - (T_j[l - 1] - T_{j-L}[l - 1]),
+// the vertical difference over the window's lag taken at the window's two corner columns.  One
+// chunk reads its span once, so the corner columns reaching past the chunk cost w_max / kLdsC
+// extra instead of a second read by the neighbouring chunk.  Two rows are in flight (the loop is
+// unrolled by two with unconditional, clamped loads) and every output store is issued through a
+// range-checked buffer resource, so the wait counts the compiler derives stay exact.
+constexpr int kLdsBS = 256;
+constexpr int kLdsV = 4;
+constexpr int kLdsC = kLdsBS * kLdsV;
+constexpr int kRsrcWord3 = 0x00020000;   // raw buffer resource, 32-bit data format
+
+template <typename OutT, int N, int NL>
+__global__ __launch_bounds__(kLdsBS) void chain_lds_kernel(ChainArgs a, int32_t span, int32_t nslot) {
+    extern __shared__ __align__(16) unsigned char ring_raw[];
+    OutT *ring = reinterpret_cast<OutT *>(ring_raw);
+    const int64_t item = xcd_item(a.per_xcd);
+    if (item >= a.items) return;
+    const ChainItem it = chain_item(item, a.chunks, a.q, a.seg);
+    int64_t pend[N];
+    int64_t jlast = -1;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        pend[i] = chain_end(a.win[i].oh, it.r, a.q, it.j0, a.seg);
+        if (pend[i] >= it.j0 && pend[i] + a.win[i].L > jlast) jlast = pend[i] + a.win[i].L;
+    }
+    if (jlast < it.j0) return;
+    const int tid = threadIdx.x;
+    const int64_t x0 = it.c * kLdsC;
+    const int64_t W = a.win[0].ow + a.win[0].w - 1;       // table width (stride 1)
+    int32_t colk[NL];
+    bool inside[NL];
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+        const int kk = k * kLdsBS + tid;
+        const int64_t col = x0 - 1 + kk;
+        inside[k] = kk < span && col >= 0 && col < W;
+        colk[k] = static_cast<int32_t>(col < 0 ? 0 : (col > W - 1 ? W - 1 : col));
+    }
+    auto gload = [&](int64_t j, uint64_t (&pre)[NL]) {
+        const int64_t jj = j <= jlast ? j : jlast;
+        const int64_t t = it.r + jj * a.q - 1;
+        const uint64_t *p = a.S + (t > 0 ? t : 0) * a.spitch;
+#pragma unroll
+        for (int k = 0; k < NL; ++k) pre[k] = p[colk[k]];
+    };
+    int slot = static_cast<int>(it.j0 % nslot);
+    auto step = [&](int64_t j, const uint64_t (&pre)[NL]) {
+        __syncthreads();                                   // the slot reused now was last read a step ago
+        const bool rowok = it.r + j * a.q > 0;             // row -1 is all zero
+        OutT *dst = ring + slot * span;
+#pragma unroll
+        for (int k = 0; k < NL; ++k) {
+            const int kk = k * kLdsBS + tid;
+            if (kk < span) dst[kk] = (rowok && inside[k]) ? static_cast<OutT>(pre[k]) : OutT(0);
+        }
+        __syncthreads();
+        const OutT *cur = dst;
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            const ChainWin &cw = a.win[i];
+            const int64_t p = j - cw.L;
+            const bool emit = p >= it.j0 && p <= pend[i];
+            int so = slot - cw.L;
+            so += so < 0 ? nslot : 0;
+            const OutT *old = ring + so * span;
+            const int64_t prow = emit ? p : it.j0;
+            OutT *rowp = static_cast<OutT *>(cw.out) + (it.r + prow * a.q) * cw.opitch + x0;
+            const int64_t remain = cw.ow - x0;
+            const int nrec = emit ? static_cast<int>((remain > 0 ? (remain < kLdsC ? remain : kLdsC) : 0) *
+                                                     static_cast<int64_t>(sizeof(OutT)))
+                                  : 0;
+            const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(rowp, 0, nrec, kRsrcWord3);
+#pragma unroll
+            for (int v = 0; v < kLdsV; ++v) {
+                const int u = v * kLdsBS + tid;
+                const OutT val = static_cast<OutT>((cur[u + cw.w] - old[u + cw.w]) - (cur[u] - old[u]));
+                if constexpr (sizeof(OutT) == 8)
+                    __builtin_amdgcn_raw_buffer_store_b64(u32x2{static_cast<uint32_t>(val),
+                                                                static_cast<uint32_t>(static_cast<uint64_t>(val) >> 32)},
+                                                          rs, u * 8, 0, 2);
+                else
+                    __builtin_amdgcn_raw_buffer_store_b32(static_cast<uint32_t>(val), rs, u * 4, 0, 2);
+            }
+        }
+        slot = slot + 1 == nslot ? 0 : slot + 1;
+    };
+    uint64_t pre0[NL], pre1[NL];
+    gload(it.j0, pre0);
+    gload(it.j0 + 1, pre1);
+#pragma unroll 1
+    for (int64_t j = it.j0; j <= jlast; j += 2) {
+        step(j, pre0);
+        gload(j + 2, pre0);
+        if (j + 1 > jlast) break;
+        step(j + 1, pre1);
+        gload(j + 3, pre1);
+    }
+}
+
 // ------------------------------------------------------------------ variants and launch
 
 enum GatherKind { G_CHAIN = 0, G_ROWPAIR = 1 };
@@ -438,7 +543,7 @@ struct GatherVariant {
     int banded;     // row-pair: 1 = column bands sized to the window height; 0 = row-major
 };
 const GatherVariant kGather[] = {
-    {"chain_auto", G_CHAIN, 0, 0},     // one output per thread for one window, two when windows share a ring
+    {"chain_auto", G_CHAIN, 0, 0},     // LDS-staged where it applies, else the ring of corner differences
     {"chain_v2", G_CHAIN, 2, 0},
     {"chain_v1", G_CHAIN, 1, 0},
     {"chain_v4", G_CHAIN, 4, 0},
@@ -532,8 +637,70 @@ int chain_v(const GatherVariant &g, int n_windows) { return g.v > 0 ? g.v : (n_w
 // 64 uneven 16-bit images at stride 4); one at stride 1.
 int stats_v(const GatherVariant &g, int64_t stride) { return g.v > 0 ? g.v : (stride > 1 ? 4 : 1); }
 
+// LDS-staged chain launches: spans of up to NL * 256 columns are compiled for these NL.
+constexpr int kLdsNL[] = {5, 6, 8, 12};
+constexpr size_t kLdsMaxBytes = 150 << 10;
+
+// Loads per thread, span and LDS bytes of an LDS-staged launch, or false where it does not apply.
+bool lds_plan(int64_t stride, int64_t wmax, int Lmax, bool out64, int *nl, int *span, size_t *lds) {
+    if (stride != 1) return false;
+    const int64_t sp = kLdsC + wmax;
+    const int64_t need = (sp + kLdsBS - 1) / kLdsBS;
+    int pick = 0;
+    for (int c : kLdsNL)
+        if (c >= need) {
+            pick = c;
+            break;
+        }
+    if (pick == 0) return false;
+    const size_t bytes = static_cast<size_t>(Lmax + 1) * static_cast<size_t>(sp) * (out64 ? 8 : 4);
+    if (bytes > kLdsMaxBytes) return false;
+    *nl = pick;
+    *span = static_cast<int>(sp);
+    *lds = bytes;
+    return true;
+}
+
+template <typename OutT, int N, int NL>
+hipError_t launch_lds_typed(ChainArgs &a, int span, int nslot, size_t lds, hipStream_t s) {
+    static bool attr_set = false;      // the maximum is set once per instantiation
+    const void *fn = reinterpret_cast<const void *>(&chain_lds_kernel<OutT, N, NL>);
+    if (!attr_set && lds > (64u << 10)) {
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(kLdsMaxBytes));
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    int64_t grid = 0;
+    xcd_grid(a.items, &grid, &a.per_xcd);
+    hipLaunchKernelGGL((chain_lds_kernel<OutT, N, NL>), dim3(static_cast<unsigned>(grid)), dim3(kLdsBS), lds, s, a,
+                       static_cast<int32_t>(span), static_cast<int32_t>(nslot));
+    return hipGetLastError();
+}
+
+template <typename OutT, int N>
+hipError_t launch_lds_n(ChainArgs &a, int nl, int span, int nslot, size_t lds, hipStream_t s) {
+    switch (nl) {
+        case 5: return launch_lds_typed<OutT, N, 5>(a, span, nslot, lds, s);
+        case 6: return launch_lds_typed<OutT, N, 6>(a, span, nslot, lds, s);
+        case 8: return launch_lds_typed<OutT, N, 8>(a, span, nslot, lds, s);
+        default: return launch_lds_typed<OutT, N, 12>(a, span, nslot, lds, s);
+    }
+}
+
+template <typename OutT>
+hipError_t launch_lds(ChainArgs &a, int n, int nl, int span, int nslot, size_t lds, hipStream_t s) {
+    switch (n) {
+        case 1: return launch_lds_n<OutT, 1>(a, nl, span, nslot, lds, s);
+        case 2: return launch_lds_n<OutT, 2>(a, nl, span, nslot, lds, s);
+        case 3: return launch_lds_n<OutT, 3>(a, nl, span, nslot, lds, s);
+        default: return launch_lds_n<OutT, 4>(a, nl, span, nslot, lds, s);
+    }
+}
+
 // One chain launch over windows idx[0..n) of d (all heights multiples of the stride, ring fits).
-hipError_t launch_chain_group(int V, const GatherDesc *d, const int *idx, int n, bool out64, hipStream_t s) {
+// allow_lds: use the LDS-staged kernel where it applies (stride 1, span within the LDS budget).
+hipError_t launch_chain_group(int V, const GatherDesc *d, const int *idx, int n, bool out64, hipStream_t s,
+                              bool allow_lds = false) {
     ChainArgs a{};
     a.S = d[idx[0]].S;
     a.spitch = d[idx[0]].spitch;
@@ -558,6 +725,18 @@ hipError_t launch_chain_group(int V, const GatherDesc *d, const int *idx, int n,
     }
     a.q = q;
     a.ow_max = ow_max;
+    int64_t wmax = 0;
+    for (int i = 0; i < n; ++i) wmax = d[idx[i]].win_w > wmax ? d[idx[i]].win_w : wmax;
+    int nl = 0, span = 0;
+    size_t lds_bytes = 0;
+    if (allow_lds && lds_plan(a.stride, wmax, Lmax, out64, &nl, &span, &lds_bytes)) {
+        a.chunks = (ow_max + kLdsC - 1) / kLdsC;
+        const int64_t P = (oh_max + q - 1) / q;
+        a.seg = chain_segments(q * a.chunks, P, Lmax);
+        a.items = q * a.chunks * ((P + a.seg - 1) / a.seg);
+        return out64 ? launch_lds<uint64_t>(a, n, nl, span, Lmax + 1, lds_bytes, s)
+                     : launch_lds<uint32_t>(a, n, nl, span, Lmax + 1, lds_bytes, s);
+    }
     a.chunks = (ow_max + 256 * V - 1) / (256 * V);
     const int64_t P = (oh_max + q - 1) / q;
     a.seg = chain_segments(q * a.chunks, P, Lmax);
@@ -620,7 +799,7 @@ hipError_t launch_window_sum(int variant, const GatherDesc &d, bool out64, hipSt
     const GatherVariant *g = &kGather[variant];
     if (g->kind == G_CHAIN && chain_ok(d)) {
         const int idx = 0;
-        return launch_chain_group(chain_v(*g, 1), &d, &idx, 1, out64, stream);
+        return launch_chain_group(chain_v(*g, 1), &d, &idx, 1, out64, stream, g->v == 0);
     }
     if (g->kind == G_CHAIN) g = &kGather[kRowPairFallback];
     return out64 ? launch_rowpair_typed<uint64_t>(g->v, d, g->banded != 0, stream)
@@ -654,7 +833,7 @@ hipError_t launch_window_sum_multi(int variant, const GatherDesc *descs, int n, 
             if (slots * slot_bytes > kRingBytes) break;
             ++m;
         }
-        hipError_t e = launch_chain_group(chain_v(g, m), descs, order + i, m, out64, stream);
+        hipError_t e = launch_chain_group(chain_v(g, m), descs, order + i, m, out64, stream, g.v == 0);
         if (e != hipSuccess) return e;
         i += m;
     }

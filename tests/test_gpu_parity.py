@@ -259,13 +259,14 @@ def test_balanced_strip_heights_tall_image():
 # ------------------------------------------------------------------ chain gathers
 
 CHAIN_CASES = [(1, 1, 1), (2, 5, 1), (301, 1111, 1), (64, 64, 4), (12, 7, 3), (300, 2, 1), (5, 517, 5),
-               (100, 100, 1), (7, 300, 3)]      # the last: height not a multiple of the stride (row pairs)
+               (100, 100, 1), (5, 1500, 1), (7, 2500, 1), (1, 3111, 1),
+               (7, 300, 3)]      # the last: height not a multiple of the stride (row pairs)
 
 
 @pytest.mark.parametrize("out64", [False, True])
 def test_chain_gather_every_variant(out64):
     rng = np.random.default_rng(15)
-    img_np = rng.integers(0, 65536, (301, 1111)).astype(np.uint16)
+    img_np = rng.integers(0, 65536, (301, 3111)).astype(np.uint16)
     S = api.sat_build(to_device(img_np))
     ref_S = oracle.sat(img_np)
     odt = torch.uint64 if out64 else torch.uint32
@@ -317,7 +318,7 @@ def test_chain_multi_window_groups(out64):
     ]
     try:
         for v, name in enumerate(api.variants(1)):
-            if name not in ("chain_v1", "chain_v2", "chain_v4", "rowpair_v4_banded"):
+            if name not in ("chain_auto", "chain_v1", "chain_v2", "chain_v4", "rowpair_v4_banded"):
                 continue
             api.force_variant(1, v)
             for wins, s in sets:
