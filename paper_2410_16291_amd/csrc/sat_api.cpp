@@ -128,9 +128,11 @@ int choose_build_variant(int64_t total_rows, int n_images, int bpp, bool sq) {
     // parallelism: 64-row strips once there are two per CU, else 32-row strips.  Eight pixels
     // per lane only for 8-bit images without the squared table (with 16-bit pixels or squares
     // that variant holds one wave per SIMD; four pixels per lane is measured faster there).
+    // Table stores are non-temporal (the table is read back only after it has long left the
+    // caches): 4-5 % faster at 70000 x 85000.
     const int64_t want = 2ll * device_cus();
     const int64_t strips64 = (total_rows + 63 * n_images) / 64;
-    if (strips64 >= want) return (bpp == 1 && !sq) ? 0 : 1;
+    if (strips64 >= want) return (bpp == 1 && !sq) ? 8 : 9;
     return 2;
 }
 

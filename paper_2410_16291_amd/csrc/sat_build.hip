@@ -133,14 +133,21 @@ __device__ __forceinline__ i32x4 make_rsrc(const void *base, uint32_t num_record
 // The compiler does not insert them for gfx950: an overwrite in the next cycle was seen to
 // corrupt lanes 12-15 of every 16-lane group.  Keeping the s_nop inside the same asm block
 // makes the gap independent of scheduling and register allocation.  The asm has no outputs.
+template <bool NT = false>
 __device__ __forceinline__ void store16_rsrc(u32x4 data, i32x4 rsrc, uint32_t voff, uint32_t soff) {
-    asm volatile("buffer_store_dwordx4 %0, %1, %2, %3 offen\n\ts_nop 1"
-                 :
-                 : "v"(data), "v"(voff), "s"(rsrc), "s"(soff)
-                 : "memory");
+    if constexpr (NT)
+        asm volatile("buffer_store_dwordx4 %0, %1, %2, %3 offen nt\n\ts_nop 1"
+                     :
+                     : "v"(data), "v"(voff), "s"(rsrc), "s"(soff)
+                     : "memory");
+    else
+        asm volatile("buffer_store_dwordx4 %0, %1, %2, %3 offen\n\ts_nop 1"
+                     :
+                     : "v"(data), "v"(voff), "s"(rsrc), "s"(soff)
+                     : "memory");
 }
 
-template <typename T, bool SQ, int PX, int RW, int NW, int MODE>
+template <typename T, bool SQ, int PX, int RW, int NW, int MODE, bool NTS = false>
 struct Build {
     static constexpr int TH = RW * NW;                       // strip height
     static constexpr int BW = 64 * PX;                       // block width
@@ -477,14 +484,14 @@ struct Build {
                 acc[2 * sb + 1] += b + pair;
                 const uint64_t o0 = u[2 * sb] + acc[2 * sb], o1 = u[2 * sb + 1] + acc[2 * sb + 1];
                 if (VEC) {
-                    store16_rsrc(u32x4{static_cast<uint32_t>(o0), static_cast<uint32_t>(o0 >> 32),
+                    store16_rsrc<NTS>(u32x4{static_cast<uint32_t>(o0), static_cast<uint32_t>(o0 >> 32),
                                        static_cast<uint32_t>(o1), static_cast<uint32_t>(o1 >> 32)},
                                  rs_blk, voff + sb * 1024, roff);
                 } else {
                     __builtin_amdgcn_raw_buffer_store_b64(u32x2{static_cast<uint32_t>(o0), static_cast<uint32_t>(o0 >> 32)},
-                                                          rs_row, voff + sb * 1024, 0, 0);
+                                                          rs_row, voff + sb * 1024, 0, NTS ? 2 : 0);
                     __builtin_amdgcn_raw_buffer_store_b64(u32x2{static_cast<uint32_t>(o1), static_cast<uint32_t>(o1 >> 32)},
-                                                          rs_row, voff + sb * 1024 + 8, 0, 0);
+                                                          rs_row, voff + sb * 1024 + 8, 0, NTS ? 2 : 0);
                 }
                 base += readlane(incl, 63);
             }
@@ -958,11 +965,11 @@ __global__ __launch_bounds__((NW + 1) * 64) void build2_kernel(const BuildDesc *
 
 // Persistent strip kernel: each workgroup takes strips (of one image, or of a batch) from the
 // ticket counter until none are left.
-template <typename T, bool SQ, int PX, int RW, int NW, int MODE>
+template <typename T, bool SQ, int PX, int RW, int NW, int MODE, bool NTS>
 __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(16 / NW > 4 ? 4 : 16 / NW)))
 void build_kernel(const BuildDesc *__restrict__ many, int n, long long total_items, uint64_t *state,
                   BuildCtrl *ctrl) {
-    using B = Build<T, SQ, PX, RW, NW, MODE>;
+    using B = Build<T, SQ, PX, RW, NW, MODE, NTS>;
     __shared__ typename B::Smem sm;
     for (;;) {
         if (threadIdx.x == 0) sm.ticket = static_cast<long long>(atomicAdd(&ctrl->ticket, 1ull));
@@ -1044,25 +1051,27 @@ __global__ __launch_bounds__(256) void colscan_kernel(uint64_t *state, long long
 // ------------------------------------------------------------------ variants and launch
 
 // Compiled variants: index, name, pixels per lane, rows per wave, waves, mode, lookback window
-// (helper mode; 0 = column totals precomputed), adaptive strip height.
-#define SAT_BUILD_VARIANTS(X)                                                   \
-    X(0, "lookback_px8_rw16_nw4", 8, 16, 4, MODE_LOOKBACK, 1, 1)                \
-    X(1, "lookback_px4_rw16_nw4", 4, 16, 4, MODE_LOOKBACK, 1, 1)                \
-    X(2, "lookback_px4_rw8_nw4", 4, 8, 4, MODE_LOOKBACK, 1, 1)                  \
-    X(3, "lookback_px4_rw8_nw8", 4, 8, 8, MODE_LOOKBACK, 1, 1)                  \
-    X(4, "reduce_scan_px4_rw16_nw4", 4, 16, 4, MODE_REDUCE_SCAN, 1, 0)          \
-    X(5, "helper_px2_rw16_nw4", 2, 16, 4, MODE_HELPER, 1, 0)                    \
-    X(6, "helper_px4_rw16_nw4", 4, 16, 4, MODE_HELPER, 1, 0)                    \
-    X(7, "helper_reduce_scan_px4_rw16_nw4", 4, 16, 4, MODE_HELPER, 0, 0)
+// (helper mode; 0 = column totals precomputed), adaptive strip height, non-temporal table stores.
+#define SAT_BUILD_VARIANTS(X)                                                      \
+    X(0, "lookback_px8_rw16_nw4", 8, 16, 4, MODE_LOOKBACK, 1, 1, false)            \
+    X(1, "lookback_px4_rw16_nw4", 4, 16, 4, MODE_LOOKBACK, 1, 1, false)            \
+    X(2, "lookback_px4_rw8_nw4", 4, 8, 4, MODE_LOOKBACK, 1, 1, false)              \
+    X(3, "lookback_px4_rw8_nw8", 4, 8, 8, MODE_LOOKBACK, 1, 1, false)              \
+    X(4, "reduce_scan_px4_rw16_nw4", 4, 16, 4, MODE_REDUCE_SCAN, 1, 0, false)      \
+    X(5, "helper_px2_rw16_nw4", 2, 16, 4, MODE_HELPER, 1, 0, false)                \
+    X(6, "helper_px4_rw16_nw4", 4, 16, 4, MODE_HELPER, 1, 0, false)                \
+    X(7, "helper_reduce_scan_px4_rw16_nw4", 4, 16, 4, MODE_HELPER, 0, 0, false)    \
+    X(8, "lookback_nt_px8_rw16_nw4", 8, 16, 4, MODE_LOOKBACK, 1, 1, true)          \
+    X(9, "lookback_nt_px4_rw16_nw4", 4, 16, 4, MODE_LOOKBACK, 1, 1, true)
 
 const BuildVariant kVariants[] = {
-#define SAT_X(i, name, px, rw, nw, mode, win, adapt) {name, px, rw, nw, mode},
+#define SAT_X(i, name, px, rw, nw, mode, win, adapt, nt) {name, px, rw, nw, mode},
     SAT_BUILD_VARIANTS(SAT_X)
 #undef SAT_X
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 const int kAdaptive[] = {
-#define SAT_X(i, name, px, rw, nw, mode, win, adapt) adapt,
+#define SAT_X(i, name, px, rw, nw, mode, win, adapt, nt) adapt,
     SAT_BUILD_VARIANTS(SAT_X)
 #undef SAT_X
 };
@@ -1076,19 +1085,19 @@ int resident_capacity(const void *kernel, int threads) {
     return cus * per_cu;
 }
 
-template <typename T, bool SQ, int PX, int RW, int NW, int MODE, int WIN>
+template <typename T, bool SQ, int PX, int RW, int NW, int MODE, int WIN, bool NT>
 int capacity_typed() {
     static int cap = 0;   // per instantiation; the library drives one device model
     if (cap == 0) {
         if constexpr (MODE == MODE_HELPER)
             cap = resident_capacity(reinterpret_cast<const void *>(&build2_kernel<T, SQ, PX, RW, NW, WIN>), (NW + 1) * 64);
         else
-            cap = resident_capacity(reinterpret_cast<const void *>(&build_kernel<T, SQ, PX, RW, NW, MODE>), NW * 64);
+            cap = resident_capacity(reinterpret_cast<const void *>(&build_kernel<T, SQ, PX, RW, NW, MODE, NT>), NW * 64);
     }
     return cap;
 }
 
-template <typename T, bool SQ, int PX, int RW, int NW, int MODE, int WIN>
+template <typename T, bool SQ, int PX, int RW, int NW, int MODE, int WIN, bool NT>
 hipError_t launch_typed(const BuildDesc *descs, int n, const BuildDesc *dev_descs, int64_t total_items,
                         void *workspace, int64_t state_words, hipStream_t stream) {
     BuildCtrl *ctrl = static_cast<BuildCtrl *>(workspace);
@@ -1121,13 +1130,13 @@ hipError_t launch_typed(const BuildDesc *descs, int n, const BuildDesc *dev_desc
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int cap = capacity_typed<T, SQ, PX, RW, NW, MODE, WIN>();
+    const int cap = capacity_typed<T, SQ, PX, RW, NW, MODE, WIN, NT>();
     const int64_t grid = total_items < cap ? total_items : cap;
     if constexpr (MODE == MODE_HELPER)
         hipLaunchKernelGGL((build2_kernel<T, SQ, PX, RW, NW, WIN>), dim3(static_cast<unsigned>(grid)),
                            dim3((NW + 1) * 64), 0, stream, table, n, static_cast<long long>(total_items), state, ctrl);
     else
-        hipLaunchKernelGGL((build_kernel<T, SQ, PX, RW, NW, MODE>), dim3(static_cast<unsigned>(grid)),
+        hipLaunchKernelGGL((build_kernel<T, SQ, PX, RW, NW, MODE, NT>), dim3(static_cast<unsigned>(grid)),
                            dim3(NW * 64), 0, stream, table, n, static_cast<long long>(total_items), state, ctrl);
     return hipGetLastError();
 }
@@ -1136,8 +1145,8 @@ template <typename T, bool SQ>
 hipError_t launch_variant(int v, const BuildDesc *descs, int n, const BuildDesc *dev_descs, int64_t total,
                           void *ws, int64_t words, hipStream_t s) {
     switch (v) {
-#define SAT_X(i, name, px, rw, nw, mode, win, adapt) \
-        case i: return launch_typed<T, SQ, px, rw, nw, mode, win>(descs, n, dev_descs, total, ws, words, s);
+#define SAT_X(i, name, px, rw, nw, mode, win, adapt, nt) \
+        case i: return launch_typed<T, SQ, px, rw, nw, mode, win, nt>(descs, n, dev_descs, total, ws, words, s);
         SAT_BUILD_VARIANTS(SAT_X)
 #undef SAT_X
         default: return hipErrorInvalidValue;
@@ -1147,8 +1156,8 @@ hipError_t launch_variant(int v, const BuildDesc *descs, int n, const BuildDesc 
 template <typename T, bool SQ>
 int capacity_variant(int v) {
     switch (v) {
-#define SAT_X(i, name, px, rw, nw, mode, win, adapt) \
-        case i: return capacity_typed<T, SQ, px, rw, nw, mode, win>();
+#define SAT_X(i, name, px, rw, nw, mode, win, adapt, nt) \
+        case i: return capacity_typed<T, SQ, px, rw, nw, mode, win, nt>();
         SAT_BUILD_VARIANTS(SAT_X)
 #undef SAT_X
         default: return 1;
