@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-image section")
     ap.add_argument("--batch-images", type=int, default=64)
     ap.add_argument("--no-serve", action="store_true", help="skip the serving section")
+    ap.add_argument("--no-banded", action="store_true", help="skip the banded (out-of-core) section")
+    ap.add_argument("--band-rows", type=int, default=8192)
     ap.add_argument("--serve-seconds", type=float, default=10.0, help="length of the 50 req/s request stream")
     ap.add_argument("--burst-seconds", type=float, default=3.0, help="length of the 500 req/s burst")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the baseline sample")
@@ -196,6 +198,37 @@ def serving_section(torch, dev, seconds, burst_seconds):
     return out
 
 
+def banded_section(torch, dev, H, W, band_rows):
+    """The same window sums computed band by band, the table never materialised: the image
+    streamed from pinned host memory (PCIe included) and from device memory."""
+    from paper_2410_16291_amd import banded, synth
+
+    mask = synth.thomas_mask(H, W, seed=2)
+    host = torch.empty((H, W), dtype=torch.uint8, pin_memory=True)
+    host.numpy()[...] = mask
+    del mask
+    wins = [(h, h) for h in WINDOWS]
+    res = {"workload": "the %dx%d mask above in bands of %d rows (plus the 499 overlap rows each band "
+                       "rebuilds); windows 100/250/500 at stride 1; outputs left on the device" % (H, W, band_rows),
+           "band_rows": band_rows}
+    for name, src in (("from_pinned_host", host), ("from_device", None)):
+        if src is None:
+            src = host.to(dev)
+        job = banded.BandedWindowSums(H, W, wins, 1, "u8", band_rows, dev)
+        job.run(lambda r0, r1: src[r0:r1], lambda i, k0, rows: None)        # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        job.run(lambda r0, r1: src[r0:r1], lambda i, k0, rows: None)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        res[name] = {"ms": round(dt * 1e3, 2), "gpix_s": round(H * W / dt / 1e9, 2), "bands": len(job.plan),
+                     "device_GB": round((sum(t.numel() for t in job.dimg) + job.table.numel() * 8) / 1e9, 2)}
+        del job, src
+        torch.cuda.empty_cache()
+    del host
+    return res
+
+
 def calibrate_copy(torch, dev):
     """Plain copies of known size for the counter scale: 1 GiB read and 1 GiB written each."""
     n = 1 << 27
@@ -323,6 +356,8 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_batched:
         res["batched"] = batched_section(torch, dev, args.batch_images)
+    if not args.no_banded:
+        res["banded"] = banded_section(torch, dev, H, W, args.band_rows)
     if not args.no_serve:
         torch.cuda.empty_cache()
         res["serving"] = serving_section(torch, dev, args.serve_seconds, args.burst_seconds)

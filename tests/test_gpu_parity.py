@@ -517,3 +517,32 @@ def test_full_scale_70000x85000_sampled():
     for r, m_ref, s_ref in zip(rows[1], ref_mean, ref_std):
         assert np.array_equal(to_host(mean[r]), m_ref), r
         check_std(to_host(std[r]), s_ref)
+
+
+# ------------------------------------------------------------------ banded (out-of-core) window sums
+
+@pytest.mark.parametrize("band_rows", [1, 50, 333, 5000])
+def test_banded_window_sums_match_oracle(band_rows):
+    from paper_2410_16291_amd import banded
+    rng = np.random.default_rng(24)
+    img_np = rng.integers(0, 256, (1001, 700)).astype(np.uint8)
+    ref_S = oracle.sat(img_np)
+    wins = [(7, 5), (64, 64), (100, 300)]
+    for s in (1, 3):
+        print("case: banded", band_rows, s, flush=True)
+        outs = banded.banded_window_sums(lambda r0, r1: img_np[r0:r1], 1001, 700, wins, s, pixel_type="u8",
+                                         band_rows=band_rows)
+        for (h, w), o in zip(wins, outs):
+            assert np.array_equal(o.astype(np.uint64), oracle.window_sum_sat(ref_S, h, w, s)), (band_rows, h, w, s)
+
+
+def test_banded_u16_from_device_rows():
+    from paper_2410_16291_amd import banded
+    img = synth.lognormal_u16_device(3000, 257, 25, "cuda:0")
+    img_np = to_host(img)
+    wins = [(16, 16), (120, 7)]
+    outs = banded.banded_window_sums(lambda r0, r1: img[r0:r1], 3000, 257, wins, 2, pixel_type="u16",
+                                     band_rows=512)
+    ref_S = oracle.sat(img_np)
+    for (h, w), o in zip(wins, outs):
+        assert np.array_equal(o.astype(np.uint64), oracle.window_sum_sat(ref_S, h, w, 2)), (h, w)
