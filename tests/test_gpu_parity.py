@@ -546,3 +546,19 @@ def test_banded_u16_from_device_rows():
     ref_S = oracle.sat(img_np)
     for (h, w), o in zip(wins, outs):
         assert np.array_equal(o.astype(np.uint64), oracle.window_sum_sat(ref_S, h, w, 2)), (h, w)
+
+
+def test_batched_build_every_variant_with_squares():
+    """Every build variant, squared table included, over one batch (the split variants run a
+    second pass from a second descriptor table)."""
+    from paper_2410_16291_amd import batch
+    imgs_np = synth.uneven_batch(6, lo=60, hi=900, seed=26)
+    imgs = [to_device(i) for i in imgs_np]
+    refs = [oracle.sat(i, squares=True) for i in imgs_np]
+    for name in api.variants(0):
+        print("case: batched build", name, flush=True)
+        tables = batch.build_batched(imgs, True, variant=name)
+        torch.cuda.synchronize()
+        for i, (ref_S, ref_Q) in enumerate(refs):
+            assert np.array_equal(to_host(tables[i][0]), ref_S), (name, i)
+            assert np.array_equal(to_host(tables[i][1]), ref_Q), (name, i)
