@@ -121,19 +121,31 @@ int gather_variant() {
     return v >= 0 && v < satk::gather_variant_count() ? v : 0;
 }
 
-int choose_build_variant(int64_t total_rows, int n_images, int bpp, bool sq) {
+// Variants the built-in choice uses (indices into the compiled table).
+constexpr int kVarNtPx8 = 8;      // lookback, non-temporal stores, 8 pixels per lane
+constexpr int kVarNtPx4 = 9;      // lookback, non-temporal stores, 4 pixels per lane
+constexpr int kVarHelper = 6;     // helper wave staging tiles by LDS DMA, 4 pixels per lane
+constexpr int kVarShort = 2;      // lookback, 32-row strips
+
+// aligned: every image row start allows 4-byte loads (the helper wave's LDS DMA needs that).
+int choose_build_variant(int64_t total_rows, int n_images, int bpp, bool sq, bool aligned) {
     const int v = g_force[0];
     if (v >= 0) return v;
     // Each work item is one strip swept across the full width, so the number of strips is the
-    // parallelism: 64-row strips once there are two per CU, else 32-row strips.  Eight pixels
-    // per lane only for 8-bit images without the squared table (with 16-bit pixels or squares
-    // that variant holds one wave per SIMD; four pixels per lane is measured faster there).
-    // Table stores are non-temporal (the table is read back only after it has long left the
-    // caches): 4-5 % faster at 70000 x 85000.
+    // parallelism.  With two 64-row strips per CU or more: lookback with non-temporal table
+    // stores (the table is read back only after it has long left the caches), eight pixels per
+    // lane only for 8-bit images without the squared table (with 16-bit pixels or squares that
+    // variant holds one wave per SIMD).  With fewer strips each workgroup's own latency decides:
+    // the helper wave that stages the next tile by DMA and runs the lookback one block ahead
+    // (15-30 % faster at 16384 x 16384), or 32-row strips when rows are not aligned for DMA.
     const int64_t want = 2ll * device_cus();
     const int64_t strips64 = (total_rows + 63 * n_images) / 64;
-    if (strips64 >= want) return (bpp == 1 && !sq) ? 8 : 9;
-    return 2;
+    if (strips64 >= want) return (bpp == 1 && !sq) ? kVarNtPx8 : kVarNtPx4;
+    return aligned ? kVarHelper : kVarShort;
+}
+
+bool rows_aligned4(const void *image, int64_t ipitch, int bpp) {
+    return reinterpret_cast<uintptr_t>(image) % 4 == 0 && (ipitch * bpp) % 4 == 0;
 }
 
 // Strip height for one image: the variant's full height unless the strips would not fit the
@@ -171,6 +183,14 @@ int64_t build_state_words(int v, int64_t H, int64_t W, bool sq) {
     return state_words_for(var, H, W, sq, min_strip_h(var, satk::build_variant_adaptive(v)));
 }
 
+// Lookback words a build of one H x W image needs whichever row alignment it turns out to have
+// (the built-in choice depends on it).
+int64_t build_state_words_any(int64_t H, int64_t W, int bpp, bool sq) {
+    const int a = choose_build_variant(H, 1, bpp, sq, true), b = choose_build_variant(H, 1, bpp, sq, false);
+    const int64_t wa = build_state_words(a, H, W, sq), wb = build_state_words(b, H, W, sq);
+    return wa > wb ? wa : wb;
+}
+
 void fill_desc(satk::BuildDesc &d, const satk::BuildVariant &v, const void *image, int bpp, int64_t H,
                int64_t W, int64_t ipitch, uint64_t *sat, uint64_t *sat_sq, int64_t spitch, int strip_h) {
     d.img = image;
@@ -187,7 +207,9 @@ void fill_desc(satk::BuildDesc &d, const satk::BuildVariant &v, const void *imag
     d.Wp = static_cast<int64_t>(d.nblocks) * v.bw();
     const uintptr_t ia = reinterpret_cast<uintptr_t>(image);
     const int64_t row_bytes = ipitch * bpp;
-    d.img_vb = 0;
+    // Rows whose starts are not 4-byte aligned still take 4-byte loads into registers (the
+    // hardware serves unaligned dword buffer loads); only the LDS DMA path needs alignment.
+    d.img_vb = -4;
     for (int vb = 16; vb >= 4; vb /= 2)
         if (ia % vb == 0 && row_bytes % vb == 0 && vb <= v.bw() * bpp) {
             d.img_vb = vb;
@@ -280,9 +302,10 @@ sat_status window_out_shape(int64_t H, int64_t W, int64_t win_h, int64_t win_w, 
 size_t sat_build_workspace_bytes(int64_t H, int64_t W, sat_dtype pixel_type, int with_sq) {
     if (H < 1 || W < 1 || H > kMaxDim || W > kMaxDim) return 0;
     if (pixel_type != SAT_U8 && pixel_type != SAT_U16) return 0;
-    const int v = choose_build_variant(H, 1, bytes_of(pixel_type), with_sq != 0);
+    const int v = choose_build_variant(H, 1, bytes_of(pixel_type), with_sq != 0, true);
     if (v < 0 || v >= satk::build_variant_count()) return 0;
-    return sizeof(satk::BuildCtrl) + 8 * static_cast<size_t>(build_state_words(v, H, W, with_sq != 0));
+    return sizeof(satk::BuildCtrl) +
+           8 * static_cast<size_t>(build_state_words_any(H, W, bytes_of(pixel_type), with_sq != 0));
 }
 
 sat_status sat_build(const void *image, sat_dtype pixel_type, int64_t H, int64_t W, int64_t image_pitch,
@@ -302,7 +325,7 @@ sat_status sat_build(const void *image, sat_dtype pixel_type, int64_t H, int64_t
     if (overlap(sw, span(image, H, image_pitch, W, bpp)) || overlap(sw, span(sat, H, sat_pitch, W, 8)) ||
         overlap(sw, span(sat_sq, H, sat_pitch, W, 8)))
         return fail(SAT_ERR_ARG, "%s: workspace overlaps an input or output", who);
-    const int v = choose_build_variant(H, 1, bpp, sat_sq != nullptr);
+    const int v = choose_build_variant(H, 1, bpp, sat_sq != nullptr, rows_aligned4(image, image_pitch, bpp));
     if (v < 0 || v >= satk::build_variant_count()) return fail(SAT_ERR_ARG, "%s: forced variant out of range", who);
     const satk::BuildVariant &var = satk::build_variant(v);
     satk::BuildDesc d{};
@@ -428,11 +451,15 @@ size_t sat_batch_workspace_bytes(const sat_batch_item *items, int32_t n, sat_dty
         if (items[i].H < 1 || items[i].W < 1 || items[i].H > kMaxDim || items[i].W > kMaxDim) return 0;
         rows += items[i].H;
     }
-    const int v = choose_build_variant(rows, n, bytes_of(pixel_type), with_sq != 0);
-    if (v < 0 || v >= satk::build_variant_count()) return 0;
-    const satk::BuildVariant &var = satk::build_variant(v);
-    for (int i = 0; i < n; ++i)
-        words += static_cast<size_t>(state_words_for(var, items[i].H, items[i].W, with_sq != 0, var.th()));
+    size_t words_any[2] = {0, 0};
+    for (int al = 0; al < 2; ++al) {
+        const int v = choose_build_variant(rows, n, bytes_of(pixel_type), with_sq != 0, al != 0);
+        if (v < 0 || v >= satk::build_variant_count()) return 0;
+        const satk::BuildVariant &var = satk::build_variant(v);
+        for (int i = 0; i < n; ++i)
+            words_any[al] += static_cast<size_t>(state_words_for(var, items[i].H, items[i].W, with_sq != 0, var.th()));
+    }
+    words = words_any[0] > words_any[1] ? words_any[0] : words_any[1];
     const size_t descs = round256(static_cast<size_t>(n) *
                                   (sizeof(satk::BuildDesc) > sizeof(satk::GatherDesc) ? sizeof(satk::BuildDesc)
                                                                                       : sizeof(satk::GatherDesc)));
@@ -479,7 +506,9 @@ sat_status sat_build_batched(const sat_batch_item *items, int32_t n, sat_dtype p
         outs.push_back(a);
         if (b.lo != b.hi) outs.push_back(b);
     }
-    const int v = choose_build_variant(rows, n, bytes_of(pixel_type), with_sq);
+    bool aligned = true;
+    for (int i = 0; i < n; ++i) aligned = aligned && rows_aligned4(items[i].image, items[i].image_pitch, bpp);
+    const int v = choose_build_variant(rows, n, bpp, with_sq, aligned);
     if (v < 0 || v >= satk::build_variant_count()) return fail(SAT_ERR_ARG, "%s: forced variant out of range", who);
     const satk::BuildVariant &var = satk::build_variant(v);
     std::vector<satk::BuildDesc> d(n);

@@ -23,7 +23,8 @@ struct BuildDesc {
     int32_t nstrips, nblocks;
     int32_t strip_h;      // rows per strip (<= the variant's strip height; chosen to balance rounds)
     int32_t wave_rows;    // rows per wave: ceil(strip_h / waves)
-    int32_t img_vb;       // widest load (16, 8 or 4 bytes) that every image row start allows; 0: none
+    int32_t img_vb;       // widest aligned load (16, 8 or 4 bytes) every image row start allows;
+                          // -4: rows not 4-byte aligned (unaligned 4-byte loads, no LDS DMA)
     int32_t sat_vec;      // 1: table rows allow 16-byte vector stores
 };
 

@@ -130,8 +130,10 @@ def request_stream(rate: float = 50.0, duration: float = 120.0, seed: int = 4,
 # above, float32 draws; not the same numbers as the numpy streams).  Tests that compare such an
 # input with the oracle copy the generated image to the host first.
 
-def lognormal_u16_device(H: int, W: int, seed: int, device, mu: float = 6.0, sigma: float = 1.0):
-    """Log-normal intensities rounded to nearest and clipped to 0..65535, as a uint16 tensor."""
+def lognormal_u16_device(H: int, W: int, seed: int, device, mu: float = 6.0, sigma: float = 1.0,
+                         pitch: Optional[int] = None):
+    """Log-normal intensities rounded to nearest and clipped to 0..65535, as a uint16 tensor
+    (`pitch`: row pitch in elements of a wider buffer the image is a view of)."""
     import torch
     g = torch.Generator(device=device)
     g.manual_seed(seed)
@@ -139,7 +141,14 @@ def lognormal_u16_device(H: int, W: int, seed: int, device, mu: float = 6.0, sig
     v = torch.exp_(z.mul_(sigma).add_(mu)).round_().clamp_(0, 65535).to(torch.int32)
     del z
     v -= (v >= 32768).to(torch.int32) * 65536          # two's-complement wrap into int16 range
-    return v.to(torch.int16).view(torch.uint16)
+    img = v.to(torch.int16)
+    if pitch is not None and pitch != W:
+        if pitch < W:
+            raise ValueError("pitch must be >= W")
+        buf = torch.zeros((H, pitch), dtype=torch.int16, device=device)
+        buf[:, :W] = img
+        img = buf[:, :W]
+    return img.view(torch.uint16)
 
 
 def thomas_mask_device(H: int, W: int, seed: int, device, parent_density: float = 2e-6, children: int = 200,
