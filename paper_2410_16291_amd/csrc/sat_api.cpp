@@ -84,21 +84,15 @@ sat_status check_dims(int64_t H, int64_t W, const char *who) {
 sat_status check_pitch(int64_t pitch, int64_t W, int64_t H, int elem, const char *who, const char *what) {
     if (pitch < W) return fail(SAT_ERR_ARG, "%s: %s pitch %lld is below the width %lld", who, what,
                                (long long)pitch, (long long)W);
-    // 32-bit buffer offsets span up to 128 rows of a strip; rows * pitch * elem stays far from
-    // int64 overflow
+    // Buffer resources span at most 64 rows of a strip (one wave's 16 rows for stores), so 32-bit
+    // byte offsets stay in range for pitches up to 2^24 elements; rows * pitch * elem stays far
+    // from int64 overflow
     if (pitch > kMaxRowElems || H > ((1ll << 60) / (pitch * elem)))
         return fail(SAT_ERR_ARG, "%s: %s pitch above 2^24 elements or extent too large", who, what);
     return SAT_OK;
 }
 
 // ------------------------------------------------------------------ build planning
-
-struct BuildPlan {
-    int variant;
-    std::vector<satk::BuildDesc> descs;
-    int64_t total_items = 0;
-    int64_t state_words = 0;
-};
 
 int device_cus() {
     static int cus = 0;
@@ -113,9 +107,8 @@ int device_cus() {
     return cus;
 }
 
-// Tallest strips that still give every compute unit about two strips to work on.
-// Gather variant of a call on this thread: the forced one, else the chain walk with two outputs
-// per thread (it falls back to row pairs by itself where chains do not apply).
+// Gather variant of a call on this thread: the forced one, else the automatic chain walk (the
+// LDS-staged kernel where it applies; chain and row-pair kernels otherwise, chosen per launch).
 int gather_variant() {
     const int v = g_force[1];
     return v >= 0 && v < satk::gather_variant_count() ? v : 0;
