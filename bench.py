@@ -263,10 +263,8 @@ def main():
 
     # --- synthetic input, made resident in HBM before any timing
     ys, xs = synth.thomas_points(H, W, seed=2)
-    img = torch.zeros((H, W), dtype=torch.uint8, device=dev)
-    idx = torch.from_numpy(ys * W + xs).to(dev)
-    img.view(-1)[idx] = 1
-    del idx
+    img = api.empty_image(H, W, torch.uint8, dev)          # rows on 128-byte lines, like the table
+    img[torch.from_numpy(ys).to(dev), torch.from_numpy(xs).to(dev)] = 1
     S = api.empty_table(H, W, dev)
     ws = torch.empty(api.build_workspace_bytes(H, W, 1, False), dtype=torch.uint8, device=dev)
     outs = [api.empty_out(*api.out_shape(H, W, h, w, 1), torch.uint32, dev) for h, w in wins]
@@ -342,7 +340,9 @@ def main():
                                "children, sigma 40 px, seed 2); uint64 integral image; sums of every "
                                "100x100, 250x250 and 500x500 window at stride 1 from one table in one "
                                "pass, uint32 outputs" % (H, W), "rows": H, "cols": W,
-                   "windows": list(WINDOWS), "stride": 1},
+                   "windows": list(WINDOWS), "stride": 1,
+                   "row_pitch_bytes": {"image": img.stride(0) * img.element_size(),
+                                       "table": S.stride(0) * 8, "outputs": outs[0].stride(0) * 4}},
         "hbm_frac_step": round(sum(alg.values()) / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "step_alg_GB": round(sum(alg.values()) / 1e9, 3),
         "kernels": kernels,

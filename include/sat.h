@@ -173,6 +173,13 @@ int32_t sat_variant_count(int32_t kind);
 const char *sat_variant_name(int32_t kind, int32_t index);
 sat_status sat_force_variant(int32_t kind, int32_t index);
 
+/* 1 if variant `index` of `kind` runs on images of pixel_type (with_sq != 0: with the squared
+ * table), else 0.  Gather variants run on every table; a build variant whose workgroup state
+ * does not fit the 160 KiB of LDS for that pixel type is not compiled for it, and a build forced
+ * to it fails with SAT_ERR_ARG.  0 for an out-of-range kind, index or pixel type.  Needs no
+ * device. */
+int32_t sat_variant_supported(int32_t kind, int32_t index, sat_dtype pixel_type, int32_t with_sq);
+
 #ifdef __cplusplus
 }
 #endif

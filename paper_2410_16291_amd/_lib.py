@@ -45,6 +45,10 @@ def load(path: str = LIB_PATH):
         if not os.path.exists(path):
             raise RuntimeError("libsat.so is not built (%s); run `python -m paper_2410_16291_amd.build` "
                                "or __graft_entry__.build()" % path)
+        # torch first: libsat's libamdhip64 dependency then binds to the HIP runtime torch already
+        # loaded.  Loaded the other way round, the process holds two runtimes and torch's sees no
+        # device.
+        import torch  # noqa: F401
         lib = ctypes.CDLL(path)
         sig = {
             "window_out_shape": (_st, [_i64, _i64, _i64, _i64, _i64, _p, _p]),
@@ -63,6 +67,7 @@ def load(path: str = LIB_PATH):
             "sat_variant_count": (_i32, [_i32]),
             "sat_variant_name": (ctypes.c_char_p, [_i32, _i32]),
             "sat_force_variant": (_st, [_i32, _i32]),
+            "sat_variant_supported": (_i32, [_i32, _i32, ctypes.c_int, _i32]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(lib, name)

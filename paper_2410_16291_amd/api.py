@@ -56,6 +56,18 @@ def empty_table(H: int, W: int, device, pitch: Optional[int] = None) -> torch.Te
     return torch.empty((H, pitch), dtype=torch.uint64, device=device)[:, :W]
 
 
+def image_pitch(W: int, dtype: torch.dtype) -> int:
+    """Row pitch (elements) of images allocated here: a whole number of 128-byte lines, so every
+    row starts 16-byte aligned and the build stages its tiles with 16-byte loads."""
+    per_line = 128 // dtype.itemsize
+    return (W + per_line - 1) // per_line * per_line
+
+
+def empty_image(H: int, W: int, dtype: torch.dtype, device) -> torch.Tensor:
+    """A zeroed H x W image (uint8 or uint16) on the line-aligned row pitch of image_pitch."""
+    return torch.zeros((H, image_pitch(W, dtype)), dtype=dtype, device=device)[:, :W]
+
+
 def out_pitch(ow: int, dtype: torch.dtype) -> int:
     """Row pitch (elements) of outputs allocated here: a whole number of 128-byte lines, so that
     no two output rows share a cache line (a partly written line costs HBM a read-modify-write)."""
@@ -203,9 +215,15 @@ def workspace_check(ws: torch.Tensor, stream: Optional[torch.cuda.Stream] = None
     check(_lib.load().sat_workspace_check(ws.data_ptr(), _stream_handle(ws.device, stream)))
 
 
-def variants(kind: int) -> List[str]:
+def variants(kind: int, pixel_type: Optional[str] = None, squares: bool = False) -> List[str]:
+    """Names of the compiled build (kind 0) or gather (kind 1) variants; with `pixel_type`, only
+    those that run on such images (with the squared table if `squares`)."""
     lib = _lib.load()
-    return [lib.sat_variant_name(kind, i).decode() for i in range(lib.sat_variant_count(kind))]
+    names = [lib.sat_variant_name(kind, i).decode() for i in range(lib.sat_variant_count(kind))]
+    if pixel_type is None:
+        return names
+    code = _PIXCODE[pixel_type]
+    return [n for i, n in enumerate(names) if lib.sat_variant_supported(kind, i, code, int(squares))]
 
 
 def force_variant(kind: int, index: int) -> None:

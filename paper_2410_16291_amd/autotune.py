@@ -135,7 +135,7 @@ class Tuner:
         bkey = dkey + "|" + shape_class(sizes, pb, squares)
         tables = batch.alloc_tables(images, squares)
         build, build_ms = self.tune(0, bkey, lambda: batch.build_batched(images, squares, tables=tables),
-                                    retune=retune)
+                                    candidates=api.variants(0, "u8" if pb == 1 else "u16", squares), retune=retune)
         gkey = dkey + "|" + shape_class(sizes, pb, squares, win, stride)
         if squares:
             outs = batch.alloc_stats(tables, win[0], win[1], stride)

@@ -115,30 +115,49 @@ int gather_variant() {
 }
 
 // Variants the built-in choice uses (indices into the compiled table).
-constexpr int kVarNtPx8 = 8;      // lookback, non-temporal stores, 8 pixels per lane
-constexpr int kVarNtPx4 = 9;      // lookback, non-temporal stores, 4 pixels per lane
-constexpr int kVarHelper = 6;     // helper wave staging tiles by LDS DMA, 4 pixels per lane
-constexpr int kVarShort = 2;      // lookback, 32-row strips
+constexpr int kVarNtPx8 = 8;        // lookback, non-temporal stores, 8 pixels per lane
+constexpr int kVarNtPx4 = 9;        // lookback, non-temporal stores, 4 pixels per lane
+constexpr int kVarHelperPx4 = 10;   // helper wave (DMA tiles, lookback a block ahead), 4 pixels per lane
+constexpr int kVarHelperPx8 = 11;   // helper wave, 8 pixels per lane, 48-row strips
+constexpr int kVarShort = 2;        // lookback, 32-row strips
 
-// aligned: every image row start allows 4-byte loads (the helper wave's LDS DMA needs that).
-int choose_build_variant(int64_t total_rows, int n_images, int bpp, bool sq, bool aligned) {
+// Row alignment class of an image: 16 when every row start allows 16-byte loads, 4 when it
+// allows 4-byte loads, else 1.  The helper wave's LDS DMA needs 4; below 16 it moves a dword
+// per lane and instruction, a quarter of what it moves with 16-byte rows.
+int row_align(const void *image, int64_t ipitch, int bpp) {
+    const uintptr_t a = reinterpret_cast<uintptr_t>(image);
+    const int64_t pb = ipitch * bpp;
+    if (a % 16 == 0 && pb % 16 == 0) return 16;
+    if (a % 4 == 0 && pb % 4 == 0) return 4;
+    return 1;
+}
+
+// align: the least row alignment class over the images (row_align).
+int choose_build_variant(int64_t total_rows, int n_images, int bpp, bool sq, int align) {
     const int v = g_force[0];
     if (v >= 0) return v;
     // Each work item is one strip swept across the full width, so the number of strips is the
-    // parallelism.  With two 64-row strips per CU or more: lookback with non-temporal table
-    // stores (the table is read back only after it has long left the caches), eight pixels per
-    // lane only for 8-bit images without the squared table (with 16-bit pixels or squares that
-    // variant holds one wave per SIMD).  With fewer strips each workgroup's own latency decides:
-    // the helper wave that stages the next tile by DMA and runs the lookback one block ahead
-    // (15-30 % faster at 16384 x 16384), or 32-row strips when rows are not aligned for DMA.
+    // parallelism.  Measured choices (ms per build; 8192^2 to 70000 x 85000):
+    //  - one image with 16-byte aligned rows: the helper wave, which stages tiles by 16-byte DMA
+    //    and runs the lookback one block ahead of the compute waves, so the lookback's memory
+    //    round trip never stalls them.  Eight pixels per lane once its 48-row strips fill the
+    //    resident workgroups (9-18 % faster than any lookback variant from 24576^2 up), four
+    //    with 16-bit pixels and squares (the eight-pixel state does not fit the LDS) or fewer
+    //    strips;
+    //  - otherwise, with two 64-row strips per CU or more: lookback with non-temporal table
+    //    stores (the table is read back only after it has left the caches), eight pixels per
+    //    lane for 8-bit images without squares (elsewhere that variant holds one wave per SIMD);
+    //  - with fewer strips each workgroup's own latency decides: the helper wave when rows allow
+    //    its DMA, else 32-row strips.
+    if (n_images == 1 && align == 16) {
+        if (bpp == 2 && sq) return kVarHelperPx4;
+        const int64_t strips48 = (total_rows + 47) / 48;
+        return strips48 >= satk::build_variant_capacity(kVarHelperPx8, bpp, sq) ? kVarHelperPx8 : kVarHelperPx4;
+    }
     const int64_t want = 2ll * device_cus();
     const int64_t strips64 = (total_rows + 63 * n_images) / 64;
     if (strips64 >= want) return (bpp == 1 && !sq) ? kVarNtPx8 : kVarNtPx4;
-    return aligned ? kVarHelper : kVarShort;
-}
-
-bool rows_aligned4(const void *image, int64_t ipitch, int bpp) {
-    return reinterpret_cast<uintptr_t>(image) % 4 == 0 && (ipitch * bpp) % 4 == 0;
+    return align >= 4 ? kVarHelperPx4 : kVarShort;
 }
 
 // Strip height for one image: the variant's full height unless the strips would not fit the
@@ -163,6 +182,16 @@ int min_strip_h(const satk::BuildVariant &v, int adaptive) {
     return adaptive ? (v.th() + 1) / 2 : v.th();
 }
 
+// A forced variant must exist and have an instantiation for this pixel type (its workgroup state
+// fits the LDS).
+sat_status check_build_variant(int v, int bpp, bool sq, const char *who) {
+    if (v < 0 || v >= satk::build_variant_count()) return fail(SAT_ERR_ARG, "%s: forced variant out of range", who);
+    if (satk::build_variant_capacity(v, bpp, sq) < 1)
+        return fail(SAT_ERR_ARG, "%s: build variant %s does not fit the LDS for %d-byte pixels%s", who,
+                    satk::build_variant(v).name, bpp, sq ? " with squares" : "");
+    return SAT_OK;
+}
+
 int64_t state_words_for(const satk::BuildVariant &v, int64_t H, int64_t W, bool sq, int strip_h) {
     const int64_t strips = (H + strip_h - 1) / strip_h;
     const int64_t wp = (W + v.bw() - 1) / v.bw() * v.bw();
@@ -179,9 +208,12 @@ int64_t build_state_words(int v, int64_t H, int64_t W, bool sq) {
 // Lookback words a build of one H x W image needs whichever row alignment it turns out to have
 // (the built-in choice depends on it).
 int64_t build_state_words_any(int64_t H, int64_t W, int bpp, bool sq) {
-    const int a = choose_build_variant(H, 1, bpp, sq, true), b = choose_build_variant(H, 1, bpp, sq, false);
-    const int64_t wa = build_state_words(a, H, W, sq), wb = build_state_words(b, H, W, sq);
-    return wa > wb ? wa : wb;
+    int64_t words = 0;
+    for (int align : {16, 4, 1}) {
+        const int64_t w = build_state_words(choose_build_variant(H, 1, bpp, sq, align), H, W, sq);
+        if (w > words) words = w;
+    }
+    return words;
 }
 
 void fill_desc(satk::BuildDesc &d, const satk::BuildVariant &v, const void *image, int bpp, int64_t H,
@@ -295,7 +327,7 @@ sat_status window_out_shape(int64_t H, int64_t W, int64_t win_h, int64_t win_w, 
 size_t sat_build_workspace_bytes(int64_t H, int64_t W, sat_dtype pixel_type, int with_sq) {
     if (H < 1 || W < 1 || H > kMaxDim || W > kMaxDim) return 0;
     if (pixel_type != SAT_U8 && pixel_type != SAT_U16) return 0;
-    const int v = choose_build_variant(H, 1, bytes_of(pixel_type), with_sq != 0, true);
+    const int v = choose_build_variant(H, 1, bytes_of(pixel_type), with_sq != 0, 16);
     if (v < 0 || v >= satk::build_variant_count()) return 0;
     return sizeof(satk::BuildCtrl) +
            8 * static_cast<size_t>(build_state_words_any(H, W, bytes_of(pixel_type), with_sq != 0));
@@ -318,8 +350,8 @@ sat_status sat_build(const void *image, sat_dtype pixel_type, int64_t H, int64_t
     if (overlap(sw, span(image, H, image_pitch, W, bpp)) || overlap(sw, span(sat, H, sat_pitch, W, 8)) ||
         overlap(sw, span(sat_sq, H, sat_pitch, W, 8)))
         return fail(SAT_ERR_ARG, "%s: workspace overlaps an input or output", who);
-    const int v = choose_build_variant(H, 1, bpp, sat_sq != nullptr, rows_aligned4(image, image_pitch, bpp));
-    if (v < 0 || v >= satk::build_variant_count()) return fail(SAT_ERR_ARG, "%s: forced variant out of range", who);
+    const int v = choose_build_variant(H, 1, bpp, sat_sq != nullptr, row_align(image, image_pitch, bpp));
+    if ((st = check_build_variant(v, bpp, sat_sq != nullptr, who))) return st;
     const satk::BuildVariant &var = satk::build_variant(v);
     satk::BuildDesc d{};
     const int strip_h = choose_strip_h(v, H, bpp, sat_sq != nullptr);
@@ -444,15 +476,15 @@ size_t sat_batch_workspace_bytes(const sat_batch_item *items, int32_t n, sat_dty
         if (items[i].H < 1 || items[i].W < 1 || items[i].H > kMaxDim || items[i].W > kMaxDim) return 0;
         rows += items[i].H;
     }
-    size_t words_any[2] = {0, 0};
-    for (int al = 0; al < 2; ++al) {
-        const int v = choose_build_variant(rows, n, bytes_of(pixel_type), with_sq != 0, al != 0);
+    for (int align : {16, 4, 1}) {   // whichever variant the rows' alignment selects
+        const int v = choose_build_variant(rows, n, bytes_of(pixel_type), with_sq != 0, align);
         if (v < 0 || v >= satk::build_variant_count()) return 0;
         const satk::BuildVariant &var = satk::build_variant(v);
+        size_t w = 0;
         for (int i = 0; i < n; ++i)
-            words_any[al] += static_cast<size_t>(state_words_for(var, items[i].H, items[i].W, with_sq != 0, var.th()));
+            w += static_cast<size_t>(state_words_for(var, items[i].H, items[i].W, with_sq != 0, var.th()));
+        if (w > words) words = w;
     }
-    words = words_any[0] > words_any[1] ? words_any[0] : words_any[1];
     const size_t descs = round256(static_cast<size_t>(n) *
                                   (sizeof(satk::BuildDesc) > sizeof(satk::GatherDesc) ? sizeof(satk::BuildDesc)
                                                                                       : sizeof(satk::GatherDesc)));
@@ -499,10 +531,13 @@ sat_status sat_build_batched(const sat_batch_item *items, int32_t n, sat_dtype p
         outs.push_back(a);
         if (b.lo != b.hi) outs.push_back(b);
     }
-    bool aligned = true;
-    for (int i = 0; i < n; ++i) aligned = aligned && rows_aligned4(items[i].image, items[i].image_pitch, bpp);
-    const int v = choose_build_variant(rows, n, bpp, with_sq, aligned);
-    if (v < 0 || v >= satk::build_variant_count()) return fail(SAT_ERR_ARG, "%s: forced variant out of range", who);
+    int align = 16;
+    for (int i = 0; i < n; ++i) {
+        const int a = row_align(items[i].image, items[i].image_pitch, bpp);
+        if (a < align) align = a;
+    }
+    const int v = choose_build_variant(rows, n, bpp, with_sq, align);
+    if (sat_status st = check_build_variant(v, bpp, with_sq, who)) return st;
     const satk::BuildVariant &var = satk::build_variant(v);
     std::vector<satk::BuildDesc> d(n);
     int64_t off = 0, items_total = 0;
@@ -611,6 +646,13 @@ const char *sat_variant_name(int32_t kind, int32_t index) {
     if (kind == 0 && index >= 0 && index < satk::build_variant_count()) return satk::build_variant(index).name;
     if (kind == 1 && index >= 0 && index < satk::gather_variant_count()) return satk::gather_variant_name(index);
     return "";
+}
+
+int32_t sat_variant_supported(int32_t kind, int32_t index, sat_dtype pixel_type, int32_t with_sq) {
+    if (index < 0 || index >= sat_variant_count(kind)) return 0;
+    if (pixel_type != SAT_U8 && pixel_type != SAT_U16) return 0;
+    if (kind == 1) return 1;
+    return satk::build_variant_capacity(index, bytes_of(pixel_type), with_sq != 0) > 0 ? 1 : 0;
 }
 
 sat_status sat_force_variant(int32_t kind, int32_t index) {

@@ -661,7 +661,7 @@ struct Build {
 //   - the compute waves only read LDS, scan and store, so they never wait on memory.
 // One workgroup barrier per block separates "helper prepared block b+1" from "compute waves
 // finished block b".
-template <typename T, bool SQ, int PX, int RW, int NW, int WIN>
+template <typename T, bool SQ, int PX, int RW, int NW, int WIN, bool NTS = false>
 struct Build2 {
     using B1 = Build<T, SQ, PX, RW, NW, MODE_LOOKBACK>;   // shared helpers (column map, lookback)
     static constexpr int TH = RW * NW;
@@ -708,8 +708,9 @@ struct Build2 {
             __builtin_amdgcn_make_buffer_rsrc(const_cast<unsigned char *>(base), 0, static_cast<int>(recs), kRsrcWord3);
         const uint32_t lb = static_cast<uint32_t>(lane) * VB;
         const uint32_t voff = (lb / ROWB) * pitchb + lb % ROWB;
+        const int nch = (nvalid * ROWB + CB - 1) / CB;      // chunks holding valid rows
 #pragma unroll 4
-        for (int c = 0; c < TILEB / CB; ++c) {
+        for (int c = 0; c < nch; ++c) {
             const uint32_t cb = static_cast<uint32_t>(c) * CB;
             const uint32_t so = (cb / ROWB) * pitchb + cb % ROWB;
             auto *dst = (__attribute__((address_space(3))) void *)(sm.tile[buf] + c * (CB / 4));
@@ -729,7 +730,7 @@ struct Build2 {
             const T *img = static_cast<const T *>(d.img);
             T *tile = reinterpret_cast<T *>(sm.tile[buf]);
 #pragma unroll 4
-            for (int e = lane; e < TH * BW; e += 64) {
+            for (int e = lane; e < nvalid * BW; e += 64) {
                 const int row = e / BW, col = e % BW;
                 const int64_t y = ys + row, x = xb + col;
                 tile[e] = (row < nvalid && x < d.W) ? img[y * d.ipitch + x] : static_cast<T>(0);
@@ -743,7 +744,7 @@ struct Build2 {
     // Helper wave: column sums of tile `buf` per compute wave and for the strip, the lookback for
     // this block, and the results in LDS buffer `buf` for the compute waves.
     static __device__ void prepare(const BuildDesc &d, Smem &sm, int buf, int64_t xb, int strip, int nvalid,
-                                   int lane, uint64_t *state, unsigned int *fault) {
+                                   int rw, int lane, uint64_t *state, unsigned int *fault) {
         uint64_t a[PX], aq[PX];
 #pragma unroll
         for (int p = 0; p < PX; ++p) { a[p] = 0; aq[p] = 0; }
@@ -753,10 +754,10 @@ struct Build2 {
             QT csq[PX];
 #pragma unroll
             for (int p = 0; p < PX; ++p) { cs[p] = 0; csq[p] = 0; }
-            const int r_end = nvalid - w * RW < RW ? nvalid - w * RW : RW;
+            const int r_end = nvalid - w * rw < rw ? nvalid - w * rw : rw;
 #pragma unroll 2
             for (int r = 0; r < r_end; ++r) {
-                const T *row = tile + (w * RW + r) * BW;
+                const T *row = tile + (w * rw + r) * BW;
 #pragma unroll
                 for (int sb = 0; sb < NS; ++sb) {
                     uint32_t pair;
@@ -802,7 +803,7 @@ struct Build2 {
     }
 
     // Compute wave: the rows of block (buf, xb).
-    static __device__ void compute(const BuildDesc &d, const Smem &sm, int buf, int64_t xb, int wave, int lane,
+    static __device__ void compute(const BuildDesc &d, const Smem &sm, int buf, int64_t xb, int wave, int rw, int lane,
                                    int rows_ok, uint64_t *S_w, uint64_t *Q_w, uint32_t pitch_bytes,
                                    uint64_t &lrow, uint64_t &lrow_q, uint64_t &ucarry, uint64_t &ucarry_q) {
         uint64_t u[PX], uq[PX];
@@ -839,19 +840,19 @@ struct Build2 {
         }
         const bool vec = d.sat_vec && xb + BW <= d.W;
         const uint32_t row_recs = static_cast<uint32_t>((d.W - xb) * 8);
-        const uint32_t *tile = sm.tile[buf];
+        const uint32_t *tile = sm.tile[buf] + wave * rw * ROWB / 4;   // this wave's first row
         if (vec) {
-            lrow += rows<uint32_t, false, true>(tile, wave, lane, u, lrow, S_w + xb, rows_ok, row_recs, pitch_bytes);
-            if (SQ) lrow_q += rows<QT, true, true>(tile, wave, lane, uq, lrow_q, Q_w + xb, rows_ok, row_recs, pitch_bytes);
+            lrow += rows<uint32_t, false, true>(tile, lane, u, lrow, S_w + xb, rows_ok, row_recs, pitch_bytes);
+            if (SQ) lrow_q += rows<QT, true, true>(tile, lane, uq, lrow_q, Q_w + xb, rows_ok, row_recs, pitch_bytes);
         } else {
-            lrow += rows<uint32_t, false, false>(tile, wave, lane, u, lrow, S_w + xb, rows_ok, row_recs, pitch_bytes);
-            if (SQ) lrow_q += rows<QT, true, false>(tile, wave, lane, uq, lrow_q, Q_w + xb, rows_ok, row_recs, pitch_bytes);
+            lrow += rows<uint32_t, false, false>(tile, lane, u, lrow, S_w + xb, rows_ok, row_recs, pitch_bytes);
+            if (SQ) lrow_q += rows<QT, true, false>(tile, lane, uq, lrow_q, Q_w + xb, rows_ok, row_recs, pitch_bytes);
         }
     }
 
-    // Rows of one table (same scheme as Build::rows_pass, reading the given LDS tile).
+    // Rows of one table (same scheme as Build::rows_pass); `tile` points at the wave's first row.
     template <typename ST, bool SQUARE, bool VEC>
-    static __device__ __forceinline__ uint64_t rows(const uint32_t *tile, int wave, int lane, const uint64_t (&u)[PX],
+    static __device__ __forceinline__ uint64_t rows(const uint32_t *tile, int lane, const uint64_t (&u)[PX],
                                                     uint64_t lcarry, uint64_t *blk0, int rows_ok, uint32_t row_recs,
                                                     uint32_t pitch_bytes) {
         uint64_t acc[PX];
@@ -864,9 +865,9 @@ struct Build2 {
         const i32x4 rs_blk = make_rsrc(blk0, VEC ? blk_recs : 0);
         const char *rowp = reinterpret_cast<const char *>(blk0);
         uint32_t roff = 0;
-        const T *trow = reinterpret_cast<const T *>(tile) + wave * RW * BW + 2 * lane;
+        const T *trow = reinterpret_cast<const T *>(tile) + 2 * lane;
 #pragma unroll 1
-        for (int r = 0; r < RW; ++r) {
+        for (int r = 0; r < nvalid; ++r) {
             uint64_t base = readlane(lcarry, r);
             const __amdgpu_buffer_rsrc_t rs_row = __builtin_amdgcn_make_buffer_rsrc(
                 const_cast<char *>(rowp), 0, (!VEC && r < rows_ok) ? static_cast<int>(row_recs) : 0, kRsrcWord3);
@@ -886,14 +887,14 @@ struct Build2 {
                 acc[2 * sb + 1] += b + pair;
                 const uint64_t o0 = u[2 * sb] + acc[2 * sb], o1 = u[2 * sb + 1] + acc[2 * sb + 1];
                 if (VEC) {
-                    store16_rsrc(u32x4{static_cast<uint32_t>(o0), static_cast<uint32_t>(o0 >> 32),
-                                       static_cast<uint32_t>(o1), static_cast<uint32_t>(o1 >> 32)},
-                                 rs_blk, voff + sb * 1024, roff);
+                    store16_rsrc<NTS>(u32x4{static_cast<uint32_t>(o0), static_cast<uint32_t>(o0 >> 32),
+                                            static_cast<uint32_t>(o1), static_cast<uint32_t>(o1 >> 32)},
+                                      rs_blk, voff + sb * 1024, roff);
                 } else {
                     __builtin_amdgcn_raw_buffer_store_b64(u32x2{static_cast<uint32_t>(o0), static_cast<uint32_t>(o0 >> 32)},
-                                                          rs_row, voff + sb * 1024, 0, 0);
+                                                          rs_row, voff + sb * 1024, 0, NTS ? 2 : 0);
                     __builtin_amdgcn_raw_buffer_store_b64(u32x2{static_cast<uint32_t>(o1), static_cast<uint32_t>(o1 >> 32)},
-                                                          rs_row, voff + sb * 1024 + 8, 0, 0);
+                                                          rs_row, voff + sb * 1024 + 8, 0, NTS ? 2 : 0);
                 }
                 base += readlane(incl, 63);
             }
@@ -909,10 +910,12 @@ struct Build2 {
         const int lane = threadIdx.x & 63;
         const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
         const bool helper = wave == HELPER;
-        const int64_t ys = static_cast<int64_t>(strip_idx) * TH;
-        const int nvalid = static_cast<int>(d.H - ys < TH ? d.H - ys : TH);
-        const int64_t yw = ys + (helper ? 0 : wave) * RW;
-        const int rows_ok = helper ? 0 : (nvalid - wave * RW < RW ? nvalid - wave * RW : RW);
+        const int th = d.strip_h, rw = d.wave_rows;                       // th <= TH, rw <= RW
+        const int64_t ys = static_cast<int64_t>(strip_idx) * th;
+        const int nvalid = static_cast<int>(d.H - ys < th ? d.H - ys : th);
+        const int64_t yw = ys + (helper ? 0 : wave) * rw;
+        const int left = nvalid - wave * rw;
+        const int rows_ok = helper ? 0 : (left < rw ? (left > 0 ? left : 0) : rw);
         uint64_t *S_w = d.S + yw * d.spitch;
         uint64_t *Q_w = SQ ? d.Q + yw * d.spitch : nullptr;
         const uint32_t pitch_bytes = static_cast<uint32_t>(d.spitch * 8);
@@ -921,7 +924,7 @@ struct Build2 {
         if (helper) {
             load_tile(d, sm, 0, ys, 0, nvalid, lane);
             wait_loads();
-            prepare(d, sm, 0, 0, strip_idx, nvalid, lane, state, fault);
+            prepare(d, sm, 0, 0, strip_idx, nvalid, rw, lane, state, fault);
         }
         barrier();
         if (helper && d.nblocks > 1) load_tile(d, sm, 1, ys, BW, nvalid, lane);
@@ -929,10 +932,10 @@ struct Build2 {
             const int buf = b & 1;
             const int64_t xb = static_cast<int64_t>(b) * BW;
             if (!helper) {
-                compute(d, sm, buf, xb, wave, lane, rows_ok, S_w, Q_w, pitch_bytes, lrow, lrow_q, ucarry, ucarry_q);
+                compute(d, sm, buf, xb, wave, rw, lane, rows_ok, S_w, Q_w, pitch_bytes, lrow, lrow_q, ucarry, ucarry_q);
             } else if (b + 1 < d.nblocks) {
                 wait_loads();
-                prepare(d, sm, buf ^ 1, xb + BW, strip_idx, nvalid, lane, state, fault);
+                prepare(d, sm, buf ^ 1, xb + BW, strip_idx, nvalid, rw, lane, state, fault);
             }
             barrier();
             if (helper && b + 2 < d.nblocks) load_tile(d, sm, buf, ys, xb + 2 * BW, nvalid, lane);
@@ -940,10 +943,10 @@ struct Build2 {
     }
 };
 
-template <typename T, bool SQ, int PX, int RW, int NW, int WIN>
+template <typename T, bool SQ, int PX, int RW, int NW, int WIN, bool NTS>
 __global__ __launch_bounds__((NW + 1) * 64) void build2_kernel(const BuildDesc *__restrict__ many, int n,
                                                                long long total_items, uint64_t *state, BuildCtrl *ctrl) {
-    using B = Build2<T, SQ, PX, RW, NW, WIN>;
+    using B = Build2<T, SQ, PX, RW, NW, WIN, NTS>;
     __shared__ typename B::Smem sm;
     for (;;) {
         if (threadIdx.x == 0) sm.ticket = static_cast<long long>(atomicAdd(&ctrl->ticket, 1ull));
@@ -1062,7 +1065,9 @@ __global__ __launch_bounds__(256) void colscan_kernel(uint64_t *state, long long
     X(6, "helper_px4_rw16_nw4", 4, 16, 4, MODE_HELPER, 1, 0, false)                \
     X(7, "helper_reduce_scan_px4_rw16_nw4", 4, 16, 4, MODE_HELPER, 0, 0, false)    \
     X(8, "lookback_nt_px8_rw16_nw4", 8, 16, 4, MODE_LOOKBACK, 1, 1, true)          \
-    X(9, "lookback_nt_px4_rw16_nw4", 4, 16, 4, MODE_LOOKBACK, 1, 1, true)
+    X(9, "lookback_nt_px4_rw16_nw4", 4, 16, 4, MODE_LOOKBACK, 1, 1, true)          \
+    X(10, "helper_nt_px4_rw16_nw4", 4, 16, 4, MODE_HELPER, 1, 1, true)             \
+    X(11, "helper_nt_px8_rw12_nw4", 8, 12, 4, MODE_HELPER, 1, 1, true)
 
 const BuildVariant kVariants[] = {
 #define SAT_X(i, name, px, rw, nw, mode, win, adapt, nt) {name, px, rw, nw, mode},
@@ -1085,60 +1090,79 @@ int resident_capacity(const void *kernel, int threads) {
     return cus * per_cu;
 }
 
+// Static LDS of a variant for one pixel type; a variant whose workgroup state exceeds the 160 KiB
+// of a compute unit is not instantiated for that pixel type (capacity 0, launch refused).
+constexpr size_t kLdsBytes = 160 * 1024;
+template <typename T, bool SQ, int PX, int RW, int NW, int MODE, int WIN, bool NT>
+constexpr bool lds_fits() {
+    if constexpr (MODE == MODE_HELPER) return sizeof(typename Build2<T, SQ, PX, RW, NW, WIN, NT>::Smem) <= kLdsBytes;
+    else return sizeof(typename Build<T, SQ, PX, RW, NW, MODE, NT>::Smem) <= kLdsBytes;
+}
+
 template <typename T, bool SQ, int PX, int RW, int NW, int MODE, int WIN, bool NT>
 int capacity_typed() {
-    static int cap = 0;   // per instantiation; the library drives one device model
-    if (cap == 0) {
-        if constexpr (MODE == MODE_HELPER)
-            cap = resident_capacity(reinterpret_cast<const void *>(&build2_kernel<T, SQ, PX, RW, NW, WIN>), (NW + 1) * 64);
-        else
-            cap = resident_capacity(reinterpret_cast<const void *>(&build_kernel<T, SQ, PX, RW, NW, MODE, NT>), NW * 64);
+    if constexpr (!lds_fits<T, SQ, PX, RW, NW, MODE, WIN, NT>()) {
+        return 0;
+    } else {
+        static int cap = 0;   // per instantiation; the library drives one device model
+        if (cap == 0) {
+            if constexpr (MODE == MODE_HELPER)
+                cap = resident_capacity(reinterpret_cast<const void *>(&build2_kernel<T, SQ, PX, RW, NW, WIN, NT>),
+                                        (NW + 1) * 64);
+            else
+                cap = resident_capacity(reinterpret_cast<const void *>(&build_kernel<T, SQ, PX, RW, NW, MODE, NT>),
+                                        NW * 64);
+        }
+        return cap;
     }
-    return cap;
 }
 
 template <typename T, bool SQ, int PX, int RW, int NW, int MODE, int WIN, bool NT>
 hipError_t launch_typed(const BuildDesc *descs, int n, const BuildDesc *dev_descs, int64_t total_items,
                         void *workspace, int64_t state_words, hipStream_t stream) {
-    BuildCtrl *ctrl = static_cast<BuildCtrl *>(workspace);
-    uint64_t *state = reinterpret_cast<uint64_t *>(static_cast<char *>(workspace) + sizeof(BuildCtrl));
-    BuildDesc *slot = n == 1 ? &ctrl->one : nullptr;
-    const BuildDesc *table = n == 1 ? slot : dev_descs;
-    constexpr int TH = RW * NW;
-    constexpr bool kPrepass = MODE == MODE_REDUCE_SCAN || (MODE == MODE_HELPER && WIN == 0);
-    if (!kPrepass) {
-        const long long pairs = (state_words + 1) / 2;
-        const long long blocks = pairs > 0 ? (pairs + 255) / 256 : 1;
-        const unsigned grid = static_cast<unsigned>(blocks < 8192 ? blocks : 8192);
-        hipLaunchKernelGGL(clear_kernel, dim3(grid), dim3(256), 0, stream, state,
-                           static_cast<long long>(state_words), ctrl, descs[0], slot);
+    if constexpr (!lds_fits<T, SQ, PX, RW, NW, MODE, WIN, NT>()) {
+        return hipErrorInvalidConfiguration;
     } else {
-        hipLaunchKernelGGL(clear_kernel, dim3(1), dim3(256), 0, stream, state, 0ll, ctrl, descs[0], slot);
-        for (int i = 0; i < n; ++i) {
-            const BuildDesc &d = descs[i];
-            const int64_t xb = (d.Wp / PX + 255) / 256;
-            hipLaunchKernelGGL((colsum_kernel<T, SQ, PX, TH>), dim3(static_cast<unsigned>(xb), d.nstrips),
-                               dim3(256), 0, stream, d, state);
-            const unsigned cb = static_cast<unsigned>((d.Wp + 255) / 256);
-            hipLaunchKernelGGL(colscan_kernel, dim3(cb), dim3(256), 0, stream, state,
-                               static_cast<long long>(d.state_off), static_cast<long long>(d.Wp), d.nstrips);
-            if (SQ)
+        BuildCtrl *ctrl = static_cast<BuildCtrl *>(workspace);
+        uint64_t *state = reinterpret_cast<uint64_t *>(static_cast<char *>(workspace) + sizeof(BuildCtrl));
+        BuildDesc *slot = n == 1 ? &ctrl->one : nullptr;
+        const BuildDesc *table = n == 1 ? slot : dev_descs;
+        constexpr int TH = RW * NW;
+        constexpr bool kPrepass = MODE == MODE_REDUCE_SCAN || (MODE == MODE_HELPER && WIN == 0);
+        if (!kPrepass) {
+            const long long pairs = (state_words + 1) / 2;
+            const long long blocks = pairs > 0 ? (pairs + 255) / 256 : 1;
+            const unsigned grid = static_cast<unsigned>(blocks < 8192 ? blocks : 8192);
+            hipLaunchKernelGGL(clear_kernel, dim3(grid), dim3(256), 0, stream, state,
+                               static_cast<long long>(state_words), ctrl, descs[0], slot);
+        } else {
+            hipLaunchKernelGGL(clear_kernel, dim3(1), dim3(256), 0, stream, state, 0ll, ctrl, descs[0], slot);
+            for (int i = 0; i < n; ++i) {
+                const BuildDesc &d = descs[i];
+                const int64_t xb = (d.Wp / PX + 255) / 256;
+                hipLaunchKernelGGL((colsum_kernel<T, SQ, PX, TH>), dim3(static_cast<unsigned>(xb), d.nstrips),
+                                   dim3(256), 0, stream, d, state);
+                const unsigned cb = static_cast<unsigned>((d.Wp + 255) / 256);
                 hipLaunchKernelGGL(colscan_kernel, dim3(cb), dim3(256), 0, stream, state,
-                                   static_cast<long long>(d.state_q_off), static_cast<long long>(d.Wp),
-                                   d.nstrips);
+                                   static_cast<long long>(d.state_off), static_cast<long long>(d.Wp), d.nstrips);
+                if (SQ)
+                    hipLaunchKernelGGL(colscan_kernel, dim3(cb), dim3(256), 0, stream, state,
+                                       static_cast<long long>(d.state_q_off), static_cast<long long>(d.Wp),
+                                       d.nstrips);
+            }
         }
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        const int cap = capacity_typed<T, SQ, PX, RW, NW, MODE, WIN, NT>();
+        const int64_t grid = total_items < cap ? total_items : cap;
+        if constexpr (MODE == MODE_HELPER)
+            hipLaunchKernelGGL((build2_kernel<T, SQ, PX, RW, NW, WIN, NT>), dim3(static_cast<unsigned>(grid)),
+                               dim3((NW + 1) * 64), 0, stream, table, n, static_cast<long long>(total_items), state, ctrl);
+        else
+            hipLaunchKernelGGL((build_kernel<T, SQ, PX, RW, NW, MODE, NT>), dim3(static_cast<unsigned>(grid)),
+                               dim3(NW * 64), 0, stream, table, n, static_cast<long long>(total_items), state, ctrl);
+        return hipGetLastError();
     }
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    const int cap = capacity_typed<T, SQ, PX, RW, NW, MODE, WIN, NT>();
-    const int64_t grid = total_items < cap ? total_items : cap;
-    if constexpr (MODE == MODE_HELPER)
-        hipLaunchKernelGGL((build2_kernel<T, SQ, PX, RW, NW, WIN>), dim3(static_cast<unsigned>(grid)),
-                           dim3((NW + 1) * 64), 0, stream, table, n, static_cast<long long>(total_items), state, ctrl);
-    else
-        hipLaunchKernelGGL((build_kernel<T, SQ, PX, RW, NW, MODE, NT>), dim3(static_cast<unsigned>(grid)),
-                           dim3(NW * 64), 0, stream, table, n, static_cast<long long>(total_items), state, ctrl);
-    return hipGetLastError();
 }
 
 template <typename T, bool SQ>

@@ -157,3 +157,28 @@ def test_variants(lib):
     assert lib.sat_force_variant(2, 0) == SAT_ERR_ARG
     assert lib.sat_force_variant(0, 1) == SAT_OK
     assert lib.sat_force_variant(0, -1) == SAT_OK
+
+
+def test_variant_supported(lib):
+    nb, ng = lib.sat_variant_count(0), lib.sat_variant_count(1)
+    names = [lib.sat_variant_name(0, i).decode() for i in range(nb)]
+    for i in range(nb):
+        assert lib.sat_variant_supported(0, i, SAT_U8, 0) == 1          # every variant builds 8-bit tables
+    px8 = names.index("helper_nt_px8_rw12_nw4")
+    # two 48-row tiles of 16-bit pixels, four waves' 64-bit squared column sums: beyond 160 KiB of LDS
+    assert lib.sat_variant_supported(0, px8, SAT_U16, 1) == 0
+    assert lib.sat_variant_supported(0, px8, SAT_U16, 0) == 1
+    assert lib.sat_variant_supported(0, px8, SAT_U8, 1) == 1
+    assert all(lib.sat_variant_supported(1, i, SAT_U16, 1) == 1 for i in range(ng))
+    assert lib.sat_variant_supported(0, nb, SAT_U8, 0) == 0
+    assert lib.sat_variant_supported(0, -1, SAT_U8, 0) == 0
+    assert lib.sat_variant_supported(2, 0, SAT_U8, 0) == 0
+    assert lib.sat_variant_supported(0, 0, SAT_U32, 0) == 0
+    # a build forced to a variant without an instantiation for the pixel type is refused
+    assert lib.sat_force_variant(0, px8) == SAT_OK
+    try:
+        ws = lib.sat_build_workspace_bytes(64, 64, SAT_U16, 1)
+        st = lib.sat_build(IMG, SAT_U16, 64, 64, 64, SAT, SQ, 64, WS, ws, None)
+        assert st == SAT_ERR_ARG and b"does not fit the LDS" in lib.sat_last_error()
+    finally:
+        lib.sat_force_variant(0, -1)

@@ -149,23 +149,42 @@ def test_max_pixel_values():
 # ------------------------------------------------------------------ variants, stress, fault word
 
 def test_every_build_variant_bit_exact():
+    """Every build variant on 16-bit pixels with squares (5200-byte rows) and on 8-bit pixels with
+    8-byte aligned rows (2600 bytes: dword DMA in the helper-wave variants) and 16-byte aligned
+    rows (pitch 2608); a variant not compiled for a pixel type is refused with SAT_ERR_ARG."""
+    from paper_2410_16291_amd._lib import SAT_ERR_ARG, SatError
     rng = np.random.default_rng(9)
     img_np = rng.integers(0, 65536, (1100, 2600)).astype(np.uint16)
     ref_S, ref_Q = oracle.sat(img_np, squares=True)
     img = to_device(img_np)
+    img8_np = (img_np & 0xFF).astype(np.uint8)
+    ref8_S, ref8_Q = oracle.sat(img8_np, squares=True)
+    img8s = [to_device(img8_np), padded_image(img8_np, 2608, 0)]
     names = api.variants(0)
+    u16_sq, u8, u8_sq = set(api.variants(0, "u16", True)), set(api.variants(0, "u8")), set(api.variants(0, "u8", True))
+    assert u8 == set(names)                                   # every variant runs plain 8-bit builds
     try:
         for v, name in enumerate(names):
             print("case: build variant", name, flush=True)
             api.force_variant(0, v)
             ws = torch.empty(api.build_workspace_bytes(1100, 2600, 2, True), dtype=torch.uint8, device="cuda:0")
-            S, Q = api.sat_build(img, squares=True, ws=ws)
-            api.workspace_check(ws)
-            assert np.array_equal(to_host(S), ref_S), name
-            assert np.array_equal(to_host(Q), ref_Q), name
-            img8 = to_device((img_np & 0xFF).astype(np.uint8))
-            S8 = api.sat_build(img8, ws=ws)
-            assert np.array_equal(to_host(S8), oracle.sat((img_np & 0xFF).astype(np.uint8))), name
+            if name in u16_sq:
+                S, Q = api.sat_build(img, squares=True, ws=ws)
+                api.workspace_check(ws)
+                assert np.array_equal(to_host(S), ref_S), name
+                assert np.array_equal(to_host(Q), ref_Q), name
+            else:
+                with pytest.raises(SatError) as e:
+                    api.sat_build(img, squares=True, ws=ws)
+                assert e.value.status == SAT_ERR_ARG
+            for im in img8s:
+                S8 = api.sat_build(im, ws=ws)
+                assert np.array_equal(to_host(S8), ref8_S), name
+                if name in u8_sq:
+                    S8, Q8 = api.sat_build(im, squares=True, ws=ws)
+                    api.workspace_check(ws)
+                    assert np.array_equal(to_host(S8), ref8_S), name
+                    assert np.array_equal(to_host(Q8), ref8_Q), name
     finally:
         api.force_variant(0, -1)
 
@@ -244,9 +263,9 @@ def test_balanced_strip_heights_tall_image():
         img = to_device(img_np)
         names = api.variants(0)
         try:
-            for v, name in enumerate(names):
+            for name in api.variants(0, "u8" if dtype == np.uint8 else "u16"):
                 print("case: tall image", np.dtype(dtype).name, name, flush=True)
-                api.force_variant(0, v)
+                api.force_variant(0, names.index(name))
                 ws = torch.empty(api.build_workspace_bytes(33001, 523, 1 if dtype == np.uint8 else 2, False),
                                  dtype=torch.uint8, device="cuda:0")
                 S = api.sat_build(img, ws=ws)
@@ -388,7 +407,7 @@ def test_autotuned_batch_matches_oracle(tmp_path):
     choice = tuner.tune_batch(imgs, squares=True, win=(32, 48), stride=2)
     print("case: autotune choice", choice["build"], choice["gather"], flush=True)
     assert choice["build"] in api.variants(0) and choice["gather"] in api.variants(1)
-    assert set(choice["build_ms"]) == set(api.variants(0))
+    assert set(choice["build_ms"]) == set(api.variants(0, "u16", True))
     again = autotune.Tuner(path=str(tmp_path / "tune.json")).tune_batch(imgs, squares=True, win=(32, 48), stride=2)
     assert again["build"] == choice["build"] and again["gather_ms"] == choice["gather_ms"]    # from the cache
     tables = batch.build_batched(imgs, True, variant=choice["build"])
@@ -474,7 +493,8 @@ def test_full_scale_70000x85000_sampled():
     dev = torch.device("cuda:0")
     print("case: full scale 70000x85000, host mask", flush=True)
     img_np = synth.thomas_mask(H, W, seed=2)
-    img = torch.from_numpy(img_np).to(dev)
+    img = api.empty_image(H, W, torch.uint8, dev)          # the bench's layout: rows on 128-byte lines
+    img.copy_(torch.from_numpy(img_np))
     S = api.empty_table(H, W, dev)
     ws = torch.empty(api.build_workspace_bytes(H, W, 1, False), dtype=torch.uint8, device=dev)
     api.sat_build(img, sat=S, ws=ws)
@@ -555,7 +575,7 @@ def test_batched_build_every_variant_with_squares():
     imgs_np = synth.uneven_batch(6, lo=60, hi=900, seed=26)
     imgs = [to_device(i) for i in imgs_np]
     refs = [oracle.sat(i, squares=True) for i in imgs_np]
-    for name in api.variants(0):
+    for name in api.variants(0, "u16", True):
         print("case: batched build", name, flush=True)
         tables = batch.build_batched(imgs, True, variant=name)
         torch.cuda.synchronize()
