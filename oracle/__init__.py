@@ -36,6 +36,11 @@ def _load():
         lib.oracle_mean_std.restype = None
         lib.oracle_coverage_total.argtypes = [_p, ctypes.c_int] + [_i64] * 6
         lib.oracle_coverage_total.restype = ctypes.c_uint64
+        lib.oracle_sat_power.argtypes = [_p, ctypes.c_int, _i64, _i64, _i64, ctypes.c_int, _p]
+        lib.oracle_window_powers.argtypes = [_p, ctypes.c_int] + [_i64] * 5 + [ctypes.c_int, _p]
+        lib.oracle_window_powers.restype = None
+        lib.oracle_moments.argtypes = [_p, _p, _p, _p, _i64, ctypes.c_uint64, _p, _p, _p, _p]
+        lib.oracle_moments.restype = None
         lib.oracle_stream.argtypes = ([_p, ctypes.c_int, _i64, _i64, _i64, ctypes.c_int, _i64, _p, _p,
                                        _i64, _p, _p, _p, _i64, _p, _p, _p])
         _lib = lib
@@ -172,3 +177,53 @@ def stream(img, windows, s, rows, sat_rows=(), squares=False):
         outs.append(out[pos:pos + n * o].reshape(n, o))
         pos += n * o
     return outs, sat_out, total.value
+
+
+# ---- higher window moments (tables of pixel powers; the method applied to I^k)
+
+def sat_power(img, k):
+    """Inclusive integral image of pixel^k (k = 1..4), uint64, wrapping mod 2^64."""
+    img, bpp, pitch = _image(img)
+    H, W = img.shape
+    T = np.empty((H, W), np.uint64)
+    if _load().oracle_sat_power(_ptr(img), bpp, H, W, pitch, int(k), _ptr(T)):
+        raise ValueError("oracle_sat_power rejected its arguments")
+    return T
+
+
+def window_powers(img, y0, x0, h, w, k):
+    """[sum of pixel^1, ..., sum of pixel^k] over one window, summed directly (mod 2^64)."""
+    img, bpp, pitch = _image(img)
+    out = np.zeros(k, np.uint64)
+    _load().oracle_window_powers(_ptr(img), bpp, pitch, y0, x0, h, w, int(k), _ptr(out))
+    return [int(v) for v in out]
+
+
+def moments(s1, s2, n, s3=None, s4=None):
+    """(mean, std, skew, kurt) in FP64 from exact window power sums over n pixels: population
+    moments, skewness m3/m2^1.5, excess kurtosis m4/m2^2 - 3 (NaN where m2 = 0); skew needs s3,
+    kurt needs s3 and s4 (None otherwise)."""
+    arrs = [np.ascontiguousarray(a, dtype=np.uint64) for a in (s1, s2)]
+    if s4 is not None and s3 is None:
+        raise ValueError("kurtosis needs s3 as well")
+    s3a = np.ascontiguousarray(s3, dtype=np.uint64) if s3 is not None else None
+    s4a = np.ascontiguousarray(s4, dtype=np.uint64) if s4 is not None else None
+    shape = arrs[0].shape
+    for a in [arrs[1], s3a, s4a]:
+        if a is not None and a.shape != shape:
+            raise ValueError("shape mismatch")
+    mean, std = np.empty(shape, np.float64), np.empty(shape, np.float64)
+    skew = np.empty(shape, np.float64) if s3a is not None else None
+    kurt = np.empty(shape, np.float64) if s4a is not None else None
+    _load().oracle_moments(_ptr(arrs[0]), _ptr(arrs[1]), _ptr(s3a) if s3a is not None else None,
+                           _ptr(s4a) if s4a is not None else None, arrs[0].size, int(n), _ptr(mean), _ptr(std),
+                           _ptr(skew) if skew is not None else None, _ptr(kurt) if kurt is not None else None)
+    return mean, std, skew, kurt
+
+
+def window_moments(img, h, w, s=1, k=4):
+    """Power sums (list of k uint64 arrays) and (mean, std, skew, kurt) of every window: tables of
+    pixel^1..pixel^k, corner lookups, then moments (skew needs k >= 3, kurt k = 4)."""
+    sums = [window_sum_sat(sat_power(img, j), h, w, s) for j in range(1, k + 1)]
+    stats = moments(sums[0], sums[1], h * w, sums[2] if k >= 3 else None, sums[3] if k >= 4 else None)
+    return sums, stats

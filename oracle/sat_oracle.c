@@ -238,3 +238,73 @@ int oracle_stream(const void *img, int bpp, int64_t H, int64_t W, int64_t pitch,
     free(T); free(next); free(row_base); free(out_base);
     return 0;
 }
+
+/* ---- Higher window moments from tables of pixel powers (the method applied to I^k).
+ *
+ * The paper lists further sliding-window statistics as future work (Sec. V) and builds every
+ * statistic it has from window sums (Sec. II-A, II-B).  The third and fourth moments are sums
+ * too: with S_k the window sum of pixel^k over n pixels, the central moments expand into the raw
+ * sums by the binomial theorem.  Readings: population moments (divisor n), skewness
+ * g1 = m3 / m2^(3/2), excess kurtosis g2 = m4 / m2^2 - 3, both undefined (NaN) when m2 = 0. */
+
+typedef __int128 i128;
+
+/* Integral image of pixel^k, k = 1..4 (k = 1, 2 give the tables of oracle_sat).  Wraps mod
+ * 2^64 exactly like oracle_sat.  Returns 0 on success. */
+int oracle_sat_power(const void *img, int bpp, int64_t H, int64_t W, int64_t pitch, int k, uint64_t *T) {
+    if (!img || !T || H < 1 || W < 1 || pitch < W || (bpp != 1 && bpp != 2) || k < 1 || k > 4) return 1;
+    for (int64_t y = 0; y < H; ++y) {
+        uint64_t run = 0;
+        for (int64_t x = 0; x < W; ++x) {
+            uint64_t v = pixel(img, bpp, pitch, y, x), p = v;
+            for (int j = 1; j < k; ++j) p *= v;
+            run += p;
+            T[y * W + x] = (y > 0 ? T[(y - 1) * W + x] : 0) + run;
+        }
+    }
+    return 0;
+}
+
+/* sums[j] = sum over the h x w window at (y0, x0) of pixel^(j+1), j < k, summed directly. */
+void oracle_window_powers(const void *img, int bpp, int64_t pitch, int64_t y0, int64_t x0, int64_t h,
+                          int64_t w, int k, uint64_t *sums) {
+    for (int j = 0; j < k; ++j) sums[j] = 0;
+    for (int64_t y = y0; y < y0 + h; ++y)
+        for (int64_t x = x0; x < x0 + w; ++x) {
+            uint64_t v = pixel(img, bpp, pitch, y, x), p = 1;
+            for (int j = 0; j < k; ++j) {
+                p *= v;
+                sums[j] += p;
+            }
+        }
+}
+
+/* Mean, std, skewness and excess kurtosis of `count` windows of n pixels from their exact power
+ * sums s1..s4 (s3, s4 may be NULL: skewness / kurtosis not computed).  With
+ *   A = n*S2 - S1^2                                   (= n^2 m2),
+ *   B = n^2*S3 - 3n*S1*S2 + 2*S1^3                    (= n^3 m3),
+ *   C = n^3*S4 - 4n^2*S1*S3 + 6n*S1^2*S2 - 3*S1^4     (= n^4 m4),
+ * formed exactly in 128-bit integers, each rounded to double once:
+ *   mean = S1/n,  std = sqrt(A)/n,  skew = B / (A*sqrt(A)),  kurt = (C - 3A^2) / (A*A).
+ * The caller keeps n and the pixel range small enough for the 128-bit terms. */
+void oracle_moments(const uint64_t *s1, const uint64_t *s2, const uint64_t *s3, const uint64_t *s4, int64_t count,
+                    uint64_t n, double *mean, double *std_dev, double *skew, double *kurt) {
+    const i128 N = (i128)n;
+    for (int64_t i = 0; i < count; ++i) {
+        const i128 a1 = (i128)s1[i], a2 = (i128)s2[i];
+        const i128 A = N * a2 - a1 * a1;
+        const double a = (double)A;
+        mean[i] = (double)s1[i] / (double)n;
+        std_dev[i] = sqrt(a) / (double)n;
+        if (skew) {
+            const i128 a3 = (i128)s3[i];
+            const i128 B = N * N * a3 - 3 * N * a1 * a2 + 2 * a1 * a1 * a1;
+            skew[i] = A == 0 ? NAN : (double)B / (a * sqrt(a));
+        }
+        if (kurt) {
+            const i128 a3 = (i128)s3[i], a4 = (i128)s4[i];
+            const i128 C = N * N * N * a4 - 4 * N * N * a1 * a3 + 6 * N * a1 * a1 * a2 - 3 * a1 * a1 * a1 * a1;
+            kurt[i] = A == 0 ? NAN : (double)(C - 3 * A * A) / (a * a);
+        }
+    }
+}
