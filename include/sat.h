@@ -166,6 +166,45 @@ sat_status sat_workspace_check(void *workspace, void *stream);
 /* Message for the last error returned on the calling thread (static storage, never NULL). */
 const char *sat_last_error(void);
 
+/* ---- Higher window moments: tables of pixel powers (the integral image of Sec. II-B applied to
+ * I^k) and sliding-window statistics beyond the mean and deviation, which the paper leaves to
+ * future work (Sec. V).  Every statistic here is a function of window sums of pixel^k. */
+
+/* Bytes of device workspace sat_build_powers needs (0 for invalid sizes, pixel types or k). */
+size_t sat_powers_workspace_bytes(int64_t H, int64_t W, sat_dtype pixel_type, int32_t k);
+
+/* Tables of pixel^1 .. pixel^k of an H x W image in one pass over it:
+ *   tables[p-1][y*sat_pitch + x] = sum_{i<=y, j<=x} image[i*image_pitch + j]^p      (mod 2^64),
+ * so k = 1 gives sat_build's sat and k = 2 its sat_sq.
+ * image: device, pixel_type SAT_U8 or SAT_U16, pitch image_pitch >= W elements.
+ * tables: HOST array of k device pointers, each H rows of sat_pitch >= W uint64_t; no two may
+ * overlap each other or the image.  k = 1..4.
+ * workspace: device, >= sat_powers_workspace_bytes(H, W, pixel_type, k) bytes, 16-byte aligned,
+ * scratch after the call (not shared by two builds in flight).
+ * Errors: SAT_ERR_ARG; SAT_ERR_OVERFLOW when a column total of some pixel^p can reach 2^62
+ * (H * max_pixel^p >= 2^62: always for 16-bit pixels and k = 4, above 16384 rows for k = 3);
+ * SAT_ERR_WORKSPACE; SAT_ERR_HIP. */
+sat_status sat_build_powers(const void *image, sat_dtype pixel_type, int64_t H, int64_t W, int64_t image_pitch,
+                            int32_t k, uint64_t *const *tables, int64_t sat_pitch, void *workspace,
+                            size_t workspace_bytes, void *stream);
+
+/* Window mean, population standard deviation, skewness and excess kurtosis of every window of
+ * the valid region from the tables of pixel^1..pixel^k (n = win_h*win_w, S_p = window sum of
+ * tables[p-1] by the corner lookup, exact):
+ *   A = n*S2 - S1^2,  B = n^2*S3 - 3n*S1*S2 + 2*S1^3,
+ *   C = n^3*S4 - 4n^2*S1*S3 + 6n*S1^2*S2 - 3*S1^4,
+ * exact in 128-bit integers, each rounded to double once;
+ *   mean = S1/n,  std = sqrt(A)/n,  skew = B / (A*sqrt(A)),  kurt = (C - 3*A^2) / (A*A),
+ * with skew and kurt NaN where A = 0 (a constant window).
+ * tables: HOST array of k device pointers (H x W, pitch sat_pitch); pixel_type (SAT_U8 or
+ * SAT_U16) bounds the pixels for the overflow checks.  Outputs: device doubles, out_h rows of
+ * out_pitch >= out_w, each may be NULL but not all; mean needs k >= 1, std 2, skew 3, kurt 4.
+ * Errors: SAT_ERR_ARG; SAT_ERR_WINDOW; SAT_ERR_OVERFLOW when a window sum of pixel^p could reach
+ * 2^64 or a numerator 2^127 (for 16-bit pixels, skewness needs n <= 65536); SAT_ERR_HIP. */
+sat_status window_moments(const uint64_t *const *tables, int32_t k, sat_dtype pixel_type, int64_t H, int64_t W,
+                          int64_t sat_pitch, int64_t win_h, int64_t win_w, int64_t stride, double *mean_out,
+                          double *std_out, double *skew_out, double *kurt_out, int64_t out_pitch, void *stream);
+
 /* Build and tuning introspection: number of compiled kernel variants of kind 0 (table build)
  * or 1 (window gather), the name of variant i, and the variant a later call on this thread
  * will use (-1 restores the built-in choice).  Used by the tile-shape tuner. */

@@ -68,6 +68,10 @@ def load(path: str = LIB_PATH):
             "sat_variant_name": (ctypes.c_char_p, [_i32, _i32]),
             "sat_force_variant": (_st, [_i32, _i32]),
             "sat_variant_supported": (_i32, [_i32, _i32, ctypes.c_int, _i32]),
+            "sat_powers_workspace_bytes": (_sz, [_i64, _i64, ctypes.c_int, _i32]),
+            "sat_build_powers": (_st, [_p, ctypes.c_int, _i64, _i64, _i64, _i32, _p, _i64, _p, _sz, _p]),
+            "window_moments": (_st, [_p, _i32, ctypes.c_int, _i64, _i64, _i64, _i64, _i64, _i64, _p, _p, _p, _p,
+                                     _i64, _p]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(lib, name)

@@ -210,6 +210,76 @@ def window_mean_std(S: torch.Tensor, Q: torch.Tensor, h: int, w: int, stride: in
     return s1, mean, std
 
 
+# ---------------------------------------------------------------- higher window moments
+
+MOMENTS = ("mean", "std", "skew", "kurt")    # statistic i needs the tables of pixel^1 .. pixel^(i+1)
+
+
+def powers_workspace_bytes(H: int, W: int, pixel_type: int, k: int) -> int:
+    n = _lib.load().sat_powers_workspace_bytes(H, W, pixel_type, k)
+    if n == 0:
+        raise ValueError("invalid size %dx%d, pixel type or k = %d" % (H, W, k))
+    return n
+
+
+def sat_build_powers(image: torch.Tensor, k: int, tables: Optional[List[torch.Tensor]] = None,
+                     ws: Optional[torch.Tensor] = None, stream: Optional[torch.cuda.Stream] = None) -> List[torch.Tensor]:
+    """Tables of pixel^1 .. pixel^k (k = 1..4) of a 2-D uint8/uint16 device image, one pass:
+    tables[p-1][y, x] = sum of image[:y+1, :x+1]^p (mod 2^64).  `tables`: k preallocated uint64
+    tables sharing one row pitch."""
+    _require_cuda(image, "image")
+    if image.dtype not in _PIXEL:
+        raise ValueError("image dtype must be uint8 or uint16")
+    H, W = image.shape
+    dev = image.device
+    if tables is None:
+        first = empty_table(H, W, dev)
+        tables = [first] + [empty_table(H, W, dev, first.stride(0)) for _ in range(k - 1)]
+    if len(tables) != k:
+        raise ValueError("need %d tables" % k)
+    for t in tables:
+        _require_cuda(t, "table")
+        if tuple(t.shape) != (H, W) or t.dtype != torch.uint64 or t.stride(0) != tables[0].stride(0):
+            raise ValueError("tables must be %d x %d uint64 sharing one row pitch" % (H, W))
+    ptype = _PIXEL[image.dtype]
+    wsb = ws if ws is not None else workspace(powers_workspace_bytes(H, W, ptype, k), dev, stream)
+    ptrs = (ctypes.c_void_p * k)(*[t.data_ptr() for t in tables])
+    check(_lib.load().sat_build_powers(image.data_ptr(), ptype, H, W, image.stride(0), k, ptrs, tables[0].stride(0),
+                                       wsb.data_ptr(), wsb.numel(), _stream_handle(dev, stream)))
+    return list(tables)
+
+
+def window_moments(tables: List[torch.Tensor], h: int, w: int, stride: int = 1, pixel_type: str = "u8",
+                   stats: Tuple[str, ...] = MOMENTS, outs: Optional[dict] = None,
+                   stream: Optional[torch.cuda.Stream] = None) -> dict:
+    """{name: float64 output} for `stats` (a subset of mean, std, skew, kurt: population moments,
+    skewness and excess kurtosis, NaN for constant windows) of every window, from the tables of
+    pixel^1 .. pixel^k (sat_build_powers; k at least the order of the highest statistic)."""
+    for t in tables:
+        _require_cuda(t, "table")
+        if t.shape != tables[0].shape or t.stride(0) != tables[0].stride(0):
+            raise ValueError("tables must share shape and row pitch")
+    bad = [s for s in stats if s not in MOMENTS]
+    if bad or not stats:
+        raise ValueError("stats must be a non-empty subset of %s" % (MOMENTS,))
+    H, W = tables[0].shape
+    oh, ow = out_shape(H, W, h, w, stride)
+    given = outs or {}
+    outs = {n: given[n] if n in given else empty_out(oh, ow, torch.float64, tables[0].device) for n in stats}
+    pitch = None
+    for name, t in outs.items():
+        _require_cuda(t, "out")
+        if tuple(t.shape) != (oh, ow) or t.dtype != torch.float64 or (pitch is not None and t.stride(0) != pitch):
+            raise ValueError("outputs must be %d x %d float64 sharing one row pitch" % (oh, ow))
+        pitch = t.stride(0)
+    k = len(tables)
+    ptrs = (ctypes.c_void_p * k)(*[t.data_ptr() for t in tables])
+    arg = [outs[n].data_ptr() if n in outs else None for n in MOMENTS]
+    check(_lib.load().window_moments(ptrs, k, _PIXCODE[pixel_type], H, W, tables[0].stride(0), h, w, stride,
+                                     arg[0], arg[1], arg[2], arg[3], pitch, _stream_handle(tables[0].device, stream)))
+    return {n: outs[n] for n in stats}
+
+
 def workspace_check(ws: torch.Tensor, stream: Optional[torch.cuda.Stream] = None) -> None:
     """Synchronise and raise if a build that used `ws` reported a lookback fault."""
     check(_lib.load().sat_workspace_check(ws.data_ptr(), _stream_handle(ws.device, stream)))

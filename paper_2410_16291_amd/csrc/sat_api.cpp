@@ -3,6 +3,7 @@
 // synchronous before the first HIP call, so every error path is testable without a GPU.
 #include "sat.h"
 
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -160,20 +161,22 @@ int choose_build_variant(int64_t total_rows, int n_images, int bpp, bool sq, int
     return align >= 4 ? kVarHelperPx4 : kVarShort;
 }
 
-// Strip height for one image: the variant's full height unless the strips would not fit the
+// Strip height of at most th rows for one image: th unless the strips would not fit the `cap`
 // resident workgroups in whole rounds; then the height that spreads them evenly over the fewest
 // rounds (a last round with few strips costs a whole strip sweep).
-int choose_strip_h(int v, int64_t H, int bpp, bool sq) {
-    const satk::BuildVariant &var = satk::build_variant(v);
-    const int th = var.th();
-    if (!satk::build_variant_adaptive(v)) return th;
-    const int64_t cap = satk::build_variant_capacity(v, bpp, sq);
+int balanced_strip_h(int64_t H, int th, int64_t cap) {
     const int64_t strips = (H + th - 1) / th;
     if (cap < 1 || strips <= cap) return th;
     const int64_t rounds = (strips + cap - 1) / cap;
     int64_t h = (H + rounds * cap - 1) / (rounds * cap);
     if (h < 1) h = 1;
     return static_cast<int>(h < th ? h : th);
+}
+
+int choose_strip_h(int v, int64_t H, int bpp, bool sq) {
+    const satk::BuildVariant &var = satk::build_variant(v);
+    if (!satk::build_variant_adaptive(v)) return var.th();
+    return balanced_strip_h(H, var.th(), satk::build_variant_capacity(v, bpp, sq));
 }
 
 // Lower bound of the strip height any variant may pick (for workspace sizing): with at least two
@@ -459,6 +462,147 @@ sat_status window_mean_std(const uint64_t *sat, const uint64_t *sat_sq, int64_t 
     const int64_t items = satk::plan_mean_std(v, &d, 1);
     if (items > 0xffffffffll) return fail(SAT_ERR_ARG, "%s: too many work items", who);
     hipError_t e = satk::launch_mean_std(v, &d, 1, nullptr, items, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, who);
+    return ok();
+}
+
+// ------------------------------------------------------------------ tables of pixel powers, moments
+
+namespace {
+
+// Geometry of the power build (for strip heights and state sizes): 2 pixels per lane, 16 rows per
+// wave, 4 compute waves.
+const satk::BuildVariant kPowVariant{"power_px2_rw16_nw4", 2, 16, 4, satk::MODE_HELPER};
+static_assert(2 * 64 == satk::kPowBlockW && 16 * 4 == satk::kPowStripH, "power build geometry");
+
+int64_t power_state_words(int64_t H, int64_t W, int k, int strip_h) {
+    const int64_t strips = (H + strip_h - 1) / strip_h;
+    const int64_t wp = (W + satk::kPowBlockW - 1) / satk::kPowBlockW * satk::kPowBlockW;
+    return (strips * wp * k + 1) & ~1ll;
+}
+
+// Largest pixel^p of the pixel type (p <= 4 fits 128 bits).
+unsigned __int128 max_pow(sat_dtype t, int p) {
+    unsigned __int128 r = 1;
+    for (int i = 0; i < p; ++i) r *= max_pixel(t);
+    return r;
+}
+
+}  // namespace
+
+size_t sat_powers_workspace_bytes(int64_t H, int64_t W, sat_dtype pixel_type, int32_t k) {
+    if (H < 1 || W < 1 || H > kMaxDim || W > kMaxDim) return 0;
+    if ((pixel_type != SAT_U8 && pixel_type != SAT_U16) || k < 1 || k > 4) return 0;
+    // the shortest strips the balanced height may pick are half the full height
+    return sizeof(satk::BuildCtrl) + 8 * static_cast<size_t>(power_state_words(H, W, k, satk::kPowStripH / 2));
+}
+
+sat_status sat_build_powers(const void *image, sat_dtype pixel_type, int64_t H, int64_t W, int64_t image_pitch,
+                            int32_t k, uint64_t *const *tables, int64_t sat_pitch, void *workspace,
+                            size_t workspace_bytes, void *stream) {
+    const char *who = "sat_build_powers";
+    if (!image || !tables) return fail(SAT_ERR_ARG, "%s: image and tables must be non-NULL", who);
+    if (pixel_type != SAT_U8 && pixel_type != SAT_U16)
+        return fail(SAT_ERR_ARG, "%s: pixel_type must be SAT_U8 or SAT_U16", who);
+    if (k < 1 || k > 4) return fail(SAT_ERR_ARG, "%s: k = %d must be 1..4", who, k);
+    sat_status st = check_dims(H, W, who);
+    if (st) return st;
+    const int bpp = bytes_of(pixel_type);
+    if ((st = check_pitch(image_pitch, W, H, bpp, who, "image"))) return st;
+    if ((st = check_pitch(sat_pitch, W, H, 8, who, "table"))) return st;
+    for (int p = 1; p <= k; ++p)
+        if (static_cast<unsigned __int128>(H) * max_pow(pixel_type, p) >= (static_cast<unsigned __int128>(1) << 62))
+            return fail(SAT_ERR_OVERFLOW, "%s: %lld rows of pixel^%d are too many for exact 62-bit column totals", who,
+                        (long long)H, p);
+    Span sp[5];
+    sp[0] = span(image, H, image_pitch, W, bpp);
+    for (int p = 0; p < k; ++p) {
+        if (!tables[p]) return fail(SAT_ERR_ARG, "%s: tables[%d] must be non-NULL", who, p);
+        sp[p + 1] = span(tables[p], H, sat_pitch, W, 8);
+        for (int q = 0; q <= p; ++q)
+            if (overlap(sp[p + 1], sp[q])) return fail(SAT_ERR_ARG, "%s: the image and tables must not overlap", who);
+    }
+    const size_t need = sat_powers_workspace_bytes(H, W, pixel_type, k);
+    if (!workspace || workspace_bytes < need)
+        return fail(SAT_ERR_WORKSPACE, "%s: workspace of %zu bytes is below the %zu needed", who, workspace_bytes,
+                    need);
+    if (reinterpret_cast<uintptr_t>(workspace) % 16) return fail(SAT_ERR_ARG, "%s: workspace must be 16-byte aligned", who);
+    const Span sw{reinterpret_cast<uintptr_t>(workspace), reinterpret_cast<uintptr_t>(workspace) + workspace_bytes};
+    for (int p = 0; p <= k; ++p)
+        if (overlap(sw, sp[p])) return fail(SAT_ERR_ARG, "%s: workspace overlaps an input or output", who);
+    const int cap = satk::power_build_capacity(bpp, k);
+    const int strip_h = balanced_strip_h(H, satk::kPowStripH, cap);
+    satk::BuildDesc d{};
+    fill_desc(d, kPowVariant, image, bpp, H, W, image_pitch, tables[0], k >= 2 ? tables[1] : nullptr, sat_pitch,
+              strip_h);
+    d.T3 = k >= 3 ? tables[2] : nullptr;
+    d.T4 = k >= 4 ? tables[3] : nullptr;
+    bool aligned = sat_pitch % 2 == 0;
+    for (int p = 0; p < k; ++p) aligned = aligned && reinterpret_cast<uintptr_t>(tables[p]) % 16 == 0;
+    d.sat_vec = aligned ? 1 : 0;
+    d.state_off = 0;
+    d.first_item = 0;
+    const int64_t words = power_state_words(H, W, k, strip_h);
+    hipError_t e = satk::launch_build_powers(bpp, k, d, workspace, words, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, who);
+    return ok();
+}
+
+sat_status window_moments(const uint64_t *const *tables, int32_t k, sat_dtype pixel_type, int64_t H, int64_t W,
+                          int64_t sat_pitch, int64_t win_h, int64_t win_w, int64_t stride, double *mean_out,
+                          double *std_out, double *skew_out, double *kurt_out, int64_t out_pitch, void *stream) {
+    const char *who = "window_moments";
+    if (!tables) return fail(SAT_ERR_ARG, "%s: tables must be non-NULL", who);
+    if (pixel_type != SAT_U8 && pixel_type != SAT_U16)
+        return fail(SAT_ERR_ARG, "%s: pixel_type must be SAT_U8 or SAT_U16", who);
+    const int order = kurt_out ? 4 : skew_out ? 3 : std_out ? 2 : mean_out ? 1 : 0;
+    if (order == 0) return fail(SAT_ERR_ARG, "%s: at least one output must be non-NULL", who);
+    if (k < order || k > 4)
+        return fail(SAT_ERR_ARG, "%s: %d tables given, the requested statistics need %d (at most 4)", who, k, order);
+    int64_t oh = 0, ow = 0;
+    sat_status st = validate_window(tables[0], H, W, sat_pitch, win_h, win_w, stride, who, &oh, &ow);
+    if (st) return st;
+    for (int p = 0; p < order; ++p)
+        if (!tables[p]) return fail(SAT_ERR_ARG, "%s: tables[%d] must be non-NULL", who, p);
+    // Window sums must be exact (below 2^64), and the 128-bit numerators must not overflow: their
+    // terms are bounded by 6 (n*m)^3 for the skewness and 17 (n*m)^4 for the kurtosis.
+    const uint64_t n = static_cast<uint64_t>(win_h) * static_cast<uint64_t>(win_w);
+    for (int p = 1; p <= order; ++p)
+        if (static_cast<unsigned __int128>(n) * max_pow(pixel_type, p) >= (static_cast<unsigned __int128>(1) << 64))
+            return fail(SAT_ERR_OVERFLOW, "%s: window sums of pixel^%d over %llu pixels can exceed 64 bits", who, p,
+                        (unsigned long long)n);
+    const double nm = static_cast<double>(n) * static_cast<double>(max_pixel(pixel_type));
+    const double lim = std::ldexp(1.0, 127) * 0.999;
+    if ((order >= 3 && 6.0 * nm * nm * nm >= lim) || (order >= 4 && 17.0 * nm * nm * nm * nm >= lim))
+        return fail(SAT_ERR_OVERFLOW, "%s: the moment numerators of %llu-pixel windows can exceed 128 bits", who,
+                    (unsigned long long)n);
+    if ((st = check_pitch(out_pitch, ow, oh, 8, who, "output"))) return st;
+    double *outs[4] = {mean_out, std_out, skew_out, kurt_out};
+    Span so[4], stab[4];
+    for (int p = 0; p < order; ++p) stab[p] = span(tables[p], H, sat_pitch, W, 8);
+    for (int i = 0; i < 4; ++i) {
+        so[i] = span(outs[i], oh, out_pitch, ow, 8);
+        for (int p = 0; p < order; ++p)
+            if (overlap(so[i], stab[p])) return fail(SAT_ERR_ARG, "%s: an output overlaps a table", who);
+        for (int j = 0; j < i; ++j)
+            if (overlap(so[i], so[j])) return fail(SAT_ERR_ARG, "%s: outputs overlap each other", who);
+    }
+    satk::MomentDesc d{};
+    for (int p = 0; p < order; ++p) d.T[p] = tables[p];
+    d.spitch = sat_pitch;
+    d.oh = oh;
+    d.ow = ow;
+    d.win_h = win_h;
+    d.win_w = win_w;
+    d.stride = stride;
+    d.mean = mean_out;
+    d.stdv = std_out;
+    d.skew = skew_out;
+    d.kurt = kurt_out;
+    d.opitch = out_pitch;
+    const int64_t chunks = (ow + 511) / 512;
+    if (oh * chunks > 0xffffffffll) return fail(SAT_ERR_ARG, "%s: too many work items", who);
+    hipError_t e = satk::launch_window_moments(order, d, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, who);
     return ok();
 }

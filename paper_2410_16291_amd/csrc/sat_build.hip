@@ -650,6 +650,64 @@ struct Build {
     }
 };
 
+// Helper-wave tile staging: the tile at columns [xb, xb+BW) of a strip's rows [ys, ys+nvalid)
+// into one LDS tile buffer (TH rows of BW pixels, row-major).
+template <typename T, int PX, int TH>
+struct TileStage {
+    static constexpr int BW = 64 * PX;
+    static constexpr int ROWB = BW * static_cast<int>(sizeof(T));
+    static constexpr int TILEB = TH * ROWB;
+    static_assert(TILEB % 1024 == 0, "tile is a whole number of 1 KiB wave loads");
+
+    // Fast path (tile inside the image width, rows 4- or 16-byte aligned): wave
+    // loads of 256 B (a dword per lane) or 1 KiB (dwordx4 per lane) from a buffer resource
+    // straight into LDS.  The resource ends after the last valid row, so rows past the image read
+    // as zero without a branch; the lane part of the address is one VGPR, the chunk part a scalar
+    // offset.  Otherwise element by element, zeros outside the image.
+    template <int VB>
+    static __device__ __forceinline__ void dma(const BuildDesc &d, uint32_t *tile, int64_t ys, int64_t xb, int nvalid,
+                                               int lane) {
+        constexpr int CB = 64 * VB;                         // bytes per wave load
+        const unsigned char *base = static_cast<const unsigned char *>(d.img) +
+                                    (ys * d.ipitch + xb) * static_cast<int64_t>(sizeof(T));
+        const uint32_t pitchb = static_cast<uint32_t>(d.ipitch * static_cast<int64_t>(sizeof(T)));
+        const uint32_t recs = static_cast<uint32_t>(nvalid - 1) * pitchb + ROWB;
+        const __amdgpu_buffer_rsrc_t rs =
+            __builtin_amdgcn_make_buffer_rsrc(const_cast<unsigned char *>(base), 0, static_cast<int>(recs), kRsrcWord3);
+        const uint32_t lb = static_cast<uint32_t>(lane) * VB;
+        const uint32_t voff = (lb / ROWB) * pitchb + lb % ROWB;
+        const int nch = (nvalid * ROWB + CB - 1) / CB;      // chunks holding valid rows
+#pragma unroll 4
+        for (int c = 0; c < nch; ++c) {
+            const uint32_t cb = static_cast<uint32_t>(c) * CB;
+            const uint32_t so = (cb / ROWB) * pitchb + cb % ROWB;
+            auto *dst = (__attribute__((address_space(3))) void *)(tile + c * (CB / 4));
+            if constexpr (VB == 16)
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, dst, 16, voff, static_cast<int>(so), 0, 0);
+            else
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, dst, 4, voff, static_cast<int>(so), 0, 0);
+        }
+    }
+
+    static __device__ void load(const BuildDesc &d, uint32_t *tile_buf, int64_t ys, int64_t xb, int nvalid,
+                                int lane) {
+        if (d.img_vb >= 4 && xb + BW <= d.W) {
+            if (d.img_vb >= 16) dma<16>(d, tile_buf, ys, xb, nvalid, lane);
+            else dma<4>(d, tile_buf, ys, xb, nvalid, lane);
+        } else {
+            const T *img = static_cast<const T *>(d.img);
+            T *tile = reinterpret_cast<T *>(tile_buf);
+#pragma unroll 4
+            for (int e = lane; e < nvalid * BW; e += 64) {
+                const int row = e / BW, col = e % BW;
+                const int64_t y = ys + row, x = xb + col;
+                tile[e] = (row < nvalid && x < d.W) ? img[y * d.ipitch + x] : static_cast<T>(0);
+            }
+        }
+    }
+
+};
+
 // ------------------------------------------------------------------ helper-wave strip worker
 //
 // Same arithmetic and lookback protocol as Build, organised around the single in-order vector
@@ -690,52 +748,9 @@ struct Build2 {
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
     }
 
-    // Helper wave: bring the tile at columns [xb, xb+BW) of the strip's rows [ys, ys+nvalid) into
-    // LDS buffer `buf`.  Fast path (tile inside the image width, rows 4- or 16-byte aligned): wave
-    // loads of 256 B (a dword per lane) or 1 KiB (dwordx4 per lane) from a buffer resource
-    // straight into LDS.  The resource ends after the last valid row, so rows past the image read
-    // as zero without a branch; the lane part of the address is one VGPR, the chunk part a scalar
-    // offset.  Otherwise element by element, zeros outside the image.
-    template <int VB>
-    static __device__ __forceinline__ void load_tile_dma(const BuildDesc &d, Smem &sm, int buf, int64_t ys, int64_t xb,
-                                                         int nvalid, int lane) {
-        constexpr int CB = 64 * VB;                         // bytes per wave load
-        const unsigned char *base = static_cast<const unsigned char *>(d.img) +
-                                    (ys * d.ipitch + xb) * static_cast<int64_t>(sizeof(T));
-        const uint32_t pitchb = static_cast<uint32_t>(d.ipitch * static_cast<int64_t>(sizeof(T)));
-        const uint32_t recs = static_cast<uint32_t>(nvalid - 1) * pitchb + ROWB;
-        const __amdgpu_buffer_rsrc_t rs =
-            __builtin_amdgcn_make_buffer_rsrc(const_cast<unsigned char *>(base), 0, static_cast<int>(recs), kRsrcWord3);
-        const uint32_t lb = static_cast<uint32_t>(lane) * VB;
-        const uint32_t voff = (lb / ROWB) * pitchb + lb % ROWB;
-        const int nch = (nvalid * ROWB + CB - 1) / CB;      // chunks holding valid rows
-#pragma unroll 4
-        for (int c = 0; c < nch; ++c) {
-            const uint32_t cb = static_cast<uint32_t>(c) * CB;
-            const uint32_t so = (cb / ROWB) * pitchb + cb % ROWB;
-            auto *dst = (__attribute__((address_space(3))) void *)(sm.tile[buf] + c * (CB / 4));
-            if constexpr (VB == 16)
-                __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, dst, 16, voff, static_cast<int>(so), 0, 0);
-            else
-                __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, dst, 4, voff, static_cast<int>(so), 0, 0);
-        }
-    }
-
     static __device__ void load_tile(const BuildDesc &d, Smem &sm, int buf, int64_t ys, int64_t xb, int nvalid,
                                      int lane) {
-        if (d.img_vb >= 4 && xb + BW <= d.W) {
-            if (d.img_vb >= 16) load_tile_dma<16>(d, sm, buf, ys, xb, nvalid, lane);
-            else load_tile_dma<4>(d, sm, buf, ys, xb, nvalid, lane);
-        } else {
-            const T *img = static_cast<const T *>(d.img);
-            T *tile = reinterpret_cast<T *>(sm.tile[buf]);
-#pragma unroll 4
-            for (int e = lane; e < nvalid * BW; e += 64) {
-                const int row = e / BW, col = e % BW;
-                const int64_t y = ys + row, x = xb + col;
-                tile[e] = (row < nvalid && x < d.W) ? img[y * d.ipitch + x] : static_cast<T>(0);
-            }
-        }
+        TileStage<T, PX, TH>::load(d, sm.tile[buf], ys, xb, nvalid, lane);
     }
 
     // Wait for this wave's outstanding global loads (the tile DMA) and LDS traffic.
@@ -942,6 +957,322 @@ struct Build2 {
         }
     }
 };
+
+// ------------------------------------------------------------------ tables of pixel powers
+//
+// The helper-wave build of Build2 for NP tables at once: the tables of pixel^1 .. pixel^NP (the
+// integral image of Sec. II-B applied to I^k), from one read of the image.  The helper wave forms
+// per-wave column sums of every power and runs one decoupled lookback over NP state planes; the
+// compute waves make one pass over the LDS tile per power, each with the scan type the power
+// needs (32-bit while a wave's 128 pixel powers sum below 2^32, else 64-bit).
+
+// Largest value of pixel^P, saturated at 2^64 - 1.
+template <typename T, int P>
+constexpr uint64_t max_pow() {
+    const uint64_t m = sizeof(T) == 1 ? 255u : 65535u;
+    uint64_t r = 1;
+    for (int i = 0; i < P; ++i) r = r > ~0ull / m ? ~0ull : r * m;
+    return r;
+}
+
+template <typename T, int P>
+using PowScan = typename std::conditional<(max_pow<T, P>() <= 0xffffffffull / 128), uint32_t, uint64_t>::type;
+
+// Sum of two values that feed a DPP scan.  In 64 bits: two 32-bit adds (with carry) and then the
+// two wait states a DPP read of a fresh VALU result needs, in one asm block.  Written as plain
+// code, the two halves may be fused into one 64-bit add (v_lshl_add_u64) whose result the
+// compiler does not guard for a following DPP read.
+__device__ __forceinline__ uint32_t dpp_src_sum(uint32_t a, uint32_t b) { return a + b; }
+__device__ __forceinline__ uint64_t dpp_src_sum(uint64_t a, uint64_t b) {
+    uint32_t lo, hi;
+    asm volatile("v_add_co_u32 %0, vcc, %2, %3\n\tv_addc_co_u32 %1, vcc, %4, %5, vcc\n\ts_nop 1"
+                 : "=&v"(lo), "=v"(hi)
+                 : "v"(static_cast<uint32_t>(a)), "v"(static_cast<uint32_t>(b)), "v"(static_cast<uint32_t>(a >> 32)),
+                   "v"(static_cast<uint32_t>(b >> 32))
+                 : "vcc");
+    return (static_cast<uint64_t>(hi) << 32) | lo;
+}
+
+template <typename ST, int P>
+__device__ __forceinline__ ST pow_of(uint32_t v) {
+    const ST x = static_cast<ST>(v);
+    ST r = x;
+#pragma unroll
+    for (int i = 1; i < P; ++i) r *= x;
+    return r;
+}
+
+template <typename T, int NP, int PX, int RW, int NW, bool NTS>
+struct BuildPow {
+    using B1 = Build<T, false, PX, RW, NW, MODE_LOOKBACK>;   // column map (soff)
+    static constexpr int TH = RW * NW;
+    static constexpr int BW = 64 * PX;
+    static constexpr int NS = PX / 2;
+    static constexpr int HELPER = NW;
+    static constexpr int ROWB = BW * static_cast<int>(sizeof(T));
+    static constexpr int TILEB = TH * ROWB;
+    static_assert(NP >= 1 && NP <= 4 && NP * PX <= 32, "power count and lane pixels fit the done mask");
+
+    struct Smem {
+        uint32_t tile[2][TILEB / 4];                      // image tiles of blocks b and b+1
+        uint64_t cs[2][NP][NW][BW];                       // per compute wave column sums of pixel^p
+        uint64_t v[2][NP][BW];                            // column totals above the strip
+        long long ticket;
+    };
+
+    static __device__ __forceinline__ void barrier() {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+        __builtin_amdgcn_s_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+    }
+
+    static __device__ __forceinline__ uint64_t *table(const BuildDesc &d, int p) {
+        return p == 0 ? d.S : p == 1 ? d.Q : p == 2 ? d.T3 : d.T4;
+    }
+
+    // Decoupled lookback over NP planes of nstrips * Wp words (the protocol of Build::lookback).
+    static __device__ void lookback(const BuildDesc &d, int strip, int64_t xb, int lane, const uint64_t (&a)[NP][PX],
+                                    uint64_t (&v)[NP][PX], uint64_t *state, unsigned int *fault) {
+        const int64_t plane = static_cast<int64_t>(d.nstrips) * d.Wp;
+        const int64_t col0 = xb + 2 * lane;
+        uint64_t *mine = state + d.state_off + static_cast<int64_t>(strip) * d.Wp + col0;
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+#pragma unroll
+            for (int i = 0; i < PX; ++i) v[p][i] = 0;
+        const uint64_t first = strip == 0 ? kStPrefix : kStAggregate;
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+#pragma unroll
+            for (int i = 0; i < PX; ++i) store_state(mine + p * plane + B1::soff(i), first | a[p][i]);
+        if (strip == 0) return;
+        constexpr uint32_t kAll = NP * PX == 32 ? 0xffffffffu : ((1u << (NP * PX)) - 1u);
+        uint32_t done = 0, spins = 0;
+        int j = strip - 1;
+        for (;;) {
+            const uint64_t *up = state + d.state_off + static_cast<int64_t>(j) * d.Wp + col0;
+            uint64_t w[NP][PX];
+            bool ready = true;
+#pragma unroll
+            for (int p = 0; p < NP; ++p)
+#pragma unroll
+                for (int i = 0; i < PX; ++i) {
+                    w[p][i] = 0;
+                    if (!(done & (1u << (p * PX + i)))) {
+                        w[p][i] = load_state(up + p * plane + B1::soff(i));
+                        ready = ready && (w[p][i] >> 62) != 0;
+                    }
+                }
+            if (!__all(ready)) {
+                if (++spins > kSpinLimit) {
+                    atomicOr(fault, 1u);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+                continue;
+            }
+#pragma unroll
+            for (int p = 0; p < NP; ++p)
+#pragma unroll
+                for (int i = 0; i < PX; ++i) {
+                    const uint32_t bit = 1u << (p * PX + i);
+                    if (!(done & bit)) {
+                        v[p][i] += w[p][i] & kValueMask;
+                        if ((w[p][i] >> 62) == 2 || j == 0) done |= bit;
+                    }
+                }
+            if (__all(done == kAll)) break;
+            --j;
+        }
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+#pragma unroll
+            for (int i = 0; i < PX; ++i) store_state(mine + p * plane + B1::soff(i), kStPrefix | (v[p][i] + a[p][i]));
+    }
+
+    // Helper wave: per-wave column sums of every power of tile `buf`, the lookback, and the
+    // column totals above the strip for the compute waves.
+    static __device__ void prepare(const BuildDesc &d, Smem &sm, int buf, int64_t xb, int strip, int nvalid, int rw,
+                                   int lane, uint64_t *state, unsigned int *fault) {
+        uint64_t a[NP][PX];
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+#pragma unroll
+            for (int i = 0; i < PX; ++i) a[p][i] = 0;
+        const T *tile = reinterpret_cast<const T *>(sm.tile[buf]) + 2 * lane;
+        for (int w = 0; w < NW; ++w) {
+            uint64_t cs[NP][PX];
+#pragma unroll
+            for (int p = 0; p < NP; ++p)
+#pragma unroll
+                for (int i = 0; i < PX; ++i) cs[p][i] = 0;
+            const int r_end = nvalid - w * rw < rw ? nvalid - w * rw : rw;
+            for (int r = 0; r < r_end; ++r) {
+                const T *row = tile + (w * rw + r) * BW;
+#pragma unroll
+                for (int sb = 0; sb < NS; ++sb) {
+                    uint32_t pair;
+                    if (sizeof(T) == 1) pair = *reinterpret_cast<const uint16_t *>(row + 128 * sb);
+                    else pair = *reinterpret_cast<const uint32_t *>(row + 128 * sb);
+                    const uint64_t v0 = sizeof(T) == 1 ? (pair & 0xffu) : (pair & 0xffffu);
+                    const uint64_t v1 = sizeof(T) == 1 ? ((pair >> 8) & 0xffu) : (pair >> 16);
+                    uint64_t p0 = v0, p1 = v1;
+#pragma unroll
+                    for (int p = 0; p < NP; ++p) {
+                        cs[p][2 * sb] += p0;
+                        cs[p][2 * sb + 1] += p1;
+                        p0 *= v0;
+                        p1 *= v1;
+                    }
+                }
+            }
+#pragma unroll
+            for (int p = 0; p < NP; ++p)
+#pragma unroll
+                for (int i = 0; i < PX; ++i) {
+                    sm.cs[buf][p][w][lane * PX + i] = cs[p][i];
+                    a[p][i] += cs[p][i];
+                }
+        }
+        uint64_t v[NP][PX];
+        lookback(d, strip, xb, lane, a, v, state, fault);
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+#pragma unroll
+            for (int i = 0; i < PX; ++i) sm.v[buf][p][lane * PX + i] = v[p][i];
+    }
+
+    // Compute wave: the rows of power P (table P-1) of block (buf, xb).
+    template <int P>
+    static __device__ __forceinline__ void power_rows(const BuildDesc &d, const Smem &sm, int buf, int64_t xb, int wave,
+                                                      int rw, int lane, int rows_ok, int64_t yw, uint32_t pitch_bytes,
+                                                      uint64_t &lrow, uint64_t &ucarry) {
+        using ST = PowScan<T, P>;
+        uint64_t u[PX];
+        {
+            uint64_t c[PX];
+#pragma unroll
+            for (int i = 0; i < PX; ++i) c[i] = sm.v[buf][P - 1][lane * PX + i];
+            for (int w = 0; w < wave; ++w)
+#pragma unroll
+                for (int i = 0; i < PX; ++i) c[i] += sm.cs[buf][P - 1][w][lane * PX + i];
+#pragma unroll
+            for (int sb = 0; sb < NS; ++sb) {
+                const uint64_t pair = dpp_src_sum(c[2 * sb], c[2 * sb + 1]);
+                const uint64_t incl = wave_scan(pair);
+                const uint64_t b = ucarry + (incl - pair);
+                u[2 * sb] = b + c[2 * sb];
+                u[2 * sb + 1] = b + pair;
+                ucarry += readlane(incl, 63);
+            }
+        }
+        uint64_t *blk0 = table(d, P - 1) + yw * d.spitch + xb;
+        const bool vec = d.sat_vec && xb + BW <= d.W;
+        const uint32_t row_recs = static_cast<uint32_t>((d.W - xb) * 8);
+        const T *trow = reinterpret_cast<const T *>(sm.tile[buf] + wave * rw * ROWB / 4) + 2 * lane;
+        uint64_t acc[PX];
+#pragma unroll
+        for (int i = 0; i < PX; ++i) acc[i] = 0;
+        uint64_t tvec = 0;
+        const uint32_t voff = static_cast<uint32_t>(lane) * 16;
+        const uint32_t blk_recs = rows_ok > 0 ? (rows_ok - 1) * pitch_bytes + row_recs : 0;
+        const i32x4 rs_blk = make_rsrc(blk0, vec ? blk_recs : 0);
+        const char *rowp = reinterpret_cast<const char *>(blk0);
+        uint32_t roff = 0;
+#pragma unroll 1
+        for (int r = 0; r < rows_ok; ++r) {
+            uint64_t base = readlane(lrow, r);
+            const __amdgpu_buffer_rsrc_t rs_row = __builtin_amdgcn_make_buffer_rsrc(
+                const_cast<char *>(rowp), 0, vec ? 0 : static_cast<int>(row_recs), kRsrcWord3);
+#pragma unroll
+            for (int sb = 0; sb < NS; ++sb) {
+                uint32_t pairv;
+                if (sizeof(T) == 1) pairv = *reinterpret_cast<const uint16_t *>(trow + 128 * sb);
+                else pairv = *reinterpret_cast<const uint32_t *>(trow + 128 * sb);
+                const uint32_t v0 = sizeof(T) == 1 ? (pairv & 0xffu) : (pairv & 0xffffu);
+                const uint32_t v1 = sizeof(T) == 1 ? ((pairv >> 8) & 0xffu) : (pairv >> 16);
+                const ST a0 = pow_of<ST, P>(v0), a1 = pow_of<ST, P>(v1);
+                const ST pair = dpp_src_sum(a0, a1);
+                const ST incl = wave_scan(pair);
+                const uint64_t b = base + (incl - pair);
+                acc[2 * sb] += b + a0;
+                acc[2 * sb + 1] += b + pair;
+                const uint64_t o0 = u[2 * sb] + acc[2 * sb], o1 = u[2 * sb + 1] + acc[2 * sb + 1];
+                if (vec) {
+                    store16_rsrc<NTS>(u32x4{static_cast<uint32_t>(o0), static_cast<uint32_t>(o0 >> 32),
+                                            static_cast<uint32_t>(o1), static_cast<uint32_t>(o1 >> 32)},
+                                      rs_blk, voff + sb * 1024, roff);
+                } else {
+                    __builtin_amdgcn_raw_buffer_store_b64(u32x2{static_cast<uint32_t>(o0), static_cast<uint32_t>(o0 >> 32)},
+                                                          rs_row, voff + sb * 1024, 0, NTS ? 2 : 0);
+                    __builtin_amdgcn_raw_buffer_store_b64(u32x2{static_cast<uint32_t>(o1), static_cast<uint32_t>(o1 >> 32)},
+                                                          rs_row, voff + sb * 1024 + 8, 0, NTS ? 2 : 0);
+                }
+                base += readlane(incl, 63);
+            }
+            if (lane == r) tvec = base - readlane(lrow, r);
+            trow += BW;
+            rowp += pitch_bytes;
+            roff += pitch_bytes;
+        }
+        lrow += tvec;
+    }
+
+    static __device__ void strip(const BuildDesc &d, int strip_idx, uint64_t *state, unsigned int *fault, Smem &sm) {
+        const int lane = threadIdx.x & 63;
+        const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+        const bool helper = wave == HELPER;
+        const int th = d.strip_h, rw = d.wave_rows;                       // th <= TH, rw <= RW
+        const int64_t ys = static_cast<int64_t>(strip_idx) * th;
+        const int nvalid = static_cast<int>(d.H - ys < th ? d.H - ys : th);
+        const int64_t yw = ys + (helper ? 0 : wave) * rw;
+        const int left = nvalid - wave * rw;
+        const int rows_ok = helper ? 0 : (left < rw ? (left > 0 ? left : 0) : rw);
+        const uint32_t pitch_bytes = static_cast<uint32_t>(d.spitch * 8);
+        uint64_t lrow[NP], ucarry[NP];       // lane r: row yw+r left of the block; table above, left of it
+#pragma unroll
+        for (int p = 0; p < NP; ++p) { lrow[p] = 0; ucarry[p] = 0; }
+
+        if (helper) {
+            TileStage<T, PX, TH>::load(d, sm.tile[0], ys, 0, nvalid, lane);
+            __builtin_amdgcn_s_waitcnt(0x0070);
+            prepare(d, sm, 0, 0, strip_idx, nvalid, rw, lane, state, fault);
+        }
+        barrier();
+        if (helper && d.nblocks > 1) TileStage<T, PX, TH>::load(d, sm.tile[1], ys, BW, nvalid, lane);
+        for (int b = 0; b < d.nblocks; ++b) {
+            const int buf = b & 1;
+            const int64_t xb = static_cast<int64_t>(b) * BW;
+            if (!helper) {
+                power_rows<1>(d, sm, buf, xb, wave, rw, lane, rows_ok, yw, pitch_bytes, lrow[0], ucarry[0]);
+                if constexpr (NP >= 2) power_rows<2>(d, sm, buf, xb, wave, rw, lane, rows_ok, yw, pitch_bytes, lrow[1], ucarry[1]);
+                if constexpr (NP >= 3) power_rows<3>(d, sm, buf, xb, wave, rw, lane, rows_ok, yw, pitch_bytes, lrow[2], ucarry[2]);
+                if constexpr (NP >= 4) power_rows<4>(d, sm, buf, xb, wave, rw, lane, rows_ok, yw, pitch_bytes, lrow[3], ucarry[3]);
+            } else if (b + 1 < d.nblocks) {
+                __builtin_amdgcn_s_waitcnt(0x0070);
+                prepare(d, sm, buf ^ 1, xb + BW, strip_idx, nvalid, rw, lane, state, fault);
+            }
+            barrier();
+            if (helper && b + 2 < d.nblocks) TileStage<T, PX, TH>::load(d, sm.tile[buf], ys, xb + 2 * BW, nvalid, lane);
+        }
+    }
+};
+
+template <typename T, int NP, int PX, int RW, int NW, bool NTS>
+__global__ __launch_bounds__((NW + 1) * 64) void build_pow_kernel(BuildDesc d, long long total_items, uint64_t *state,
+                                                                  BuildCtrl *ctrl) {
+    using B = BuildPow<T, NP, PX, RW, NW, NTS>;
+    __shared__ typename B::Smem sm;
+    for (;;) {
+        if (threadIdx.x == 0) sm.ticket = static_cast<long long>(atomicAdd(&ctrl->ticket, 1ull));
+        __syncthreads();
+        const long long t = static_cast<long long>(__builtin_amdgcn_readfirstlane(static_cast<int>(sm.ticket))) |
+                            (static_cast<long long>(__builtin_amdgcn_readfirstlane(static_cast<int>(sm.ticket >> 32))) << 32);
+        __syncthreads();
+        if (t >= total_items) return;
+        B::strip(d, __builtin_amdgcn_readfirstlane(static_cast<int>(t)), state, &ctrl->fault, sm);
+    }
+}
 
 template <typename T, bool SQ, int PX, int RW, int NW, int WIN, bool NTS>
 __global__ __launch_bounds__((NW + 1) * 64) void build2_kernel(const BuildDesc *__restrict__ many, int n,
@@ -1188,7 +1519,78 @@ int capacity_variant(int v) {
     }
 }
 
+// Power builds: 2 pixels per lane (128-column blocks), 16 rows per wave, 4 compute waves and the
+// helper, non-temporal table stores.  With four 8-bit tables the workgroup state is 56 KiB of
+// LDS, two workgroups per CU.
+template <typename T, int NP>
+const void *pow_kernel() {
+    return reinterpret_cast<const void *>(&build_pow_kernel<T, NP, 2, 16, 4, true>);
+}
+static_assert(64 * 2 == kPowBlockW && 16 * 4 == kPowStripH, "power build geometry");
+
+template <typename T, int NP>
+int pow_capacity_typed() {
+    static int cap = 0;
+    if (cap == 0) cap = resident_capacity(pow_kernel<T, NP>(), 5 * 64);
+    return cap;
+}
+
+template <typename T, int NP>
+hipError_t launch_pow_typed(const BuildDesc &d, void *workspace, int64_t state_words, hipStream_t stream) {
+    BuildCtrl *ctrl = static_cast<BuildCtrl *>(workspace);
+    uint64_t *state = reinterpret_cast<uint64_t *>(static_cast<char *>(workspace) + sizeof(BuildCtrl));
+    const long long pairs = (state_words + 1) / 2;
+    const long long blocks = pairs > 0 ? (pairs + 255) / 256 : 1;
+    const unsigned cgrid = static_cast<unsigned>(blocks < 8192 ? blocks : 8192);
+    hipLaunchKernelGGL(clear_kernel, dim3(cgrid), dim3(256), 0, stream, state, static_cast<long long>(state_words), ctrl,
+                       d, static_cast<BuildDesc *>(nullptr));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int cap = pow_capacity_typed<T, NP>();
+    const int64_t grid = d.nstrips < cap ? d.nstrips : cap;
+    hipLaunchKernelGGL((build_pow_kernel<T, NP, 2, 16, 4, true>), dim3(static_cast<unsigned>(grid)), dim3(5 * 64), 0,
+                       stream, d, static_cast<long long>(d.nstrips), state, ctrl);
+    return hipGetLastError();
+}
+
 }  // namespace
+
+int power_build_capacity(int bpp, int np) {
+    if (bpp == 1) {
+        switch (np) {
+            case 1: return pow_capacity_typed<uint8_t, 1>();
+            case 2: return pow_capacity_typed<uint8_t, 2>();
+            case 3: return pow_capacity_typed<uint8_t, 3>();
+            case 4: return pow_capacity_typed<uint8_t, 4>();
+        }
+    } else {
+        switch (np) {
+            case 1: return pow_capacity_typed<uint16_t, 1>();
+            case 2: return pow_capacity_typed<uint16_t, 2>();
+            case 3: return pow_capacity_typed<uint16_t, 3>();
+        }
+    }
+    return 0;
+}
+
+hipError_t launch_build_powers(int bpp, int np, const BuildDesc &d, void *workspace, int64_t state_words,
+                               hipStream_t stream) {
+    if (bpp == 1) {
+        switch (np) {
+            case 1: return launch_pow_typed<uint8_t, 1>(d, workspace, state_words, stream);
+            case 2: return launch_pow_typed<uint8_t, 2>(d, workspace, state_words, stream);
+            case 3: return launch_pow_typed<uint8_t, 3>(d, workspace, state_words, stream);
+            case 4: return launch_pow_typed<uint8_t, 4>(d, workspace, state_words, stream);
+        }
+    } else {
+        switch (np) {
+            case 1: return launch_pow_typed<uint16_t, 1>(d, workspace, state_words, stream);
+            case 2: return launch_pow_typed<uint16_t, 2>(d, workspace, state_words, stream);
+            case 3: return launch_pow_typed<uint16_t, 3>(d, workspace, state_words, stream);
+        }
+    }
+    return hipErrorInvalidValue;
+}
 
 int build_variant_count() { return kNumVariants; }
 const BuildVariant &build_variant(int v) { return kVariants[v]; }

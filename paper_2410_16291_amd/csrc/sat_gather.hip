@@ -904,4 +904,109 @@ hipError_t launch_mean_std(int variant, const GatherDesc *descs, int n, const Ga
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ higher window moments
+//
+// Window statistics beyond mean and std from tables of pixel powers (the method applied to
+// I^k): with S_k the window sum of pixel^k over n pixels (four-corner lookups, exact), the
+// central moments expand into the raw sums by the binomial theorem,
+//   A = n*S2 - S1^2 = n^2 m2,   B = n^2*S3 - 3n*S1*S2 + 2*S1^3 = n^3 m3,
+//   C = n^3*S4 - 4n^2*S1*S3 + 6n*S1^2*S2 - 3*S1^4 = n^4 m4,
+// formed exactly in signed 128-bit integers (the host bounds n and the pixel range so that no
+// term overflows) and rounded to double once each:
+//   mean = S1/n, std = sqrt(A)/n, skewness = B / (A*sqrt(A)), excess kurtosis = (C - 3A^2)/(A*A),
+// population moments; skewness and kurtosis are NaN where A = 0.  One output row segment per
+// work item, reading the two table rows of each power (row pairs, banded for L2 reuse).
+
+namespace {
+
+typedef __int128 i128;
+
+__device__ __forceinline__ double i128_to_double(i128 x) {
+    const bool neg = x < 0;
+    const unsigned __int128 u = neg ? static_cast<unsigned __int128>(-x) : static_cast<unsigned __int128>(x);
+    const double r = u128_to_double(static_cast<uint64_t>(u >> 64), static_cast<uint64_t>(u));
+    return neg ? -r : r;
+}
+
+template <int K>
+__device__ __forceinline__ void moments_store(const MomentDesc &d, int64_t o, const uint64_t (&s)[K], uint64_t n,
+                                              double dn) {
+    if (d.mean) __builtin_nontemporal_store(static_cast<double>(s[0]) / dn, d.mean + o);
+    if constexpr (K >= 2) {
+        const i128 N = static_cast<i128>(n), a1 = static_cast<i128>(s[0]), a2 = static_cast<i128>(s[1]);
+        const i128 A = N * a2 - a1 * a1;
+        const double a = i128_to_double(A);
+        const double ra = sqrt(a);
+        if (d.stdv) __builtin_nontemporal_store(ra / dn, d.stdv + o);
+        if constexpr (K >= 3) {
+            const i128 a3 = static_cast<i128>(s[2]);
+            if (d.skew) {
+                const i128 B = N * N * a3 - 3 * N * a1 * a2 + 2 * a1 * a1 * a1;
+                __builtin_nontemporal_store(A == 0 ? __builtin_nan("") : i128_to_double(B) / (a * ra), d.skew + o);
+            }
+            if constexpr (K >= 4) {
+                if (d.kurt) {
+                    const i128 a4 = static_cast<i128>(s[3]);
+                    const i128 C = N * N * N * a4 - 4 * N * N * a1 * a3 + 6 * N * a1 * a1 * a2 - 3 * a1 * a1 * a1 * a1;
+                    __builtin_nontemporal_store(A == 0 ? __builtin_nan("") : i128_to_double(C - 3 * A * A) / (a * a),
+                                                d.kurt + o);
+                }
+            }
+        }
+    }
+}
+
+template <int K, int V>
+__global__ __launch_bounds__(256) void moments_kernel(MomentDesc d, int64_t band) {
+    const ItemMap m = map_item(blockIdx.x, d.oh, d.chunks, band);
+    GatherDesc g{};
+    g.ow = d.ow;
+    g.stride = d.stride;
+    g.win_w = d.win_w;
+    const int64_t y0 = m.k * d.stride;
+    const int64_t y1 = y0 + d.win_h - 1;
+    const bool has_top = y0 > 0;
+    const uint64_t n = static_cast<uint64_t>(d.win_h) * static_cast<uint64_t>(d.win_w);
+    const double dn = static_cast<double>(n);
+    const int64_t l0 = m.c * (256 * V) + threadIdx.x;
+    Corners c[K][V];
+#pragma unroll
+    for (int p = 0; p < K; ++p) {
+        const uint64_t *bot = d.T[p] + y1 * d.spitch;
+        const uint64_t *top = d.T[p] + (has_top ? y0 - 1 : 0) * d.spitch;
+#pragma unroll
+        for (int v = 0; v < V; ++v) c[p][v] = load_corners(top, bot, l0 + v * 256, g);
+    }
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        const int64_t l = l0 + v * 256;
+        if (l < d.ow) {
+            uint64_t s[K];
+#pragma unroll
+            for (int p = 0; p < K; ++p) s[p] = corner_sum(c[p][v], l, g, has_top);
+            moments_store<K>(d, m.k * d.opitch + l, s, n, dn);
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_window_moments(int order, MomentDesc d, hipStream_t stream) {
+    constexpr int V = 2;
+    d.chunks = (d.ow + 256 * V - 1) / (256 * V);
+    GatherDesc g{};
+    g.chunks = d.chunks;
+    g.stride = d.stride;
+    const int64_t band = band_chunks(g, V, true, d.win_h * order);
+    const dim3 grid(static_cast<unsigned>(d.oh * d.chunks));
+    switch (order) {
+        case 1: hipLaunchKernelGGL((moments_kernel<1, V>), grid, dim3(256), 0, stream, d, band); break;
+        case 2: hipLaunchKernelGGL((moments_kernel<2, V>), grid, dim3(256), 0, stream, d, band); break;
+        case 3: hipLaunchKernelGGL((moments_kernel<3, V>), grid, dim3(256), 0, stream, d, band); break;
+        case 4: hipLaunchKernelGGL((moments_kernel<4, V>), grid, dim3(256), 0, stream, d, band); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 }  // namespace satk

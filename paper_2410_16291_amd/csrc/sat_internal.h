@@ -15,6 +15,7 @@ struct BuildDesc {
     const void *img;
     uint64_t *S;          // table of pixels
     uint64_t *Q;          // table of squared pixels, or nullptr
+    uint64_t *T3, *T4;    // power builds: tables of pixel^3 and pixel^4, or nullptr
     int64_t H, W, ipitch, spitch;
     int64_t Wp;           // state row length: nblocks * block width
     int64_t state_off;    // first lookback word of this image in the state array (S part)
@@ -64,6 +65,14 @@ hipError_t launch_build(int variant, int bpp, bool sq, const BuildDesc *descs, i
                         const BuildDesc *dev_descs, int64_t total_items, void *workspace,
                         int64_t state_words, hipStream_t stream);
 
+// Tables of pixel^1..pixel^np of one image (S, Q, T3, T4 of the descriptor) in one pass: the
+// helper-wave build with np lookback planes of nstrips * Wp words each (state_off: the first).
+constexpr int kPowBlockW = 128;   // block width (columns) of the power build
+constexpr int kPowStripH = 64;    // its largest strip height
+int power_build_capacity(int bpp, int np);
+hipError_t launch_build_powers(int bpp, int np, const BuildDesc &d, void *workspace, int64_t state_words,
+                               hipStream_t stream);
+
 // ---------------------------------------------------------------- window gathers
 
 struct GatherDesc {
@@ -81,6 +90,19 @@ struct GatherDesc {
     int64_t q;               // chain gathers: output rows between two reads of one table row
     int64_t seg;             // chain gathers: chain positions per work item
 };
+
+// Window moments from tables of pixel powers: up to four tables, any subset of the outputs.
+struct MomentDesc {
+    const uint64_t *T[4];    // tables of pixel^1 .. pixel^order
+    int64_t spitch;
+    int64_t oh, ow;
+    int64_t win_h, win_w, stride;
+    double *mean, *stdv, *skew, *kurt;   // outputs, nullptr where not wanted
+    int64_t opitch;
+    int64_t chunks;          // column chunks per output row (filled by the launcher)
+};
+// order: number of tables read (1 mean, 2 std, 3 skewness, 4 excess kurtosis).
+hipError_t launch_window_moments(int order, MomentDesc d, hipStream_t stream);
 
 int gather_variant_count();
 const char *gather_variant_name(int v);

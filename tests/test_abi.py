@@ -182,3 +182,36 @@ def test_variant_supported(lib):
         assert st == SAT_ERR_ARG and b"does not fit the LDS" in lib.sat_last_error()
     finally:
         lib.sat_force_variant(0, -1)
+
+
+def test_powers_and_moments_validation(lib):
+    P = ctypes.c_void_p
+    T3 = (P * 3)(SAT, SQ, OUT)
+    ws = lib.sat_powers_workspace_bytes(64, 64, SAT_U8, 3)
+    assert ws > 0
+    assert lib.sat_powers_workspace_bytes(64, 64, SAT_U8, 5) == 0
+    assert lib.sat_powers_workspace_bytes(64, 64, SAT_U32, 2) == 0
+    assert lib.sat_powers_workspace_bytes(0, 64, SAT_U8, 2) == 0
+    # k beyond 4, a NULL table, overlapping tables, a short workspace
+    assert lib.sat_build_powers(IMG, SAT_U8, 64, 64, 64, 5, T3, 64, WS, ws, None) == SAT_ERR_ARG
+    assert lib.sat_build_powers(IMG, SAT_U8, 64, 64, 64, 3, (P * 3)(SAT, None, OUT), 64, WS, ws, None) == SAT_ERR_ARG
+    assert lib.sat_build_powers(IMG, SAT_U8, 64, 64, 64, 3, (P * 3)(SAT, SAT + 8, OUT), 64, WS, ws, None) == SAT_ERR_ARG
+    assert lib.sat_build_powers(IMG, SAT_U8, 64, 64, 64, 3, T3, 64, WS, ws - 8, None) == SAT_ERR_WORKSPACE
+    assert lib.sat_build_powers(IMG, SAT_U8, 64, 64, 64, 3, None, 64, WS, ws, None) == SAT_ERR_ARG
+    # 62-bit column totals: 16-bit pixel^4 never fits, pixel^3 up to 16384 rows
+    T4 = (P * 4)(SAT, SQ, OUT, OUT2)
+    ws16 = lib.sat_powers_workspace_bytes(64, 64, SAT_U16, 4)
+    assert lib.sat_build_powers(IMG, SAT_U16, 64, 64, 64, 4, T4, 64, WS, ws16, None) == SAT_ERR_OVERFLOW
+    big = lib.sat_powers_workspace_bytes(16385, 64, SAT_U16, 3)
+    assert lib.sat_build_powers(IMG, SAT_U16, 16385, 64, 64, 3, T3, 64, WS, big, None) == SAT_ERR_OVERFLOW
+    # no output, too few tables for the highest statistic, window too large
+    assert lib.window_moments(T3, 3, SAT_U8, 64, 64, 64, 8, 8, 1, None, None, None, None, 64, None) == SAT_ERR_ARG
+    assert lib.window_moments(T3, 3, SAT_U8, 64, 64, 64, 8, 8, 1, None, None, None, OUT3, 64, None) == SAT_ERR_ARG
+    assert lib.window_moments(T3, 3, SAT_U8, 64, 64, 64, 65, 8, 1, OUT2, None, None, None, 64, None) == SAT_ERR_WINDOW
+    # outputs overlapping each other or a table
+    assert lib.window_moments(T3, 3, SAT_U8, 64, 64, 64, 8, 8, 1, OUT2, OUT2 + 8, None, None, 64, None) == SAT_ERR_ARG
+    assert lib.window_moments(T3, 3, SAT_U8, 64, 64, 64, 8, 8, 1, SAT + 8, None, None, None, 64, None) == SAT_ERR_ARG
+    # 16-bit skewness: window sums of pixel^3 exceed 64 bits beyond 65536 pixels
+    big16 = (P * 3)(SAT, SQ, OUT)
+    assert lib.window_moments(big16, 3, SAT_U16, 4096, 4096, 4096, 256, 257, 1, None, None, OUT2, None, 4096,
+                              None) == SAT_ERR_OVERFLOW
