@@ -600,9 +600,9 @@ sat_status window_moments(const uint64_t *const *tables, int32_t k, sat_dtype pi
     d.skew = skew_out;
     d.kurt = kurt_out;
     d.opitch = out_pitch;
-    const int64_t chunks = (ow + 511) / 512;
+    const int64_t chunks = (ow + 255) / 256;
     if (oh * chunks > 0xffffffffll) return fail(SAT_ERR_ARG, "%s: too many work items", who);
-    hipError_t e = satk::launch_window_moments(order, d, static_cast<hipStream_t>(stream));
+    hipError_t e = satk::launch_window_moments(gather_variant(), order, d, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, who);
     return ok();
 }

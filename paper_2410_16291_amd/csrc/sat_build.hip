@@ -975,6 +975,12 @@ constexpr uint64_t max_pow() {
     return r;
 }
 
+// Narrowest exact types: one pixel's power, a sum of up to 16 of them (a wave's rows), and the
+// scan of a wave's 128 pixel powers.
+template <typename T, int P>
+using PowT = typename std::conditional<(max_pow<T, P>() <= 0xffffffffull), uint32_t, uint64_t>::type;
+template <typename T, int P>
+using SumT = typename std::conditional<(max_pow<T, P>() <= 0xffffffffull / 16), uint32_t, uint64_t>::type;
 template <typename T, int P>
 using PowScan = typename std::conditional<(max_pow<T, P>() <= 0xffffffffull / 128), uint32_t, uint64_t>::type;
 
@@ -993,13 +999,11 @@ __device__ __forceinline__ uint64_t dpp_src_sum(uint64_t a, uint64_t b) {
     return (static_cast<uint64_t>(hi) << 32) | lo;
 }
 
-template <typename ST, int P>
-__device__ __forceinline__ ST pow_of(uint32_t v) {
-    const ST x = static_cast<ST>(v);
-    ST r = x;
-#pragma unroll
-    for (int i = 1; i < P; ++i) r *= x;
-    return r;
+// pixel^P, each product in the narrowest type that holds it exactly (8-bit pixels: all 32-bit).
+template <typename T, int P>
+__device__ __forceinline__ PowT<T, P> pow_of(uint32_t v) {
+    if constexpr (P == 1) return v;
+    else return static_cast<PowT<T, P>>(pow_of<T, P - 1>(v)) * v;
 }
 
 template <typename T, int NP, int PX, int RW, int NW, bool NTS>
@@ -1101,11 +1105,12 @@ struct BuildPow {
             for (int i = 0; i < PX; ++i) a[p][i] = 0;
         const T *tile = reinterpret_cast<const T *>(sm.tile[buf]) + 2 * lane;
         for (int w = 0; w < NW; ++w) {
-            uint64_t cs[NP][PX];
+            SumT<T, 1> c1[PX];
+            SumT<T, 2> c2[PX];
+            SumT<T, 3> c3[PX];
+            SumT<T, 4> c4[PX];
 #pragma unroll
-            for (int p = 0; p < NP; ++p)
-#pragma unroll
-                for (int i = 0; i < PX; ++i) cs[p][i] = 0;
+            for (int i = 0; i < PX; ++i) { c1[i] = 0; c2[i] = 0; c3[i] = 0; c4[i] = 0; }
             const int r_end = nvalid - w * rw < rw ? nvalid - w * rw : rw;
             for (int r = 0; r < r_end; ++r) {
                 const T *row = tile + (w * rw + r) * BW;
@@ -1114,25 +1119,32 @@ struct BuildPow {
                     uint32_t pair;
                     if (sizeof(T) == 1) pair = *reinterpret_cast<const uint16_t *>(row + 128 * sb);
                     else pair = *reinterpret_cast<const uint32_t *>(row + 128 * sb);
-                    const uint64_t v0 = sizeof(T) == 1 ? (pair & 0xffu) : (pair & 0xffffu);
-                    const uint64_t v1 = sizeof(T) == 1 ? ((pair >> 8) & 0xffu) : (pair >> 16);
-                    uint64_t p0 = v0, p1 = v1;
 #pragma unroll
-                    for (int p = 0; p < NP; ++p) {
-                        cs[p][2 * sb] += p0;
-                        cs[p][2 * sb + 1] += p1;
-                        p0 *= v0;
-                        p1 *= v1;
+                    for (int j = 0; j < 2; ++j) {
+                        const uint32_t v = sizeof(T) == 1 ? ((pair >> (8 * j)) & 0xffu) : ((pair >> (16 * j)) & 0xffffu);
+                        const int i = 2 * sb + j;
+                        c1[i] += v;
+                        if constexpr (NP >= 2) {
+                            const PowT<T, 2> q2 = pow_of<T, 2>(v);
+                            c2[i] += q2;
+                            if constexpr (NP >= 3) {
+                                const PowT<T, 3> q3 = static_cast<PowT<T, 3>>(q2) * v;
+                                c3[i] += q3;
+                                if constexpr (NP >= 4) c4[i] += static_cast<PowT<T, 4>>(q3) * v;
+                            }
+                        }
                     }
                 }
             }
 #pragma unroll
-            for (int p = 0; p < NP; ++p)
+            for (int i = 0; i < PX; ++i) {
+                const uint64_t cw[4] = {c1[i], c2[i], c3[i], c4[i]};
 #pragma unroll
-                for (int i = 0; i < PX; ++i) {
-                    sm.cs[buf][p][w][lane * PX + i] = cs[p][i];
-                    a[p][i] += cs[p][i];
+                for (int p = 0; p < NP; ++p) {
+                    sm.cs[buf][p][w][lane * PX + i] = cw[p];
+                    a[p][i] += cw[p];
                 }
+            }
         }
         uint64_t v[NP][PX];
         lookback(d, strip, xb, lane, a, v, state, fault);
@@ -1191,7 +1203,7 @@ struct BuildPow {
                 else pairv = *reinterpret_cast<const uint32_t *>(trow + 128 * sb);
                 const uint32_t v0 = sizeof(T) == 1 ? (pairv & 0xffu) : (pairv & 0xffffu);
                 const uint32_t v1 = sizeof(T) == 1 ? ((pairv >> 8) & 0xffu) : (pairv >> 16);
-                const ST a0 = pow_of<ST, P>(v0), a1 = pow_of<ST, P>(v1);
+                const ST a0 = pow_of<T, P>(v0), a1 = pow_of<T, P>(v1);
                 const ST pair = dpp_src_sum(a0, a1);
                 const ST incl = wave_scan(pair);
                 const uint64_t b = base + (incl - pair);

@@ -914,8 +914,10 @@ hipError_t launch_mean_std(int variant, const GatherDesc *descs, int n, const Ga
 // formed exactly in signed 128-bit integers (the host bounds n and the pixel range so that no
 // term overflows) and rounded to double once each:
 //   mean = S1/n, std = sqrt(A)/n, skewness = B / (A*sqrt(A)), excess kurtosis = (C - 3A^2)/(A*A),
-// population moments; skewness and kurtosis are NaN where A = 0.  One output row segment per
-// work item, reading the two table rows of each power (row pairs, banded for L2 reuse).
+// population moments; skewness and kurtosis are NaN where A = 0.  Where the window height is a
+// multiple of the stride the outputs come from chain walks (each table row of every power read
+// once, as for the mean and deviation); otherwise one output row segment per work item reads
+// the two table rows of each power (row pairs, banded for L2 reuse).
 
 namespace {
 
@@ -928,28 +930,36 @@ __device__ __forceinline__ double i128_to_double(i128 x) {
     return neg ? -r : r;
 }
 
+// 64 x 64 -> 128-bit products, the only wide multiplications below.
+__device__ __forceinline__ i128 mul64(uint64_t x, uint64_t y) {
+    return static_cast<i128>(static_cast<unsigned __int128>(x) * y);
+}
+
+// The numerators in factored forms with few wide products (the same integers as the expansions
+// above): with D = n*S3 - S1*S2 and F = n*S4 - 4*S1*S3 + 3*S2^2,
+//   B = n*D - 2*S1*A,    C - 3A^2 = n^2*F - 6*A^2.
+// n <= 2^32, so n^2 fits 64 bits; where the kurtosis is allowed, A < 2^63.
 template <int K>
 __device__ __forceinline__ void moments_store(const MomentDesc &d, int64_t o, const uint64_t (&s)[K], uint64_t n,
                                               double dn) {
     if (d.mean) __builtin_nontemporal_store(static_cast<double>(s[0]) / dn, d.mean + o);
     if constexpr (K >= 2) {
-        const i128 N = static_cast<i128>(n), a1 = static_cast<i128>(s[0]), a2 = static_cast<i128>(s[1]);
-        const i128 A = N * a2 - a1 * a1;
+        const i128 A = mul64(n, s[1]) - mul64(s[0], s[0]);
         const double a = i128_to_double(A);
         const double ra = sqrt(a);
         if (d.stdv) __builtin_nontemporal_store(ra / dn, d.stdv + o);
         if constexpr (K >= 3) {
-            const i128 a3 = static_cast<i128>(s[2]);
             if (d.skew) {
-                const i128 B = N * N * a3 - 3 * N * a1 * a2 + 2 * a1 * a1 * a1;
+                const i128 D = mul64(n, s[2]) - mul64(s[0], s[1]);
+                const i128 B = static_cast<i128>(n) * D - 2 * static_cast<i128>(s[0]) * A;
                 __builtin_nontemporal_store(A == 0 ? __builtin_nan("") : i128_to_double(B) / (a * ra), d.skew + o);
             }
             if constexpr (K >= 4) {
                 if (d.kurt) {
-                    const i128 a4 = static_cast<i128>(s[3]);
-                    const i128 C = N * N * N * a4 - 4 * N * N * a1 * a3 + 6 * N * a1 * a1 * a2 - 3 * a1 * a1 * a1 * a1;
-                    __builtin_nontemporal_store(A == 0 ? __builtin_nan("") : i128_to_double(C - 3 * A * A) / (a * a),
-                                                d.kurt + o);
+                    const i128 F = mul64(n, s[3]) - 4 * mul64(s[0], s[2]) + 3 * mul64(s[1], s[1]);
+                    const uint64_t a64 = static_cast<uint64_t>(A);
+                    const i128 E = static_cast<i128>(n * n) * F - 6 * mul64(a64, a64);
+                    __builtin_nontemporal_store(A == 0 ? __builtin_nan("") : i128_to_double(E) / (a * a), d.kurt + o);
                 }
             }
         }
@@ -989,9 +999,104 @@ __global__ __launch_bounds__(256) void moments_kernel(MomentDesc d, int64_t band
     }
 }
 
+// Chain walk over K tables: chain position j reads table row (r + j*q)*stride - 1 of every power
+// once; output row r + (j-1)*q is the difference of the corner differences at positions j and
+// j-1 (q*stride = win_h).
+template <int K, int V>
+__global__ __launch_bounds__(256) void chain_moments_kernel(MomentDesc d, int64_t q, int64_t seg, int64_t total,
+                                                            int64_t per_xcd) {
+    const int64_t item = xcd_item(per_xcd);
+    if (item >= total) return;
+    const ChainItem it = chain_item(item, d.chunks, q, seg);
+    const int64_t pend = chain_end(d.oh, it.r, q, it.j0, seg);
+    if (pend < it.j0) return;
+    const int64_t jlast = pend + 1;
+    const int tid = threadIdx.x;
+    const int32_t s = static_cast<int32_t>(d.stride);
+    int32_t lx[V], xl[V], xr[V];
+    bool has_left[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        lx[v] = static_cast<int32_t>(it.c * (256 * V)) + v * 256 + tid;
+        const int32_t lc = lx[v] < d.ow ? lx[v] : static_cast<int32_t>(d.ow) - 1;
+        has_left[v] = lc > 0;
+        xl[v] = lc > 0 ? lc * s - 1 : 0;
+        xr[v] = lc * s + static_cast<int32_t>(d.win_w) - 1;
+    }
+    const uint64_t nn = static_cast<uint64_t>(d.win_h) * static_cast<uint64_t>(d.win_w);
+    const double dn = static_cast<double>(nn);
+    auto load = [&](int64_t j, uint64_t (&rows)[2 * K][V]) {
+        const int64_t t = (it.r + j * q) * d.stride - 1;
+        const int64_t off = (t > 0 ? t : 0) * d.spitch;
+#pragma unroll
+        for (int p = 0; p < K; ++p) {
+            const uint64_t *pt = d.T[p] + off;
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                rows[2 * p][v] = pt[xl[v]];
+                rows[2 * p + 1][v] = pt[xr[v]];
+            }
+        }
+    };
+    uint64_t cur[2 * K][V], nxt[2 * K][V], prev[K][V];
+    load(it.j0, cur);
+#pragma unroll 1
+    for (int64_t j = it.j0; j <= jlast; ++j) {
+        if (j < jlast) load(j + 1, nxt);
+        const bool row_ok = it.r + j * q > 0;
+        const int64_t orow = (it.r + (j - 1) * q) * d.opitch;
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            uint64_t dd[K];
+#pragma unroll
+            for (int p = 0; p < K; ++p) dd[p] = row_ok ? cur[2 * p + 1][v] - (has_left[v] ? cur[2 * p][v] : 0) : 0;
+            if (j > it.j0 && lx[v] < d.ow) {
+                uint64_t sums[K];
+#pragma unroll
+                for (int p = 0; p < K; ++p) sums[p] = dd[p] - prev[p][v];
+                moments_store<K>(d, orow + lx[v], sums, nn, dn);
+            }
+#pragma unroll
+            for (int p = 0; p < K; ++p) prev[p][v] = dd[p];
+        }
+#pragma unroll
+        for (int k = 0; k < 2 * K; ++k)
+#pragma unroll
+            for (int v = 0; v < V; ++v) cur[k][v] = nxt[k][v];
+    }
+}
+
+template <int K>
+void launch_chain_moments(const MomentDesc &d, int V, int64_t q, int64_t seg, int64_t total, hipStream_t stream) {
+    int64_t grid = 0, per = 0;
+    xcd_grid(total, &grid, &per);
+    if (V == 2)
+        hipLaunchKernelGGL((chain_moments_kernel<K, 2>), dim3(static_cast<unsigned>(grid)), dim3(256), 0, stream, d, q,
+                           seg, total, per);
+    else
+        hipLaunchKernelGGL((chain_moments_kernel<K, 1>), dim3(static_cast<unsigned>(grid)), dim3(256), 0, stream, d, q,
+                           seg, total, per);
+}
+
 }  // namespace
 
-hipError_t launch_window_moments(int order, MomentDesc d, hipStream_t stream) {
+hipError_t launch_window_moments(int variant, int order, MomentDesc d, hipStream_t stream) {
+    if (order < 1 || order > 4) return hipErrorInvalidValue;
+    if (kGather[variant].kind == G_CHAIN && d.win_h % d.stride == 0) {
+        const int V = d.stride > 1 ? 2 : 1;
+        const int64_t q = d.win_h / d.stride;
+        d.chunks = (d.ow + 256 * V - 1) / (256 * V);
+        const int64_t P = (d.oh + q - 1) / q;                 // chain positions with outputs
+        const int64_t seg = chain_segments(q * d.chunks, P, 1);
+        const int64_t total = q * d.chunks * ((P + seg - 1) / seg);
+        switch (order) {
+            case 1: launch_chain_moments<1>(d, V, q, seg, total, stream); break;
+            case 2: launch_chain_moments<2>(d, V, q, seg, total, stream); break;
+            case 3: launch_chain_moments<3>(d, V, q, seg, total, stream); break;
+            default: launch_chain_moments<4>(d, V, q, seg, total, stream); break;
+        }
+        return hipGetLastError();
+    }
     constexpr int V = 2;
     d.chunks = (d.ow + 256 * V - 1) / (256 * V);
     GatherDesc g{};

@@ -101,8 +101,9 @@ struct MomentDesc {
     int64_t opitch;
     int64_t chunks;          // column chunks per output row (filled by the launcher)
 };
-// order: number of tables read (1 mean, 2 std, 3 skewness, 4 excess kurtosis).
-hipError_t launch_window_moments(int order, MomentDesc d, hipStream_t stream);
+// order: number of tables read (1 mean, 2 std, 3 skewness, 4 excess kurtosis).  variant: a
+// gather variant; chain variants walk chains where the window height is a multiple of the stride.
+hipError_t launch_window_moments(int variant, int order, MomentDesc d, hipStream_t stream);
 
 int gather_variant_count();
 const char *gather_variant_name(int v);
