@@ -470,10 +470,10 @@ sat_status window_mean_std(const uint64_t *sat, const uint64_t *sat_sq, int64_t 
 
 namespace {
 
-// Geometry of the power build (for strip heights and state sizes): 2 pixels per lane, 16 rows per
+// Geometry of the power build (for strip heights and state sizes): 4 pixels per lane, 16 rows per
 // wave, 4 compute waves.
-const satk::BuildVariant kPowVariant{"power_px2_rw16_nw4", 2, 16, 4, satk::MODE_HELPER};
-static_assert(2 * 64 == satk::kPowBlockW && 16 * 4 == satk::kPowStripH, "power build geometry");
+const satk::BuildVariant kPowVariant{"power_px4_rw16_nw4", 4, 16, 4, satk::MODE_HELPER};
+static_assert(4 * 64 == satk::kPowBlockW && 16 * 4 == satk::kPowStripH, "power build geometry");
 
 int64_t power_state_words(int64_t H, int64_t W, int k, int strip_h) {
     const int64_t strips = (H + strip_h - 1) / strip_h;

@@ -67,7 +67,7 @@ hipError_t launch_build(int variant, int bpp, bool sq, const BuildDesc *descs, i
 
 // Tables of pixel^1..pixel^np of one image (S, Q, T3, T4 of the descriptor) in one pass: the
 // helper-wave build with np lookback planes of nstrips * Wp words each (state_off: the first).
-constexpr int kPowBlockW = 128;   // block width (columns) of the power build
+constexpr int kPowBlockW = 256;   // block width (columns) of the power build
 constexpr int kPowStripH = 64;    // its largest strip height
 int power_build_capacity(int bpp, int np);
 hipError_t launch_build_powers(int bpp, int np, const BuildDesc &d, void *workspace, int64_t state_words,
