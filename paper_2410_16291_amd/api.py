@@ -249,12 +249,14 @@ def sat_build_powers(image: torch.Tensor, k: int, tables: Optional[List[torch.Te
     return list(tables)
 
 
-def window_moments(tables: List[torch.Tensor], h: int, w: int, stride: int = 1, pixel_type: str = "u8",
+def window_moments(tables: List[torch.Tensor], h: int, w: int, stride: int = 1, *, pixel_type: str,
                    stats: Tuple[str, ...] = MOMENTS, outs: Optional[dict] = None,
                    stream: Optional[torch.cuda.Stream] = None) -> dict:
     """{name: float64 output} for `stats` (a subset of mean, std, skew, kurt: population moments,
     skewness and excess kurtosis, NaN for constant windows) of every window, from the tables of
-    pixel^1 .. pixel^k (sat_build_powers; k at least the order of the highest statistic)."""
+    pixel^1 .. pixel^k (sat_build_powers; k at least the order of the highest statistic).
+    pixel_type ("u8" or "u16", the image the tables came from) is required: it bounds the sums
+    for the overflow checks."""
     for t in tables:
         _require_cuda(t, "table")
         if t.shape != tables[0].shape or t.stride(0) != tables[0].stride(0):
