@@ -275,35 +275,40 @@ struct Build {
     // after publishing this strip's own totals a / aq.  Run by one full wave.
     // Offset of the lane's p-th column from its first column (2 * lane) inside a block.
     static __device__ __forceinline__ int soff(int p) { return (p >> 1) * 128 + (p & 1); }
+    // Lookback word of lane l's p-th column in a block's state row: p * 64 + l.  Only the lookback
+    // writes and reads these words, so any fixed permutation of the block's columns serves; this
+    // one makes every 64-lane access 512 contiguous bytes (whole cache lines), where the column
+    // order (soff) would touch every line half.
+    static __device__ __forceinline__ int lslot(int p) { return p * 64; }
 
     static __device__ void lookback(const BuildDesc &d, int strip, int64_t xb, int lane,
                                     const uint64_t (&a)[PX], const uint64_t (&aq)[PX],
                                     uint64_t (&v)[PX], uint64_t (&vq)[PX], uint64_t *state,
                                     unsigned int *fault) {
-        uint64_t *mine = state + d.state_off + static_cast<int64_t>(strip) * d.Wp + xb + 2 * lane;
-        uint64_t *mine_q = state + d.state_q_off + static_cast<int64_t>(strip) * d.Wp + xb + 2 * lane;
+        uint64_t *mine = state + d.state_off + static_cast<int64_t>(strip) * d.Wp + xb + lane;
+        uint64_t *mine_q = state + d.state_q_off + static_cast<int64_t>(strip) * d.Wp + xb + lane;
 #pragma unroll
         for (int p = 0; p < PX; ++p) { v[p] = 0; vq[p] = 0; }
         if (strip == 0) {
 #pragma unroll
             for (int p = 0; p < PX; ++p) {
-                store_state(mine + soff(p), kStPrefix | a[p]);
-                if (SQ) store_state(mine_q + soff(p), kStPrefix | aq[p]);
+                store_state(mine + lslot(p), kStPrefix | a[p]);
+                if (SQ) store_state(mine_q + lslot(p), kStPrefix | aq[p]);
             }
             return;
         }
 #pragma unroll
         for (int p = 0; p < PX; ++p) {
-            store_state(mine + soff(p), kStAggregate | a[p]);
-            if (SQ) store_state(mine_q + soff(p), kStAggregate | aq[p]);
+            store_state(mine + lslot(p), kStAggregate | a[p]);
+            if (SQ) store_state(mine_q + lslot(p), kStAggregate | aq[p]);
         }
         constexpr uint32_t kAll = SQ ? ((1u << (2 * PX)) - 1u) : ((1u << PX) - 1u);
         uint32_t done = 0;
         uint32_t spins = 0;
         int j = strip - 1;
         for (;;) {
-            const uint64_t *up = state + d.state_off + static_cast<int64_t>(j) * d.Wp + xb + 2 * lane;
-            const uint64_t *up_q = state + d.state_q_off + static_cast<int64_t>(j) * d.Wp + xb + 2 * lane;
+            const uint64_t *up = state + d.state_off + static_cast<int64_t>(j) * d.Wp + xb + lane;
+            const uint64_t *up_q = state + d.state_q_off + static_cast<int64_t>(j) * d.Wp + xb + lane;
             uint64_t w[PX], wq[PX];
             bool ready = true;
 #pragma unroll
@@ -311,11 +316,11 @@ struct Build {
                 w[p] = 0;
                 wq[p] = 0;
                 if (!(done & (1u << p))) {
-                    w[p] = load_state(up + soff(p));
+                    w[p] = load_state(up + lslot(p));
                     ready = ready && (w[p] >> 62) != 0;
                 }
                 if (SQ && !(done & (1u << (PX + p)))) {
-                    wq[p] = load_state(up_q + soff(p));
+                    wq[p] = load_state(up_q + lslot(p));
                     ready = ready && (wq[p] >> 62) != 0;
                 }
             }
@@ -343,8 +348,8 @@ struct Build {
         }
 #pragma unroll
         for (int p = 0; p < PX; ++p) {
-            store_state(mine + soff(p), kStPrefix | (v[p] + a[p]));
-            if (SQ) store_state(mine_q + soff(p), kStPrefix | (vq[p] + aq[p]));
+            store_state(mine + lslot(p), kStPrefix | (v[p] + a[p]));
+            if (SQ) store_state(mine_q + lslot(p), kStPrefix | (vq[p] + aq[p]));
         }
     }
 
@@ -358,7 +363,7 @@ struct Build {
                                         const uint64_t (&a)[PX], const uint64_t (&aq)[PX],
                                         uint64_t (&v)[PX], uint64_t (&vq)[PX], uint64_t *state,
                                         unsigned int *fault) {
-        const int64_t col0 = xb + 2 * lane;
+        const int64_t col0 = xb + lane;
         uint64_t *mine = state + d.state_off + static_cast<int64_t>(strip) * d.Wp + col0;
         uint64_t *mine_q = state + d.state_q_off + static_cast<int64_t>(strip) * d.Wp + col0;
 #pragma unroll
@@ -366,15 +371,15 @@ struct Build {
         if (strip == 0) {
 #pragma unroll
             for (int p = 0; p < PX; ++p) {
-                store_state(mine + soff(p), kStPrefix | a[p]);
-                if (SQ) store_state(mine_q + soff(p), kStPrefix | aq[p]);
+                store_state(mine + lslot(p), kStPrefix | a[p]);
+                if (SQ) store_state(mine_q + lslot(p), kStPrefix | aq[p]);
             }
             return;
         }
 #pragma unroll
         for (int p = 0; p < PX; ++p) {
-            store_state(mine + soff(p), kStAggregate | a[p]);
-            if (SQ) store_state(mine_q + soff(p), kStAggregate | aq[p]);
+            store_state(mine + lslot(p), kStAggregate | a[p]);
+            if (SQ) store_state(mine_q + lslot(p), kStAggregate | aq[p]);
         }
         constexpr uint32_t kAll = SQ ? ((1u << (2 * PX)) - 1u) : ((1u << PX) - 1u);
         uint32_t done = 0;
@@ -391,8 +396,8 @@ struct Build {
                 for (int p = 0; p < PX; ++p) {
                     w[k][p] = 0;
                     wq[k][p] = 0;
-                    if (jj >= 0 && !(done & (1u << p))) w[k][p] = load_state(up + soff(p));
-                    if (SQ && jj >= 0 && !(done & (1u << (PX + p)))) wq[k][p] = load_state(up_q + soff(p));
+                    if (jj >= 0 && !(done & (1u << p))) w[k][p] = load_state(up + lslot(p));
+                    if (SQ && jj >= 0 && !(done & (1u << (PX + p)))) wq[k][p] = load_state(up_q + lslot(p));
                 }
             }
             int consumed = 0;
@@ -436,8 +441,8 @@ struct Build {
         }
 #pragma unroll
         for (int p = 0; p < PX; ++p) {
-            store_state(mine + soff(p), kStPrefix | (v[p] + a[p]));
-            if (SQ) store_state(mine_q + soff(p), kStPrefix | (vq[p] + aq[p]));
+            store_state(mine + lslot(p), kStPrefix | (v[p] + a[p]));
+            if (SQ) store_state(mine_q + lslot(p), kStPrefix | (vq[p] + aq[p]));
         }
     }
 
@@ -1008,7 +1013,7 @@ __device__ __forceinline__ PowT<T, P> pow_of(uint32_t v) {
 
 template <typename T, int NP, int PX, int RW, int NW, bool NTS>
 struct BuildPow {
-    using B1 = Build<T, false, PX, RW, NW, MODE_LOOKBACK>;   // column map (soff)
+    using B1 = Build<T, false, PX, RW, NW, MODE_LOOKBACK>;   // lookback word map (lslot)
     static constexpr int TH = RW * NW;
     static constexpr int BW = 64 * PX;
     static constexpr int NS = PX / 2;
@@ -1038,7 +1043,7 @@ struct BuildPow {
     static __device__ void lookback(const BuildDesc &d, int strip, int64_t xb, int lane, const uint64_t (&a)[NP][PX],
                                     uint64_t (&v)[NP][PX], uint64_t *state, unsigned int *fault) {
         const int64_t plane = static_cast<int64_t>(d.nstrips) * d.Wp;
-        const int64_t col0 = xb + 2 * lane;
+        const int64_t col0 = xb + lane;
         uint64_t *mine = state + d.state_off + static_cast<int64_t>(strip) * d.Wp + col0;
 #pragma unroll
         for (int p = 0; p < NP; ++p)
@@ -1048,7 +1053,7 @@ struct BuildPow {
 #pragma unroll
         for (int p = 0; p < NP; ++p)
 #pragma unroll
-            for (int i = 0; i < PX; ++i) store_state(mine + p * plane + B1::soff(i), first | a[p][i]);
+            for (int i = 0; i < PX; ++i) store_state(mine + p * plane + B1::lslot(i), first | a[p][i]);
         if (strip == 0) return;
         constexpr uint32_t kAll = NP * PX == 32 ? 0xffffffffu : ((1u << (NP * PX)) - 1u);
         uint32_t done = 0, spins = 0;
@@ -1063,7 +1068,7 @@ struct BuildPow {
                 for (int i = 0; i < PX; ++i) {
                     w[p][i] = 0;
                     if (!(done & (1u << (p * PX + i)))) {
-                        w[p][i] = load_state(up + p * plane + B1::soff(i));
+                        w[p][i] = load_state(up + p * plane + B1::lslot(i));
                         ready = ready && (w[p][i] >> 62) != 0;
                     }
                 }
@@ -1091,7 +1096,7 @@ struct BuildPow {
 #pragma unroll
         for (int p = 0; p < NP; ++p)
 #pragma unroll
-            for (int i = 0; i < PX; ++i) store_state(mine + p * plane + B1::soff(i), kStPrefix | (v[p][i] + a[p][i]));
+            for (int i = 0; i < PX; ++i) store_state(mine + p * plane + B1::lslot(i), kStPrefix | (v[p][i] + a[p][i]));
     }
 
     // Helper wave: per-wave column sums of every power of tile `buf`, the lookback, and the
