@@ -48,6 +48,7 @@ def parse():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving section")
     ap.add_argument("--no-banded", action="store_true", help="skip the banded (out-of-core) section")
     ap.add_argument("--no-moments", action="store_true", help="skip the higher-moments section")
+    ap.add_argument("--no-meanstd", action="store_true", help="skip the 8192^2 16-bit mean/std section")
     ap.add_argument("--moments-size", type=int, default=32768)
     ap.add_argument("--band-rows", type=int, default=8192)
     ap.add_argument("--serve-seconds", type=float, default=10.0, help="length of the 50 req/s request stream")
@@ -175,13 +176,59 @@ def batched_section(torch, dev, n_images):
     return res
 
 
+def timed_ms(torch, stream, fn, reps):
+    """Mean HIP-event time of `fn` on `stream` over `reps` runs after one untimed run."""
+    import numpy as np
+    fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        fn()
+        b.record(stream)
+        b.synchronize()
+        ts.append(a.elapsed_time(b))
+    return float(np.mean(ts))
+
+
+def meanstd_section(torch, dev, n, reps):
+    """An n x n uint16 log-normal image (mu 6, sigma 1): tables of pixels and squares, then the
+    sum, mean and std of every 64 x 64 window at stride 1.  Algorithmic bytes: image + S + Q for
+    the build (18 B/px); S and Q read once and 24 B per output for the statistics."""
+    from paper_2410_16291_amd import api, synth
+    h = 64
+    img = api.empty_image(n, n, torch.uint16, dev)
+    img.copy_(synth.lognormal_u16_device(n, n, 1, dev))
+    S = api.empty_table(n, n, dev)
+    Q = api.empty_table(n, n, dev, S.stride(0))
+    ws = torch.empty(api.build_workspace_bytes(n, n, 2, True), dtype=torch.uint8, device=dev)
+    oh, ow = api.out_shape(n, n, h, h, 1)
+    outs = (api.empty_out(oh, ow, torch.uint64, dev), api.empty_out(oh, ow, torch.float64, dev),
+            api.empty_out(oh, ow, torch.float64, dev))
+    stream = torch.cuda.current_stream(dev)
+    t_build = timed_ms(torch, stream, lambda: api.sat_build(img, sat=S, sat_sq=Q, ws=ws), reps)
+    api.workspace_check(ws)
+    t_stats = timed_ms(torch, stream, lambda: api.window_mean_std(S, Q, h, h, 1, outs=outs), reps)
+    alg_b = n * n * 18
+    alg_g = n * n * 16 + oh * ow * 24
+    res = {"workload": "%dx%d uint16 log-normal intensities (mu 6, sigma 1, seed 1); tables of pixels and squares; "
+                       "sum, mean and std of every %dx%d window at stride 1" % (n, n, h, h),
+           "build_ms": round(t_build, 4), "build_GB_s": round(alg_b / (t_build * 1e-3) / 1e9, 1),
+           "build_frac_hbm_peak": round(alg_b / (t_build * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+           "mean_std_ms": round(t_stats, 4), "mean_std_GB_s": round(alg_g / (t_stats * 1e-3) / 1e9, 1),
+           "mean_std_frac_hbm_peak": round(alg_g / (t_stats * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+           "gpix_s": round(n * n / ((t_build + t_stats) * 1e-3) / 1e9, 2)}
+    del img, S, Q, ws, outs
+    torch.cuda.empty_cache()
+    return res
+
+
 def moments_section(torch, dev, n, reps):
     """Tables of pixel^1..pixel^4 of an n x n 8-bit intensity image in one pass, then the mean, std,
     skewness and excess kurtosis of every 64 x 64 window at stride 1 (HIP events on the launch
     stream, inputs resident).  Algorithmic bytes: the image and four tables for the build
     (1 + 32 B/px); four tables read once and four float64 outputs for the gather."""
-    import numpy as np
-
     from paper_2410_16291_amd import api, synth
     h = 64
     img = api.empty_image(n, n, torch.uint8, dev)
@@ -192,23 +239,9 @@ def moments_section(torch, dev, n, reps):
     oh, ow = api.out_shape(n, n, h, h, 1)
     outs = {k: api.empty_out(oh, ow, torch.float64, dev) for k in api.MOMENTS}
     stream = torch.cuda.current_stream(dev)
-
-    def timed(fn):
-        fn()
-        torch.cuda.synchronize()
-        ts = []
-        for _ in range(reps):
-            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            a.record(stream)
-            fn()
-            b.record(stream)
-            b.synchronize()
-            ts.append(a.elapsed_time(b))
-        return float(np.mean(ts))
-
-    t_build = timed(lambda: api.sat_build_powers(img, 4, tables=tables, ws=ws))
+    t_build = timed_ms(torch, stream, lambda: api.sat_build_powers(img, 4, tables=tables, ws=ws), reps)
     api.workspace_check(ws)
-    t_gather = timed(lambda: api.window_moments(tables, h, h, 1, pixel_type="u8", outs=outs))
+    t_gather = timed_ms(torch, stream, lambda: api.window_moments(tables, h, h, 1, pixel_type="u8", outs=outs), reps)
     alg_b = n * n * (1 + 32)
     alg_g = n * n * 32 + oh * ow * 32
     res = {"workload": "%dx%d uint8 log-normal intensities (mu 4, sigma 0.9, seed 5, clipped to 255); tables of "
@@ -411,6 +444,8 @@ def main():
         res["batched"] = batched_section(torch, dev, args.batch_images)
     if not args.no_banded:
         res["banded"] = banded_section(torch, dev, H, W, args.band_rows)
+    if not args.no_meanstd:
+        res["mean_std_8192"] = meanstd_section(torch, dev, 8192, 10)
     if not args.no_moments:
         res["moments"] = moments_section(torch, dev, args.moments_size, 5)
     if not args.no_serve:
