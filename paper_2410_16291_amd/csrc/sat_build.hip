@@ -9,11 +9,11 @@
 //   C_w[x]  = sum of column x above row y0_w  (strip column totals from the lookback, plus the
 //             rows of the waves above this one inside the strip)
 //
-// A workgroup owns one strip of TH = RW*NW rows and sweeps it left to right in blocks of
-// BW = 64*PX columns; wave w owns RW rows of the strip and lane l owns PX adjacent columns of a
-// block.  The row direction is handled by the sweep itself (the left carry L of each row is a
-// register); the column direction crosses strips, and the totals of the strips above come from
-// a decoupled lookback down each column:
+// A workgroup owns one strip of up to TH = RW*NW rows and sweeps it left to right in blocks of
+// BW = 64*PX columns; wave w owns a band of the strip's rows and lane l owns the column pair
+// (2l, 2l+1) of every 128-column sub-block of a block.  The row direction is handled by the sweep
+// itself (the left carry L of each row is a register); the column direction crosses strips, and
+// the totals of the strips above come from a decoupled lookback down each column:
 //   - for block b the strip publishes its column totals A (status "aggregate"),
 //   - reads the state of the strip above: an inclusive total P ends the walk, an aggregate is
 //     added and the walk continues one strip higher,
@@ -25,9 +25,16 @@
 // on dispatch order.  Every wait is bounded; a wait that exceeds the bound sets a fault word in
 // the workspace and the kernel still completes.
 //
-// The same strip code also runs in a reduce-then-scan mode (an ablation): one kernel writes the
-// strip column totals, a second scans them down each column, and the strip kernel then reads
-// its totals instead of looking back.
+// Three strip workers share this scheme:
+//   Build     every wave computes; wave 0 runs the lookback between two workgroup barriers.  The
+//             same code also runs in a reduce-then-scan mode (an ablation): one kernel writes the
+//             strip column totals, a second scans them down each column, and the strip kernel
+//             then reads its totals instead of looking back.
+//   Build2    four compute waves and a helper wave that stages the next tile by LDS DMA, forms
+//             its column sums and runs its lookback one block ahead, so that the lookback's
+//             memory round trip is never on the compute waves' path.
+//   BuildPow  Build2 for the tables of pixel^1..pixel^k (k lookback planes, one pass over the
+//             LDS tile per power).
 //
 // Per-row work: the 64 lanes of a wave scan a row of BW pixels with DPP (row_shr 1/2/4/8 within
 // rows of 16 lanes, then row_bcast 15 and 31 across them) in 32-bit integers, which cannot
