@@ -70,7 +70,8 @@ sat_status window_out_shape(int64_t H, int64_t W, int64_t win_h, int64_t win_w, 
 
 /* Bytes of device workspace sat_build needs for an H x W image (with_sq != 0: also the squared
  * table), for the kernel variant a sat_build on the calling thread would use (the built-in choice
- * for this size, or the one sat_force_variant set).  Returns 0 for invalid sizes.  The workspace
+ * for this size, whatever the alignment of the image's rows, or the one sat_force_variant set).
+ * Returns 0 for invalid sizes.  The workspace
  * holds one lookback word per column per strip of rows for the column scan and a control block;
  * its contents need no initialisation and are scratch after the call returns, but the workspace
  * must not be shared by two builds in flight. */
@@ -79,7 +80,9 @@ size_t sat_build_workspace_bytes(int64_t H, int64_t W, sat_dtype pixel_type, int
 /* Integral image of an H x W image (Sec. II-B, Sec. III-B):
  *   sat[y*sat_pitch + x]    = sum_{i<=y, j<=x} image[i*image_pitch + j]           (mod 2^64)
  *   sat_sq[y*sat_pitch + x] = sum_{i<=y, j<=x} image[i*image_pitch + j]^2        (mod 2^64)
- * image: device, pixel_type SAT_U8 or SAT_U16, pitch image_pitch >= W elements.
+ * image: device, pixel_type SAT_U8 or SAT_U16, pitch image_pitch >= W elements, any alignment;
+ * rows that start 16-byte aligned (base and pitch) let the build stage image tiles with 16-byte
+ * loads, its fastest form.
  * sat: device, H rows of sat_pitch >= W uint64_t; sat_sq: same shape and pitch, or NULL to skip
  * the squared table.  Entries beyond column W-1 of each row are not written.
  * workspace: device, >= sat_build_workspace_bytes(H, W, pixel_type, sat_sq != NULL) bytes.
