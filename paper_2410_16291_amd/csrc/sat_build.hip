@@ -1322,9 +1322,10 @@ __global__ __launch_bounds__((NW + 1) * 64) void build2_kernel(const BuildDesc *
 }
 
 // Persistent strip kernel: each workgroup takes strips (of one image, or of a batch) from the
-// ticket counter until none are left.  The occupancy hint holds the 4-pixel variants to 128
-// VGPRs (four waves per SIMD); the 8-pixel ones need more and stay at two or one, for which the
-// compiler reports the hint as not met (-Wpass-failed), as expected.
+// ticket counter until none are left.  The occupancy hint holds the variants that can to 128
+// VGPRs (four waves per SIMD, e.g. 4 pixels per lane on 8-bit images); the others (8 pixels per
+// lane, or 16-bit pixels with squares) need more and stay at two or one wave per SIMD, for which
+// the compiler reports the hint as not met (-Wpass-failed), as expected.
 template <typename T, bool SQ, int PX, int RW, int NW, int MODE, bool NTS>
 __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(16 / NW > 4 ? 4 : 16 / NW)))
 void build_kernel(const BuildDesc *__restrict__ many, int n, long long total_items, uint64_t *state,
