@@ -70,7 +70,9 @@ def test_power_tables_many_strips_and_rounds():
         assert torch.equal(Q.view(torch.int64), Q2.view(torch.int64))
 
 
-MOMENT_CASES = [(1, 1, 1), (5, 7, 1), (16, 16, 4), (33, 9, 3), (64, 64, 1), (1, 200, 2), (300, 420, 1)]
+# windows from 1 x 1 to 300 x 420 at strides 1 to 4
+MOMENT_CASES = [(1, 1, 1), (5, 7, 1), (16, 16, 4), (33, 9, 3), (64, 64, 1), (66, 66, 1), (70, 70, 1), (1, 200, 2),
+                (300, 420, 1)]
 PATHS = [None, "rowpair_v4_banded"]          # built-in (chain walks where they apply), row pairs
 
 
