@@ -1066,6 +1066,123 @@ __global__ __launch_bounds__(256) void chain_moments_kernel(MomentDesc d, int64_
     }
 }
 
+// Stride-1 chain walk with the row spans of all K tables staged in LDS (the scheme of
+// chain_lds_kernel for one window, lag 1): a work item owns kLdsC consecutive outputs; at every
+// chain step its workgroup loads the table rows' columns [x0 - 1, x0 + kLdsC + w - 1) of each
+// power once into a two-slot ring, and forms each output's power sums as
+//     (T_j[l + w - 1] - T_{j-1}[l + w - 1]) - (T_j[l - 1] - T_{j-1}[l - 1]).
+// Two steps' loads are in flight (unrolled by two, unconditional clamped loads); the epilogue
+// loop over a thread's outputs is not unrolled, to bound register use.
+template <int K, int NL>
+__global__ __launch_bounds__(kLdsBS) void chain_lds_moments_kernel(MomentDesc d, int64_t q, int64_t seg, int64_t total,
+                                                                   int64_t per_xcd, int32_t span) {
+    extern __shared__ __align__(16) unsigned char ring_raw[];
+    uint64_t *ring = reinterpret_cast<uint64_t *>(ring_raw);        // [slot][power][span]
+    const int64_t item = xcd_item(per_xcd);
+    if (item >= total) return;
+    const ChainItem it = chain_item(item, d.chunks, q, seg);
+    const int64_t pend = chain_end(d.oh, it.r, q, it.j0, seg);
+    if (pend < it.j0) return;
+    const int64_t jlast = pend + 1;
+    const int tid = threadIdx.x;
+    const int64_t x0 = it.c * kLdsC;
+    const int64_t W = d.ow + d.win_w - 1;                          // table width (stride 1)
+    const int32_t w = static_cast<int32_t>(d.win_w);
+    const uint64_t nn = static_cast<uint64_t>(d.win_h) * static_cast<uint64_t>(d.win_w);
+    const double dn = static_cast<double>(nn);
+    int32_t colk[NL];
+    bool inside[NL];
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+        const int kk = k * kLdsBS + tid;
+        const int64_t col = x0 - 1 + kk;
+        inside[k] = kk < span && col >= 0 && col < W;
+        colk[k] = static_cast<int32_t>(col < 0 ? 0 : (col > W - 1 ? W - 1 : col));
+    }
+    auto gload = [&](int64_t j, uint64_t (&pre)[K][NL]) {
+        const int64_t jj = j <= jlast ? j : jlast;
+        const int64_t t = it.r + jj * q - 1;
+        const int64_t off = (t > 0 ? t : 0) * d.spitch;
+#pragma unroll
+        for (int p = 0; p < K; ++p) {
+            const uint64_t *row = d.T[p] + off;
+#pragma unroll
+            for (int k = 0; k < NL; ++k) pre[p][k] = row[colk[k]];
+        }
+    };
+    int slot = static_cast<int>(it.j0 & 1);
+    auto step = [&](int64_t j, const uint64_t (&pre)[K][NL]) {
+        __syncthreads();                                   // the slot reused now was last read a step ago
+        const bool rowok = it.r + j * q > 0;               // row -1 is all zero
+        uint64_t *dst = ring + static_cast<int64_t>(slot) * K * span;
+#pragma unroll
+        for (int p = 0; p < K; ++p)
+#pragma unroll
+            for (int k = 0; k < NL; ++k) {
+                const int kk = k * kLdsBS + tid;
+                if (kk < span) dst[p * span + kk] = (rowok && inside[k]) ? pre[p][k] : 0;
+            }
+        __syncthreads();
+        const int64_t prow = j - 1;                        // output position emitted at this step
+        if (prow >= it.j0 && prow <= pend) {
+            const uint64_t *cur = dst;
+            const uint64_t *old = ring + static_cast<int64_t>(slot ^ 1) * K * span;
+            const int64_t orow = (it.r + prow * q) * d.opitch + x0;
+#pragma unroll 1
+            for (int v = 0; v < kLdsV; ++v) {
+                const int u = v * kLdsBS + tid;
+                if (x0 + u < d.ow) {
+                    uint64_t sums[K];
+#pragma unroll
+                    for (int p = 0; p < K; ++p)
+                        sums[p] = (cur[p * span + u + w] - old[p * span + u + w]) - (cur[p * span + u] - old[p * span + u]);
+                    moments_store<K>(d, orow + u, sums, nn, dn);
+                }
+            }
+        }
+        slot ^= 1;
+    };
+    uint64_t pre0[K][NL], pre1[K][NL];
+    gload(it.j0, pre0);
+    gload(it.j0 + 1, pre1);
+#pragma unroll 1
+    for (int64_t j = it.j0; j <= jlast; j += 2) {
+        step(j, pre0);
+        gload(j + 2, pre0);
+        if (j + 1 > jlast) break;
+        step(j + 1, pre1);
+        gload(j + 3, pre1);
+    }
+}
+
+template <int K, int NL>
+hipError_t launch_lds_moments_typed(const MomentDesc &d, int64_t q, int64_t seg, int64_t total, int span, size_t lds,
+                                    hipStream_t s) {
+    static bool attr_set = false;      // the maximum is set once per instantiation
+    const void *fn = reinterpret_cast<const void *>(&chain_lds_moments_kernel<K, NL>);
+    if (!attr_set && lds > (64u << 10)) {
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(kLdsMaxBytes));
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    int64_t grid = 0, per = 0;
+    xcd_grid(total, &grid, &per);
+    hipLaunchKernelGGL((chain_lds_moments_kernel<K, NL>), dim3(static_cast<unsigned>(grid)), dim3(kLdsBS), lds, s, d, q,
+                       seg, total, per, static_cast<int32_t>(span));
+    return hipGetLastError();
+}
+
+template <int K>
+hipError_t launch_lds_moments(const MomentDesc &d, int64_t q, int64_t seg, int64_t total, int nl, int span, size_t lds,
+                              hipStream_t s) {
+    switch (nl) {
+        case 5: return launch_lds_moments_typed<K, 5>(d, q, seg, total, span, lds, s);
+        case 6: return launch_lds_moments_typed<K, 6>(d, q, seg, total, span, lds, s);
+        case 8: return launch_lds_moments_typed<K, 8>(d, q, seg, total, span, lds, s);
+        default: return launch_lds_moments_typed<K, 12>(d, q, seg, total, span, lds, s);
+    }
+}
+
 template <int K>
 void launch_chain_moments(const MomentDesc &d, int V, int64_t q, int64_t seg, int64_t total, hipStream_t stream) {
     int64_t grid = 0, per = 0;
@@ -1086,6 +1203,26 @@ void launch_chain_moments(const MomentDesc &d, int V, int64_t q, int64_t seg, in
 hipError_t launch_window_moments(int variant, int order, MomentDesc d, hipStream_t stream) {
     if (order < 1 || order > 4) return hipErrorInvalidValue;
     const GatherVariant &gv = kGather[variant];
+    int nl = 0, span = 0;
+    size_t lds = 0;
+    // Built-in chain choice at stride 1: the LDS-staged walk for up to three tables when its ring
+    // (two slots of each table's span) fits, and for three tables only up to 6 * 256 loaded
+    // columns.  At 32768^2, 64 x 64 it took 3.48 / 5.23 / 7.64 ms for one / two / three tables
+    // against 3.60 / 5.64 / 8.15 ms for the register walk; with four tables it holds 198 VGPRs,
+    // two waves per SIMD, and lost (15.24 against 14.78 ms), so four take the register walk.
+    if (gv.kind == G_CHAIN && gv.v == 0 && d.stride == 1 && order <= 3 &&
+        lds_plan(1, d.win_w, 2 * order - 1, true, &nl, &span, &lds) && (order <= 2 || nl <= 6)) {
+        const int64_t q = d.win_h;
+        d.chunks = (d.ow + kLdsC - 1) / kLdsC;
+        const int64_t P = (d.oh + q - 1) / q;
+        const int64_t seg = chain_segments(q * d.chunks, P, 1);
+        const int64_t total = q * d.chunks * ((P + seg - 1) / seg);
+        switch (order) {
+            case 1: return launch_lds_moments<1>(d, q, seg, total, nl, span, lds, stream);
+            case 2: return launch_lds_moments<2>(d, q, seg, total, nl, span, lds, stream);
+            default: return launch_lds_moments<3>(d, q, seg, total, nl, span, lds, stream);
+        }
+    }
     if (gv.kind == G_CHAIN && d.win_h % d.stride == 0) {
         // outputs per thread: four at stride 1 keep 32 loads per thread in flight (15.5 ms against
         // 16.6 ms with one at 32768^2, 64 x 64, four statistics); strides above 1 are insensitive

@@ -73,7 +73,9 @@ def test_power_tables_many_strips_and_rounds():
 # windows from 1 x 1 to 300 x 420 at strides 1 to 4
 MOMENT_CASES = [(1, 1, 1), (5, 7, 1), (16, 16, 4), (33, 9, 3), (64, 64, 1), (66, 66, 1), (70, 70, 1), (1, 200, 2),
                 (300, 420, 1)]
-PATHS = [None, "rowpair_v4_banded"]          # built-in (chain walks where they apply), row pairs
+# built-in (LDS-staged chain walk for up to three tables at stride 1, register chain walk
+# otherwise), register chain walk, row pairs
+PATHS = [None, "chain_v4", "rowpair_v4_banded"]
 
 
 @pytest.mark.parametrize("path", PATHS)
@@ -145,3 +147,24 @@ def test_moments_4096_u8_64x64():
     assert np.array_equal(to_host(got["mean"]), ref[0])
     for name, r in zip(("std", "skew", "kurt"), ref[1:]):
         check_close(to_host(got[name]), r, name)
+
+
+@pytest.mark.parametrize("stats", [("mean",), ("std",), ("mean", "std"), ("mean", "std", "skew")])
+def test_lds_walk_up_to_three_tables(stats):
+    """The LDS-staged chain walk (stride 1, up to three tables): windows from 1 x 1 to 2 x 1500
+    (spans of 5 to 8 loaded columns per thread), an image with ragged chunks, against the oracle."""
+    img_np = synth.lognormal_u16(700, 2900, 4.0, 0.9, rng=np.random.default_rng(31)).clip(0, 255).astype(np.uint8)
+    img = to_device(img_np)
+    k = {"mean": 1, "std": 2, "skew": 3}[stats[-1]]
+    tables = api.sat_build_powers(img, 3)
+    for h, w in [(1, 1), (64, 64), (300, 420), (5, 700), (2, 1500)]:
+        print("case: lds moments", stats, h, w, flush=True)
+        got = api.window_moments(tables[:k], h, w, 1, pixel_type="u8", stats=stats)
+        torch.cuda.synchronize()
+        _, ref = oracle.window_moments(img_np, h, w, 1, k=3)
+        for name in stats:
+            r = ref[{"mean": 0, "std": 1, "skew": 2}[name]]
+            if name == "mean":
+                assert np.array_equal(to_host(got[name]), r), (h, w)
+            else:
+                check_close(to_host(got[name]), r, name)
