@@ -332,8 +332,8 @@ def calibrate_copy(torch, dev):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py measures one GPU: the path has no multi-GPU implementation (how it would "
-              "shard is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the path has no multi-GPU implementation (it would shard "
+              "an image by strips of rows, one per GPU); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
