@@ -49,6 +49,7 @@ def parse():
     ap.add_argument("--no-banded", action="store_true", help="skip the banded (out-of-core) section")
     ap.add_argument("--no-moments", action="store_true", help="skip the higher-moments section")
     ap.add_argument("--no-meanstd", action="store_true", help="skip the 8192^2 16-bit mean/std section")
+    ap.add_argument("--no-shard", action="store_true", help="skip the one-GPU row-shard section")
     ap.add_argument("--moments-size", type=int, default=32768)
     ap.add_argument("--band-rows", type=int, default=8192)
     ap.add_argument("--serve-seconds", type=float, default=10.0, help="length of the 50 req/s request stream")
@@ -286,8 +287,9 @@ def serving_section(torch, dev, seconds, burst_seconds):
 
 def banded_section(torch, dev, H, W, band_rows):
     """The same window sums computed band by band, the table never materialised: the image
-    streamed from pinned host memory (PCIe included) and from device memory."""
-    from paper_2410_16291_amd import banded, synth
+    streamed from pinned host memory (PCIe included) and from device memory.  Then the whole table
+    built in HBM as the image streams in from pinned host memory."""
+    from paper_2410_16291_amd import api, banded, synth
 
     mask = synth.thomas_mask(H, W, seed=2)
     host = torch.empty((H, W), dtype=torch.uint8, pin_memory=True)
@@ -311,7 +313,59 @@ def banded_section(torch, dev, H, W, band_rows):
                      "device_GB": round((sum(t.numel() for t in job.dimg) + job.table.numel() * 8) / 1e9, 2)}
         del job, src
         torch.cuda.empty_cache()
-    del host
+    # the whole table in HBM, built band by band as the image streams in (no overlap rows: each
+    # band starts from the column totals of the rows above)
+    S = api.empty_table(H, W, dev)
+    banded.build_table_streamed(lambda r0, r1: host[r0:r1], H, W, "u8", band_rows=band_rows, device=dev, sat=S)
+    t0 = time.perf_counter()
+    banded.build_table_streamed(lambda r0, r1: host[r0:r1], H, W, "u8", band_rows=band_rows, device=dev, sat=S)
+    dt = time.perf_counter() - t0
+    res["table_from_pinned_host"] = {"ms": round(dt * 1e3, 2), "gpix_s": round(H * W / dt / 1e9, 2)}
+    del S, host
+    torch.cuda.empty_cache()
+    return res
+
+
+def shard_section(torch, dev, H, W, shards, reps):
+    """One GPU's share of the image split by rows over `shards` GPUs, at its real shape: the
+    column totals of its rows (what it would contribute to the exchange of totals), then its band
+    build seeded with the totals of the rows above (what the exchange would return), next to the
+    plain build of the same rows.  A middle shard of the bench mask; HIP events on the launch
+    stream, inputs resident.  Algorithmic bytes: the shard's image for the totals, its image and
+    table for the builds (plus the W-word vectors)."""
+    from paper_2410_16291_amd import api, synth
+
+    rows = H // shards
+    k = shards // 2
+    r0, r1 = k * rows, (k + 1) * rows
+    ys, xs = synth.thomas_points(H, W, seed=2)
+    img = api.empty_image(H, W, torch.uint8, dev)
+    img[torch.from_numpy(ys).to(dev), torch.from_numpy(xs).to(dev)] = 1
+    carry = api.column_totals(img[:r0])
+    band = img[r0:r1]
+    S = api.empty_table(rows, W, dev)
+    T = api.empty_totals(W, dev)
+    own = api.empty_totals(W, dev)
+    ws = torch.empty(api.build_workspace_bytes(rows, W, 1, False), dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    t_tot = timed_ms(torch, stream, lambda: api.column_totals(band, out=own), reps)
+    t_band = timed_ms(torch, stream, lambda: api.sat_build_band(band, carry=carry, rows_above=r0, sat=S, total=T,
+                                                                ws=ws), reps)
+    api.workspace_check(ws)
+    t_plain = timed_ms(torch, stream, lambda: api.sat_build(band, sat=S, ws=ws), reps)
+    px = rows * W
+    alg_tot = px + 16 * W
+    alg_band = 9 * px + 16 * W
+    res = {"workload": "rows %d..%d of the %dx%d mask above (one of %d row shards), 128-byte row pitch"
+                       % (r0, r1 - 1, H, W, shards),
+           "column_totals_ms": round(t_tot, 4), "column_totals_GB_s": round(alg_tot / (t_tot * 1e-3) / 1e9, 1),
+           "column_totals_frac_hbm_peak": round(alg_tot / (t_tot * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+           "band_build_ms": round(t_band, 4), "band_build_GB_s": round(alg_band / (t_band * 1e-3) / 1e9, 1),
+           "band_build_frac_hbm_peak": round(alg_band / (t_band * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+           "plain_build_ms": round(t_plain, 4),
+           "share_gpix_s": round(px / ((t_tot + t_band) * 1e-3) / 1e9, 2)}
+    del img, band, carry, S, T, own, ws
+    torch.cuda.empty_cache()
     return res
 
 
@@ -444,6 +498,8 @@ def main():
         res["batched"] = batched_section(torch, dev, args.batch_images)
     if not args.no_banded:
         res["banded"] = banded_section(torch, dev, H, W, args.band_rows)
+    if not args.no_shard:
+        res["row_shard"] = shard_section(torch, dev, H, W, 8, 10)
     if not args.no_meanstd:
         res["mean_std_8192"] = meanstd_section(torch, dev, 8192, 10)
     if not args.no_moments:

@@ -12,7 +12,9 @@
  *                    the four-corner lookup into the table (Sec. II-B; cost 4(r*c), Sec. III-B);
  *   window_mean_std  the window average and standard deviation from the two tables (Sec. II-A);
  *   window_sum_multi several window sizes from one table in one pass (Sec. I, Sec. V);
- *   *_batched        the same over many images in one launch.
+ *   *_batched        the same over many images in one launch;
+ *   sat_build_band   the table of a band of rows of a taller image, from the band and the column
+ *                    totals of the rows above it (sat_column_totals).
  *
  * Conventions shared by every call:
  *   - Images are row-major, 8- or 16-bit unsigned, with a row pitch in ELEMENTS (>= width; the
@@ -92,6 +94,50 @@ sat_status sat_build(const void *image, sat_dtype pixel_type, int64_t H, int64_t
                      int64_t image_pitch, uint64_t *sat, uint64_t *sat_sq, int64_t sat_pitch,
                      void *workspace, size_t workspace_bytes, void *stream);
 
+/* ---- Bands of a taller image.  The integral image is a prefix sum down the columns of the
+ * row-wise prefix sums (Sec. II-B), so the table rows of a band of image rows r0 .. r0+H-1 follow
+ * from the band alone plus one vector: the column totals of the rows above it,
+ *   carry[x] = sum_{i<r0} I[i][x],
+ * which contributes sum_{j<=x} carry[j] to every table entry of the band.  Building an image in
+ * bands (streamed from the host, or one band per GPU) therefore needs only these W-word vectors
+ * passed between bands. */
+
+/* Column totals of an H x W image added to a carry:
+ *   out[x]    = carry[x]    + sum_{y<H} image[y*image_pitch + x]                 (mod 2^64)
+ *   out_sq[x] = carry_sq[x] + sum_{y<H} image[y*image_pitch + x]^2               (mod 2^64)
+ * The carry of the next band, or (with carry = NULL) one band's own totals, for a caller that
+ * needs the totals of the rows above a band before that band's rows exist as a table.
+ * image: device, SAT_U8 or SAT_U16, as sat_build.  carry / carry_sq: device, W uint64_t, or NULL
+ * for zero; each may equal its output (accumulate in place) or must overlap no output.
+ * out: device, W uint64_t, 8-byte aligned; out_sq: device, W uint64_t, or NULL to skip the
+ * squares (carry_sq must then be NULL; with out_sq and a carry, carry_sq is required).
+ * Needs no workspace.  Errors: SAT_ERR_ARG, SAT_ERR_HIP. */
+sat_status sat_column_totals(const void *image, sat_dtype pixel_type, int64_t H, int64_t W,
+                             int64_t image_pitch, const uint64_t *carry, const uint64_t *carry_sq,
+                             uint64_t *out, uint64_t *out_sq, void *stream);
+
+/* Integral image of a band of rows of a taller image, given the column totals of the rows above
+ * it (Sec. II-B, as above).  With `image` the band's H rows and carry the column totals of the
+ * rows_above rows above it:
+ *   sat[y*sat_pitch + x] = sum_{j<=x} carry[j] + sum_{i<=y, j<=x} image[i*image_pitch + j],
+ * which is row rows_above + y of the whole image's table; sat_sq likewise from carry_sq and the
+ * squared pixels.  carry = NULL means no rows above (rows_above must be 0): then this is
+ * sat_build.
+ * total_out / total_sq_out: device, W uint64_t, or NULL: receive carry + this band's column
+ * totals (carry_sq + squared totals), the carry of the band below.  Each may equal its carry
+ * (advance a carry in place) or must overlap nothing else.
+ * rows_above bounds the carry: every carry[x] must be at most rows_above * max_pixel (and
+ * carry_sq[x] at most rows_above * max_pixel^2), as column totals of rows_above rows are.  The
+ * host refuses (rows_above + H) * max_pixel(^2) >= 2^62 with SAT_ERR_OVERFLOW; a carry beyond
+ * 2^62 - 1 - H * max_pixel(^2) makes sat_workspace_check report SAT_ERR_DEVICE.
+ * Other arguments, workspace (sat_build_workspace_bytes(H, W, ...)) and errors as sat_build;
+ * a carry with sat_sq needs carry_sq; carries and totals 8-byte aligned. */
+sat_status sat_build_band(const void *image, sat_dtype pixel_type, int64_t H, int64_t W,
+                          int64_t image_pitch, const uint64_t *carry, const uint64_t *carry_sq,
+                          int64_t rows_above, uint64_t *sat, uint64_t *sat_sq, int64_t sat_pitch,
+                          uint64_t *total_out, uint64_t *total_sq_out, void *workspace,
+                          size_t workspace_bytes, void *stream);
+
 /* Sum of every window of the valid region by the four-corner lookup (Sec. II-B):
  *   out[k*out_pitch + l] = T(y1, x1) - T(y0-1, x1) - T(y1, x0-1) + T(y0-1, x0-1),
  *   y0 = k*stride, y1 = y0+win_h-1, x0 = l*stride, x1 = x0+win_w-1, T(-1, .) = T(., -1) = 0.
@@ -162,8 +208,9 @@ sat_status window_mean_std_batched(const sat_batch_item *items, int32_t n, int64
                                    size_t workspace_bytes, void *stream);
 
 /* Synchronises `stream` and reads the fault word a build left in `workspace`: SAT_OK, or
- * SAT_ERR_DEVICE if a column-lookback wait hit its spin bound (the tables of that call are then
- * unreliable), or SAT_ERR_HIP.  Meant for tests and debugging; the fast path never waits. */
+ * SAT_ERR_DEVICE if a column-lookback wait hit its spin bound or a band build's carry exceeded
+ * the bound its rows_above sets (the tables of that call are then unreliable), or SAT_ERR_HIP.
+ * Meant for tests and debugging; the fast path never waits. */
 sat_status sat_workspace_check(void *workspace, void *stream);
 
 /* Message for the last error returned on the calling thread (static storage, never NULL). */

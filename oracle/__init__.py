@@ -36,6 +36,7 @@ def _load():
         lib.oracle_mean_std.restype = None
         lib.oracle_coverage_total.argtypes = [_p, ctypes.c_int] + [_i64] * 6
         lib.oracle_coverage_total.restype = ctypes.c_uint64
+        lib.oracle_column_totals.argtypes = [_p, ctypes.c_int, _i64, _i64, _i64, _p, _p, _p, _p]
         lib.oracle_sat_power.argtypes = [_p, ctypes.c_int, _i64, _i64, _i64, ctypes.c_int, _p]
         lib.oracle_window_powers.argtypes = [_p, ctypes.c_int] + [_i64] * 5 + [ctypes.c_int, _p]
         lib.oracle_window_powers.restype = None
@@ -79,6 +80,25 @@ def sat(img, squares=False):
     if rc:
         raise ValueError("oracle_sat rejected its arguments")
     return (S, Q) if squares else S
+
+
+def column_totals(img, squares=False, carry=None, carry_sq=None):
+    """Column totals of the image added to `carry` (uint64, zero if None): T[x] = carry[x] +
+    sum_y img[y, x] (mod 2^64).  Returns T, or (T, T2) with the totals of the squared pixels."""
+    img, bpp, pitch = _image(img)
+    H, W = img.shape
+    c = None if carry is None else np.ascontiguousarray(carry, dtype=np.uint64)
+    cq = None if carry_sq is None else np.ascontiguousarray(carry_sq, dtype=np.uint64)
+    for a in (c, cq):
+        if a is not None and a.shape != (W,):
+            raise ValueError("carry must have W entries")
+    T = np.empty(W, np.uint64)
+    T2 = np.empty(W, np.uint64) if squares else None
+    if _load().oracle_column_totals(_ptr(img), bpp, H, W, pitch, _ptr(c) if c is not None else None,
+                                    _ptr(cq) if cq is not None else None, _ptr(T),
+                                    _ptr(T2) if T2 is not None else None):
+        raise ValueError("oracle_column_totals: bad arguments")
+    return (T, T2) if squares else T
 
 
 def window_sum_sat(S, h, w, s=1):

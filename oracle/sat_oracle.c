@@ -64,6 +64,27 @@ int oracle_sat(const void *img, int bpp, int64_t H, int64_t W, int64_t pitch,
     return 0;
 }
 
+/* Column totals of an image (the column direction of the table of Sec. II-B): entry x is the
+ * sum of column x over all H rows, added to carry[x] (zero where carry is NULL); T2 likewise over
+ * the squared pixels (may be NULL).  Row r0 + y of a taller image's table is then the table of
+ * its rows r0 .. r0 + H' - 1 plus the running sum along x of the totals of rows 0 .. r0 - 1. */
+int oracle_column_totals(const void *img, int bpp, int64_t H, int64_t W, int64_t pitch,
+                         const uint64_t *carry, const uint64_t *carry_sq, uint64_t *T, uint64_t *T2) {
+    if (!img || !T || H < 1 || W < 1 || pitch < W || (bpp != 1 && bpp != 2)) return 1;
+    for (int64_t x = 0; x < W; ++x) {
+        T[x] = carry ? carry[x] : 0;
+        if (T2) T2[x] = carry_sq ? carry_sq[x] : 0;
+    }
+    for (int64_t y = 0; y < H; ++y) {       /* row by row, in memory order */
+        for (int64_t x = 0; x < W; ++x) {
+            uint64_t v = pixel(img, bpp, pitch, y, x);
+            T[x] += v;
+            if (T2) T2[x] += v * v;
+        }
+    }
+    return 0;
+}
+
 /* Table entry with the convention that row -1 and column -1 are zero. */
 static uint64_t sat_at(const uint64_t *S, int64_t W, int64_t y, int64_t x) {
     if (y < 0 || x < 0) return 0;

@@ -115,6 +115,78 @@ def sat_build(image: torch.Tensor, squares: bool = False, sat: Optional[torch.Te
     return (S, Q) if squares or sat_sq is not None else S
 
 
+def _vector(t: Optional[torch.Tensor], W: int, name: str) -> Optional[int]:
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("%s must be a device (cuda) tensor" % name)
+    if t.dtype not in (torch.uint64, torch.int64) or t.dim() != 1 or t.numel() != W or t.stride(0) != 1:
+        raise ValueError("%s must be a contiguous 64-bit vector of %d elements" % (name, W))
+    return t.data_ptr()
+
+
+def empty_totals(W: int, device) -> torch.Tensor:
+    """A device vector for W column totals."""
+    return torch.empty(W, dtype=torch.uint64, device=device)
+
+
+def column_totals(image: torch.Tensor, squares: bool = False, carry: Optional[torch.Tensor] = None,
+                  carry_sq: Optional[torch.Tensor] = None, out: Optional[torch.Tensor] = None,
+                  out_sq: Optional[torch.Tensor] = None, stream: Optional[torch.cuda.Stream] = None):
+    """Column totals of a 2-D uint8/uint16 device image added to `carry` (zero if None):
+    out[x] = carry[x] + sum_y image[y, x] (mod 2^64); with squares=True also of the squared pixels.
+    `out` may be `carry` itself.  Returns T, or (T, TQ)."""
+    _require_cuda(image, "image")
+    if image.dtype not in _PIXEL:
+        raise ValueError("image dtype must be uint8 or uint16")
+    H, W = image.shape
+    dev = image.device
+    T = out if out is not None else empty_totals(W, dev)
+    TQ = out_sq if out_sq is not None else (empty_totals(W, dev) if squares else None)
+    check(_lib.load().sat_column_totals(image.data_ptr(), _PIXEL[image.dtype], H, W, image.stride(0),
+                                        _vector(carry, W, "carry"), _vector(carry_sq, W, "carry_sq"),
+                                        _vector(T, W, "out"), _vector(TQ, W, "out_sq"),
+                                        _stream_handle(dev, stream)))
+    return (T, TQ) if TQ is not None else T
+
+
+def sat_build_band(image: torch.Tensor, carry: Optional[torch.Tensor] = None, rows_above: int = 0,
+                   squares: bool = False, carry_sq: Optional[torch.Tensor] = None,
+                   sat: Optional[torch.Tensor] = None, sat_sq: Optional[torch.Tensor] = None,
+                   totals: bool = True, total: Optional[torch.Tensor] = None,
+                   total_sq: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None,
+                   stream: Optional[torch.cuda.Stream] = None):
+    """Table rows rows_above .. rows_above+H-1 of a taller image from its band of rows `image` and
+    `carry`, the column totals of the rows_above rows above the band (None: no rows above).
+
+    With totals=True the band's column totals through its last row (carry included: the carry of
+    the band below) are returned as well; `total` may be `carry` itself to advance it in place.
+    Returns (S, T), or (S, Q, T, TQ) with squares=True (T, TQ None with totals=False)."""
+    _require_cuda(image, "image")
+    if image.dtype not in _PIXEL:
+        raise ValueError("image dtype must be uint8 or uint16")
+    H, W = image.shape
+    dev = image.device
+    S = sat if sat is not None else empty_table(H, W, dev)
+    Q = sat_sq if sat_sq is not None else (empty_table(H, W, dev, S.stride(0)) if squares else None)
+    _require_cuda(S, "sat")
+    if Q is not None:
+        _require_cuda(Q, "sat_sq")
+        if Q.stride(0) != S.stride(0):
+            raise ValueError("sat and sat_sq must share a row pitch")
+    T = total if total is not None else (empty_totals(W, dev) if totals else None)
+    TQ = total_sq if total_sq is not None else (empty_totals(W, dev) if totals and Q is not None else None)
+    ptype = _PIXEL[image.dtype]
+    need = build_workspace_bytes(H, W, ptype, Q is not None)
+    wsb = ws if ws is not None else workspace(need, dev, stream)
+    check(_lib.load().sat_build_band(image.data_ptr(), ptype, H, W, image.stride(0), _vector(carry, W, "carry"),
+                                     _vector(carry_sq, W, "carry_sq"), rows_above, S.data_ptr(),
+                                     Q.data_ptr() if Q is not None else None, S.stride(0), _vector(T, W, "total"),
+                                     _vector(TQ, W, "total_sq"), wsb.data_ptr(), wsb.numel(),
+                                     _stream_handle(dev, stream)))
+    return (S, Q, T, TQ) if Q is not None else (S, T)
+
+
 def out_shape(H: int, W: int, h: int, w: int, stride: int = 1) -> Tuple[int, int]:
     oh, ow = ctypes.c_int64(), ctypes.c_int64()
     check(_lib.load().window_out_shape(H, W, h, w, stride, ctypes.byref(oh), ctypes.byref(ow)))

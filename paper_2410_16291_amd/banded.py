@@ -17,6 +17,10 @@ collects them into host arrays.
 
 Cost over the whole-image path: the h_max - 1 overlap rows are built again for every band, and
 their outputs are discarded: about (h_max - 1) / band_rows extra table rows per band.
+
+`build_table_streamed` is the other use of bands: the whole image's table in HBM, built band by
+band as the image arrives.  There the bands do not overlap; each band's build starts from the
+column totals of the rows above it and leaves those through its own last row for the next band.
 """
 from __future__ import annotations
 
@@ -64,44 +68,27 @@ def band_outputs(r0: int, b0: int, b1: int, H: int, h: int, stride: int) -> Tupl
     return k0, max(k0, k1)
 
 
-class BandedWindowSums:
-    """Streams an H x W image through the device in bands and produces window sums.
+class _Uploader:
+    """Two device image buffers of rows_max x W and two pinned staging buffers: stage() puts image
+    rows [r0, r1) into buffer `slot` on the copy stream (host rows through a pinned buffer), after
+    the compute stream has released that buffer."""
 
-    read_rows(r0, r1) -> image rows [r0, r1) as a (r1-r0, W) numpy array, pinned host tensor or
-    device tensor.
-    on_rows(i, k0, rows) receives, for window i, the device tensor of its output rows [k0, k0+n).
-    """
-
-    def __init__(self, H: int, W: int, windows: Sequence[Tuple[int, int]], stride: int = 1,
-                 pixel_type: str = "u8", band_rows: int = 8192, device="cuda:0",
-                 out_dtype: Optional[torch.dtype] = None):
-        _check_windows(H, W, windows, stride)
-        self.H, self.W = H, W
-        self.windows = [(int(h), int(w)) for h, w in windows]
-        self.stride = stride
-        self.pixel_type = pixel_type
+    def __init__(self, rows_max: int, W: int, pixel_type: str, dev: torch.device):
+        self.W = W
         self.np_dtype = np.uint8 if pixel_type == "u8" else np.uint16
         self.t_dtype = torch.uint8 if pixel_type == "u8" else torch.uint16
-        self.dev = torch.device(device)
-        self.h_max = max(h for h, _ in self.windows)
-        self.band_rows = band_rows
-        self.plan = band_plan(H, self.h_max, stride, band_rows)
-        big = any(api.default_out_dtype(h, w, pixel_type) == torch.uint64 for h, w in self.windows)
-        self.out_dtype = out_dtype or (torch.uint64 if big else torch.uint32)
-        self.compute = torch.cuda.Stream(self.dev)
-        self.copy = torch.cuda.Stream(self.dev)
-        rows_max = max(b1 - r0 for r0, _, b1 in self.plan)
-        self.rows_max = rows_max
-        # two device image buffers and two pinned staging buffers (double buffering)
-        self.dimg = [torch.empty((rows_max, W), dtype=self.t_dtype, device=self.dev) for _ in range(2)]
+        self.copy = torch.cuda.Stream(dev)
+        self.dimg = [torch.empty((rows_max, W), dtype=self.t_dtype, device=dev) for _ in range(2)]
         self.pinned = [torch.empty((rows_max, W), dtype=torch.uint8 if self.np_dtype == np.uint8 else torch.int16,
                                    pin_memory=True) for _ in range(2)]
-        self.table = api.empty_table(rows_max, W, self.dev)
-        self.bpp = 1 if pixel_type == "u8" else 2
         self.uploaded = [torch.cuda.Event() for _ in range(2)]
         self.consumed = [torch.cuda.Event() for _ in range(2)]
 
-    def _stage(self, slot: int, r0: int, r1: int, read_rows: Callable) -> None:
+    def start(self, compute: torch.cuda.Stream) -> None:
+        for e in self.consumed:
+            e.record(compute)
+
+    def stage(self, slot: int, r0: int, r1: int, read_rows: Callable) -> None:
         rows = read_rows(r0, r1)
         n = r1 - r0
         if isinstance(rows, torch.Tensor) and (rows.is_cuda or rows.is_pinned()):
@@ -129,23 +116,59 @@ class BandedWindowSums:
             dst.view(host.dtype).copy_(host, non_blocking=True)
             self.uploaded[slot].record(self.copy)
 
+    def acquire(self, compute: torch.cuda.Stream, slot: int, n: int) -> torch.Tensor:
+        compute.wait_event(self.uploaded[slot])
+        return self.dimg[slot][:n]
+
+    def release(self, compute: torch.cuda.Stream, slot: int) -> None:
+        self.consumed[slot].record(compute)
+
+
+class BandedWindowSums:
+    """Streams an H x W image through the device in bands and produces window sums.
+
+    read_rows(r0, r1) -> image rows [r0, r1) as a (r1-r0, W) numpy array, pinned host tensor or
+    device tensor.
+    on_rows(i, k0, rows) receives, for window i, the device tensor of its output rows [k0, k0+n).
+    """
+
+    def __init__(self, H: int, W: int, windows: Sequence[Tuple[int, int]], stride: int = 1,
+                 pixel_type: str = "u8", band_rows: int = 8192, device="cuda:0",
+                 out_dtype: Optional[torch.dtype] = None):
+        _check_windows(H, W, windows, stride)
+        self.H, self.W = H, W
+        self.windows = [(int(h), int(w)) for h, w in windows]
+        self.stride = stride
+        self.pixel_type = pixel_type
+        self.dev = torch.device(device)
+        self.h_max = max(h for h, _ in self.windows)
+        self.band_rows = band_rows
+        self.plan = band_plan(H, self.h_max, stride, band_rows)
+        big = any(api.default_out_dtype(h, w, pixel_type) == torch.uint64 for h, w in self.windows)
+        self.out_dtype = out_dtype or (torch.uint64 if big else torch.uint32)
+        self.compute = torch.cuda.Stream(self.dev)
+        rows_max = max(b1 - r0 for r0, _, b1 in self.plan)
+        self.rows_max = rows_max
+        self.up = _Uploader(rows_max, W, pixel_type, self.dev)      # double-buffered image bands
+        self.dimg = self.up.dimg
+        self.table = api.empty_table(rows_max, W, self.dev)
+        self.bpp = 1 if pixel_type == "u8" else 2
+
     def run(self, read_rows: Callable, on_rows: Callable) -> None:
         plan = self.plan
-        for e in self.consumed:
-            e.record(self.compute)
-        self._stage(0, plan[0][0], plan[0][2], read_rows)
+        self.up.start(self.compute)
+        self.up.stage(0, plan[0][0], plan[0][2], read_rows)
         for bi, (r0, b0, b1) in enumerate(plan):
             slot = bi & 1
             if bi + 1 < len(plan):
                 nr0, _, nb1 = plan[bi + 1]
-                self._stage(slot ^ 1, nr0, nb1, read_rows)
+                self.up.stage(slot ^ 1, nr0, nb1, read_rows)
             n = b1 - r0
-            self.compute.wait_event(self.uploaded[slot])
-            img = self.dimg[slot][:n]
+            img = self.up.acquire(self.compute, slot, n)
             S = self.table[:n]
             ws = api.workspace(api.build_workspace_bytes(n, self.W, self.bpp, False), self.dev, self.compute)
             api.sat_build(img, sat=S, ws=ws, stream=self.compute)
-            self.consumed[slot].record(self.compute)
+            self.up.release(self.compute, slot)
             # every window with output rows in this band, in one pass over the band's table
             todo = []
             for i, (h, w) in enumerate(self.windows):
@@ -184,3 +207,44 @@ def banded_window_sums(read_rows: Callable, H: int, W: int, windows: Sequence[Tu
         a = t.numpy()
         host[i][k0:k0 + a.shape[0]] = a.view(host[i].dtype)
     return host
+
+
+def build_table_streamed(read_rows: Callable, H: int, W: int, pixel_type: str = "u8", squares: bool = False,
+                         band_rows: int = 8192, device="cuda:0", sat: Optional[torch.Tensor] = None,
+                         sat_sq: Optional[torch.Tensor] = None):
+    """The integral image of the whole H x W image (and of its squares) in HBM, from image rows
+    that arrive band by band (read_rows as for BandedWindowSums).  Each band's table rows are
+    built from the band and the column totals of the rows above it (sat_build_band), which the
+    band's build advances in place for the next band; bands are uploaded on a copy stream while
+    the previous band builds.  The device holds the table, two image bands and the W-word totals.
+    Returns S, or (S, Q)."""
+    if H < 1 or W < 1 or band_rows < 1:
+        raise ValueError("H, W and band_rows must be >= 1")
+    dev = torch.device(device)
+    S = sat if sat is not None else api.empty_table(H, W, dev)
+    Q = sat_sq if sat_sq is not None else (api.empty_table(H, W, dev, S.stride(0)) if squares else None)
+    bpp = 1 if pixel_type == "u8" else 2
+    bands = [(b0, min(H, b0 + band_rows)) for b0 in range(0, H, band_rows)]
+    rows_max = max(b1 - b0 for b0, b1 in bands)
+    compute = torch.cuda.Stream(dev)
+    up = _Uploader(rows_max, W, pixel_type, dev)
+    carry = api.empty_totals(W, dev)
+    carry_sq = api.empty_totals(W, dev) if Q is not None else None
+    # the build variant (and so the workspace it needs) depends on the band height
+    need = max(api.build_workspace_bytes(n, W, bpp, Q is not None) for n in {b1 - b0 for b0, b1 in bands})
+    ws = api.workspace(need, dev, compute)
+    up.start(compute)
+    up.stage(0, bands[0][0], bands[0][1], read_rows)
+    for bi, (b0, b1) in enumerate(bands):
+        slot = bi & 1
+        if bi + 1 < len(bands):
+            up.stage(slot ^ 1, bands[bi + 1][0], bands[bi + 1][1], read_rows)
+        img = up.acquire(compute, slot, b1 - b0)
+        first = bi == 0
+        api.sat_build_band(img, carry=None if first else carry, rows_above=b0, squares=Q is not None,
+                           carry_sq=None if first or Q is None else carry_sq, sat=S[b0:b1],
+                           sat_sq=Q[b0:b1] if Q is not None else None, total=carry, total_sq=carry_sq, ws=ws,
+                           stream=compute)
+        up.release(compute, slot)
+    compute.synchronize()
+    return (S, Q) if Q is not None else S

@@ -315,6 +315,76 @@ satk::GatherDesc gather_desc(const uint64_t *sat, const uint64_t *sat_sq, int64_
 }
 
 
+// sat_build and sat_build_band: one image, optionally seeded with the column totals of the rows
+// above it (carry, rows_above) and emitting its own column totals through its last row (total).
+sat_status build_one(const void *image, sat_dtype pixel_type, int64_t H, int64_t W, int64_t image_pitch,
+                     const uint64_t *carry, const uint64_t *carry_sq, int64_t rows_above, uint64_t *sat,
+                     uint64_t *sat_sq, int64_t sat_pitch, uint64_t *total, uint64_t *total_sq, void *workspace,
+                     size_t workspace_bytes, void *stream, const char *who) {
+    sat_status st = validate_build_item(image, pixel_type, H, W, image_pitch, sat, sat_sq, sat_pitch, who);
+    if (st) return st;
+    const bool sq = sat_sq != nullptr;
+    const int bpp = bytes_of(pixel_type);
+    if (rows_above < 0 || rows_above > kMaxDim)
+        return fail(SAT_ERR_ARG, "%s: rows_above %lld out of range", who, (long long)rows_above);
+    if (rows_above > 0 && !carry) return fail(SAT_ERR_ARG, "%s: rows_above > 0 needs a carry", who);
+    if (carry && sq && !carry_sq) return fail(SAT_ERR_ARG, "%s: a carry with sat_sq needs carry_sq", who);
+    if (carry_sq && (!carry || !sq)) return fail(SAT_ERR_ARG, "%s: carry_sq needs carry and sat_sq", who);
+    if (total_sq && !sq) return fail(SAT_ERR_ARG, "%s: total_sq_out needs sat_sq", who);
+    {
+        // every column total of the band, carry included, must stay below 2^62
+        const unsigned __int128 m = max_pixel(pixel_type);
+        const unsigned __int128 col = static_cast<unsigned __int128>(rows_above + H) * (sq ? m * m : m);
+        if (col >= (static_cast<unsigned __int128>(1) << 62))
+            return fail(SAT_ERR_OVERFLOW, "%s: %lld rows above and %lld rows are too many for exact 62-bit column "
+                        "totals", who, (long long)rows_above, (long long)H);
+    }
+    const Span si = span(image, H, image_pitch, W, bpp), ss = span(sat, H, sat_pitch, W, 8),
+               sqs = span(sat_sq, H, sat_pitch, W, 8);
+    const Span sc = span(carry, 1, W, W, 8), scq = span(carry_sq, 1, W, W, 8);
+    const Span st_ = span(total, 1, W, W, 8), stq = span(total_sq, 1, W, W, 8);
+    for (const Span *o : {&st_, &stq})
+        if (overlap(*o, si) || overlap(*o, ss) || overlap(*o, sqs))
+            return fail(SAT_ERR_ARG, "%s: a total output overlaps the image or a table", who);
+    if (overlap(st_, stq)) return fail(SAT_ERR_ARG, "%s: total_out and total_sq_out overlap", who);
+    for (const Span *c : {&sc, &scq})
+        if (overlap(*c, ss) || overlap(*c, sqs)) return fail(SAT_ERR_ARG, "%s: a carry overlaps a table", who);
+    // a carry is either its own total output (in place) or apart from both totals
+    if ((carry != total && (overlap(sc, st_) || overlap(sc, stq))) ||
+        (carry_sq != total_sq && (overlap(scq, st_) || overlap(scq, stq))))
+        return fail(SAT_ERR_ARG, "%s: a carry must equal its total output or overlap no total", who);
+    if (reinterpret_cast<uintptr_t>(carry) % 8 || reinterpret_cast<uintptr_t>(carry_sq) % 8 ||
+        reinterpret_cast<uintptr_t>(total) % 8 || reinterpret_cast<uintptr_t>(total_sq) % 8)
+        return fail(SAT_ERR_ARG, "%s: carries and totals must be 8-byte aligned", who);
+    const size_t need = sat_build_workspace_bytes(H, W, pixel_type, sq);
+    if (!workspace || workspace_bytes < need)
+        return fail(SAT_ERR_WORKSPACE, "%s: workspace of %zu bytes is below the %zu needed", who, workspace_bytes,
+                    need);
+    if (reinterpret_cast<uintptr_t>(workspace) % 16)
+        return fail(SAT_ERR_ARG, "%s: workspace must be 16-byte aligned", who);
+    const Span sw{reinterpret_cast<uintptr_t>(workspace), reinterpret_cast<uintptr_t>(workspace) + workspace_bytes};
+    for (const Span *o : {&si, &ss, &sqs, &sc, &scq, &st_, &stq})
+        if (overlap(sw, *o)) return fail(SAT_ERR_ARG, "%s: workspace overlaps an input or output", who);
+    const int v = choose_build_variant(H, 1, bpp, sq, row_align(image, image_pitch, bpp));
+    if ((st = check_build_variant(v, bpp, sq, who))) return st;
+    const satk::BuildVariant &var = satk::build_variant(v);
+    satk::BuildDesc d{};
+    const int strip_h = choose_strip_h(v, H, bpp, sq);
+    fill_desc(d, var, image, bpp, H, W, image_pitch, sat, sat_sq, sat_pitch, strip_h);
+    d.state_off = 0;
+    d.state_q_off = static_cast<int64_t>(d.nstrips) * d.Wp;
+    d.first_item = 0;
+    d.carry = carry;
+    d.carry_q = carry_sq;
+    d.total = total;
+    d.total_q = total_sq;
+    const int64_t words = state_words_for(var, H, W, sq, strip_h);
+    hipError_t e = satk::launch_build(v, bpp, sq, &d, 1, nullptr, d.nstrips, workspace, words,
+                                      static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, who);
+    return ok();
+}
+
 }  // namespace
 
 extern "C" {
@@ -344,32 +414,47 @@ size_t sat_build_workspace_bytes(int64_t H, int64_t W, sat_dtype pixel_type, int
 sat_status sat_build(const void *image, sat_dtype pixel_type, int64_t H, int64_t W, int64_t image_pitch,
                      uint64_t *sat, uint64_t *sat_sq, int64_t sat_pitch, void *workspace, size_t workspace_bytes,
                      void *stream) {
-    const char *who = "sat_build";
-    sat_status st = validate_build_item(image, pixel_type, H, W, image_pitch, sat, sat_sq, sat_pitch, who);
+    return build_one(image, pixel_type, H, W, image_pitch, nullptr, nullptr, 0, sat, sat_sq, sat_pitch, nullptr,
+                     nullptr, workspace, workspace_bytes, stream, "sat_build");
+}
+
+sat_status sat_build_band(const void *image, sat_dtype pixel_type, int64_t H, int64_t W, int64_t image_pitch,
+                          const uint64_t *carry, const uint64_t *carry_sq, int64_t rows_above, uint64_t *sat,
+                          uint64_t *sat_sq, int64_t sat_pitch, uint64_t *total_out, uint64_t *total_sq_out,
+                          void *workspace, size_t workspace_bytes, void *stream) {
+    return build_one(image, pixel_type, H, W, image_pitch, carry, carry_sq, rows_above, sat, sat_sq, sat_pitch,
+                     total_out, total_sq_out, workspace, workspace_bytes, stream, "sat_build_band");
+}
+
+sat_status sat_column_totals(const void *image, sat_dtype pixel_type, int64_t H, int64_t W, int64_t image_pitch,
+                             const uint64_t *carry, const uint64_t *carry_sq, uint64_t *out, uint64_t *out_sq,
+                             void *stream) {
+    const char *who = "sat_column_totals";
+    if (!image || !out) return fail(SAT_ERR_ARG, "%s: image and out must be non-NULL", who);
+    if (pixel_type != SAT_U8 && pixel_type != SAT_U16)
+        return fail(SAT_ERR_ARG, "%s: pixel_type must be SAT_U8 or SAT_U16", who);
+    sat_status st = check_dims(H, W, who);
     if (st) return st;
-    const size_t need = sat_build_workspace_bytes(H, W, pixel_type, sat_sq != nullptr);
-    if (!workspace || workspace_bytes < need)
-        return fail(SAT_ERR_WORKSPACE, "%s: workspace of %zu bytes is below the %zu needed", who, workspace_bytes,
-                    need);
-    if (reinterpret_cast<uintptr_t>(workspace) % 16)
-        return fail(SAT_ERR_ARG, "%s: workspace must be 16-byte aligned", who);
-    const Span sw{reinterpret_cast<uintptr_t>(workspace), reinterpret_cast<uintptr_t>(workspace) + workspace_bytes};
     const int bpp = bytes_of(pixel_type);
-    if (overlap(sw, span(image, H, image_pitch, W, bpp)) || overlap(sw, span(sat, H, sat_pitch, W, 8)) ||
-        overlap(sw, span(sat_sq, H, sat_pitch, W, 8)))
-        return fail(SAT_ERR_ARG, "%s: workspace overlaps an input or output", who);
-    const int v = choose_build_variant(H, 1, bpp, sat_sq != nullptr, row_align(image, image_pitch, bpp));
-    if ((st = check_build_variant(v, bpp, sat_sq != nullptr, who))) return st;
-    const satk::BuildVariant &var = satk::build_variant(v);
-    satk::BuildDesc d{};
-    const int strip_h = choose_strip_h(v, H, bpp, sat_sq != nullptr);
-    fill_desc(d, var, image, bpp, H, W, image_pitch, sat, sat_sq, sat_pitch, strip_h);
-    d.state_off = 0;
-    d.state_q_off = static_cast<int64_t>(d.nstrips) * d.Wp;
-    d.first_item = 0;
-    const int64_t words = state_words_for(var, H, W, sat_sq != nullptr, strip_h);
-    hipError_t e = satk::launch_build(v, bpp, sat_sq != nullptr, &d, 1, nullptr, d.nstrips, workspace, words,
-                                      static_cast<hipStream_t>(stream));
+    if ((st = check_pitch(image_pitch, W, H, bpp, who, "image"))) return st;
+    if (carry_sq && !out_sq) return fail(SAT_ERR_ARG, "%s: carry_sq needs out_sq", who);
+    if (out_sq && carry && !carry_sq)
+        return fail(SAT_ERR_ARG, "%s: with a carry and out_sq, carry_sq must be non-NULL", who);
+    const Span si = span(image, H, image_pitch, W, bpp);
+    const Span so = span(out, 1, W, W, 8), soq = span(out_sq, 1, W, W, 8);
+    const Span sc = span(carry, 1, W, W, 8), scq = span(carry_sq, 1, W, W, 8);
+    if (overlap(si, so) || overlap(si, soq) || overlap(so, soq))
+        return fail(SAT_ERR_ARG, "%s: image, out and out_sq must not overlap", who);
+    // a carry is either the output itself (in place) or apart from both outputs
+    if ((carry != out && (overlap(sc, so) || overlap(sc, soq))) ||
+        (carry_sq != out_sq && (overlap(scq, so) || overlap(scq, soq))))
+        return fail(SAT_ERR_ARG, "%s: a carry must equal its output or overlap no output", who);
+    if (reinterpret_cast<uintptr_t>(out) % 8 || reinterpret_cast<uintptr_t>(out_sq) % 8 ||
+        reinterpret_cast<uintptr_t>(carry) % 8 || reinterpret_cast<uintptr_t>(carry_sq) % 8)
+        return fail(SAT_ERR_ARG, "%s: totals and carries must be 8-byte aligned", who);
+    const int vec16 = row_align(image, image_pitch, bpp) == 16 ? 1 : 0;
+    hipError_t e = satk::launch_column_totals(bpp, image, H, W, image_pitch, vec16, carry, carry_sq, out, out_sq,
+                                              static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, who);
     return ok();
 }
@@ -781,7 +866,10 @@ sat_status sat_workspace_check(void *workspace, void *stream) {
     satk::BuildCtrl ctrl;
     e = hipMemcpy(&ctrl, workspace, sizeof ctrl, hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "sat_workspace_check");
-    if (ctrl.fault) return fail(SAT_ERR_DEVICE, "sat_workspace_check: a lookback wait exceeded its spin bound");
+    if (ctrl.fault & 1u) return fail(SAT_ERR_DEVICE, "sat_workspace_check: a lookback wait exceeded its spin bound");
+    if (ctrl.fault & 2u)
+        return fail(SAT_ERR_DEVICE, "sat_workspace_check: a carried column total leaves no room below 2^62 for "
+                    "the band (a carry above its rows_above bound)");
     return ok();
 }
 

@@ -288,6 +288,46 @@ struct Build {
     // order (soff) would touch every line half.
     static __device__ __forceinline__ int lslot(int p) { return p * 64; }
 
+    // Strip 0 of a band build: the column totals above the strip are the carried totals of the
+    // rows above the image (zero without a carry).  Every lookback value of the band is then a
+    // carry plus at most H maximal pixels, which must stay below 2^62: a carry above
+    // 2^62 - 1 - H * max_pixel (the host has checked that H * max_pixel < 2^62) sets fault bit 1.
+    static __device__ __forceinline__ void seed(const BuildDesc &d, int64_t xb, int lane, uint64_t (&v)[PX],
+                                                uint64_t (&vq)[PX], unsigned int *fault) {
+        if (!d.carry) return;
+        constexpr uint64_t kMaxPix = sizeof(T) == 1 ? 255u : 65535u;
+        const uint64_t room = kValueMask - static_cast<uint64_t>(d.H) * kMaxPix;
+        const uint64_t room_q = kValueMask - static_cast<uint64_t>(d.H) * kMaxPix * kMaxPix;
+        bool big = false;
+#pragma unroll
+        for (int p = 0; p < PX; ++p) {
+            const int64_t x = xb + col(lane, p);
+            v[p] = x < d.W ? d.carry[x] : 0;
+            big = big || v[p] > room;
+            if (SQ) {
+                vq[p] = x < d.W ? d.carry_q[x] : 0;
+                big = big || vq[p] > room_q;
+            }
+        }
+        if (big) atomicOr(fault, 2u);
+    }
+
+    // The last strip's inclusive totals (totals above + its own) are the column totals through
+    // the image's last row: the carry of the next band.
+    static __device__ __forceinline__ void emit_total(const BuildDesc &d, int strip, int64_t xb, int lane,
+                                                      const uint64_t (&v)[PX], const uint64_t (&a)[PX],
+                                                      const uint64_t (&vq)[PX], const uint64_t (&aq)[PX]) {
+        if (strip != d.nstrips - 1) return;
+#pragma unroll
+        for (int p = 0; p < PX; ++p) {
+            const int64_t x = xb + col(lane, p);
+            if (x < d.W) {
+                if (d.total) d.total[x] = v[p] + a[p];
+                if (SQ && d.total_q) d.total_q[x] = vq[p] + aq[p];
+            }
+        }
+    }
+
     static __device__ void lookback(const BuildDesc &d, int strip, int64_t xb, int lane,
                                     const uint64_t (&a)[PX], const uint64_t (&aq)[PX],
                                     uint64_t (&v)[PX], uint64_t (&vq)[PX], uint64_t *state,
@@ -297,11 +337,13 @@ struct Build {
 #pragma unroll
         for (int p = 0; p < PX; ++p) { v[p] = 0; vq[p] = 0; }
         if (strip == 0) {
+            seed(d, xb, lane, v, vq, fault);
 #pragma unroll
             for (int p = 0; p < PX; ++p) {
-                store_state(mine + lslot(p), kStPrefix | a[p]);
-                if (SQ) store_state(mine_q + lslot(p), kStPrefix | aq[p]);
+                store_state(mine + lslot(p), kStPrefix | (v[p] + a[p]));
+                if (SQ) store_state(mine_q + lslot(p), kStPrefix | (vq[p] + aq[p]));
             }
+            emit_total(d, strip, xb, lane, v, a, vq, aq);
             return;
         }
 #pragma unroll
@@ -358,6 +400,7 @@ struct Build {
             store_state(mine + lslot(p), kStPrefix | (v[p] + a[p]));
             if (SQ) store_state(mine_q + lslot(p), kStPrefix | (vq[p] + aq[p]));
         }
+        emit_total(d, strip, xb, lane, v, a, vq, aq);
     }
 
     // Decoupled lookback that reads the states of WIN strips per round trip (j, j-1, ...,
@@ -376,11 +419,13 @@ struct Build {
 #pragma unroll
         for (int p = 0; p < PX; ++p) { v[p] = 0; vq[p] = 0; }
         if (strip == 0) {
+            seed(d, xb, lane, v, vq, fault);
 #pragma unroll
             for (int p = 0; p < PX; ++p) {
-                store_state(mine + lslot(p), kStPrefix | a[p]);
-                if (SQ) store_state(mine_q + lslot(p), kStPrefix | aq[p]);
+                store_state(mine + lslot(p), kStPrefix | (v[p] + a[p]));
+                if (SQ) store_state(mine_q + lslot(p), kStPrefix | (vq[p] + aq[p]));
             }
+            emit_total(d, strip, xb, lane, v, a, vq, aq);
             return;
         }
 #pragma unroll
@@ -451,6 +496,7 @@ struct Build {
             store_state(mine + lslot(p), kStPrefix | (v[p] + a[p]));
             if (SQ) store_state(mine_q + lslot(p), kStPrefix | (vq[p] + aq[p]));
         }
+        emit_total(d, strip, xb, lane, v, a, vq, aq);
     }
 
     // One table's rows of the block for this wave; returns the row totals (lane r holds row r's)
@@ -1395,18 +1441,118 @@ __global__ __launch_bounds__(256) void colsum_kernel(BuildDesc d, uint64_t *stat
     }
 }
 
-// Reduce-then-scan ablation, phase 2: exclusive scan of the strip totals down each column.
+// Reduce-then-scan ablation, phase 2: exclusive scan of the strip totals down each column,
+// starting from the carried column totals of a band build (zero without them); the inclusive
+// end of the scan is the band's total output.
 __global__ __launch_bounds__(256) void colscan_kernel(uint64_t *state, long long off, long long Wp,
-                                                      int nstrips) {
+                                                      int nstrips, const uint64_t *carry, uint64_t *total,
+                                                      long long W) {
     const long long x = static_cast<long long>(blockIdx.x) * 256 + threadIdx.x;
     if (x >= Wp) return;
-    uint64_t run = 0;
+    uint64_t run = (carry && x < W) ? carry[x] : 0;
     for (int i = 0; i < nstrips; ++i) {
         uint64_t *p = state + off + static_cast<long long>(i) * Wp + x;
         const uint64_t t = *p;
         *p = run;
         run += t;
     }
+    if (total && x < W) total[x] = run;
+}
+
+// ------------------------------------------------------------------ column totals
+
+// out[x] = carry[x] (zero without a carry); the squared output likewise.  A fill kernel, not a
+// memset, so that a captured graph replays it correctly.
+__global__ __launch_bounds__(256) void totals_init_kernel(const uint64_t *carry, const uint64_t *carry_q,
+                                                          uint64_t *out, uint64_t *out_q, long long W) {
+    const long long x = static_cast<long long>(blockIdx.x) * 256 + threadIdx.x;
+    if (x >= W) return;
+    out[x] = carry ? carry[x] : 0;
+    if (out_q) out_q[x] = carry_q ? carry_q[x] : 0;
+}
+
+// Column totals of an image added to out (and of its squares to out_q): the prepass a strip of
+// rows needs before its band build when the strips above are built elsewhere.  A workgroup is one
+// wave over a tile of kTotRowBytes-byte columns and rows_per rows (<= 65536, so that a lane's
+// 32-bit sums of pixels, of 8-bit squares, are exact); each lane sums its columns down the rows
+// in registers and adds them to out with 64-bit atomics.  Tiles wholly inside the image with
+// 16-byte aligned rows give each lane 16 contiguous bytes (one 16-byte load per row); other
+// tiles give lane l the columns l, l + 64, ... (one coalesced element load per column group).
+constexpr int kTotRowBytes = 1024;
+
+template <typename T, bool SQ>
+__global__ __launch_bounds__(64) void column_totals_kernel(const T *__restrict__ img, long long H, long long W,
+                                                           long long pitch, long long rows_per, long long ncol,
+                                                           int vec16, uint64_t *out, uint64_t *out_q) {
+    constexpr int VEC = 16 / static_cast<int>(sizeof(T));   // columns per lane
+    constexpr int CW = kTotRowBytes / static_cast<int>(sizeof(T));   // columns per tile
+    using QT = typename std::conditional<sizeof(T) == 1, uint32_t, uint64_t>::type;
+    const long long cb = static_cast<long long>(blockIdx.x) % ncol, rb = static_cast<long long>(blockIdx.x) / ncol;
+    const long long y0 = rb * rows_per;
+    const long long y1 = y0 + rows_per < H ? y0 + rows_per : H;
+    const long long xw = cb * CW;
+    const int lane = static_cast<int>(threadIdx.x);
+    uint32_t sum[VEC];
+    QT sq[VEC];
+#pragma unroll
+    for (int k = 0; k < VEC; ++k) { sum[k] = 0; sq[k] = 0; }
+    const bool fast = vec16 && xw + CW <= W;   // uniform over the workgroup
+    if (fast) {
+        const T *p = img + y0 * pitch + xw + lane * VEC;
+#pragma unroll 4
+        for (long long y = y0; y < y1; ++y, p += pitch) {
+            const u32x4 t = *reinterpret_cast<const u32x4 *>(p);
+            const uint32_t wd[4] = {t.x, t.y, t.z, t.w};
+#pragma unroll
+            for (int k = 0; k < VEC; ++k) {
+                const uint32_t v = sizeof(T) == 1 ? (wd[k >> 2] >> (8 * (k & 3))) & 0xffu
+                                                  : (wd[k >> 1] >> (16 * (k & 1))) & 0xffffu;
+                sum[k] += v;
+                if (SQ) sq[k] += static_cast<QT>(v) * v;
+            }
+        }
+    } else {
+        for (long long y = y0; y < y1; ++y) {
+            const T *row = img + y * pitch + xw + lane;
+#pragma unroll
+            for (int k = 0; k < VEC; ++k) {
+                const uint32_t v = xw + lane + 64 * k < W ? static_cast<uint32_t>(row[64 * k]) : 0u;
+                sum[k] += v;
+                if (SQ) sq[k] += static_cast<QT>(v) * v;
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < VEC; ++k) {
+        const long long x = fast ? xw + lane * VEC + k : xw + lane + 64 * k;
+        if (x < W) {
+            atomicAdd(reinterpret_cast<unsigned long long *>(out + x), static_cast<unsigned long long>(sum[k]));
+            if (SQ) atomicAdd(reinterpret_cast<unsigned long long *>(out_q + x), static_cast<unsigned long long>(sq[k]));
+        }
+    }
+}
+
+template <typename T, bool SQ>
+hipError_t launch_totals_typed(const void *img, int64_t H, int64_t W, int64_t pitch, int vec16,
+                               const uint64_t *carry, const uint64_t *carry_q, uint64_t *out, uint64_t *out_q,
+                               hipStream_t stream) {
+    hipLaunchKernelGGL(totals_init_kernel, dim3(static_cast<unsigned>((W + 255) / 256)), dim3(256), 0, stream, carry,
+                       carry_q, out, out_q, static_cast<long long>(W));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    constexpr int CW = kTotRowBytes / static_cast<int>(sizeof(T));
+    const int64_t ncol = (W + CW - 1) / CW;
+    // About 4096 workgroups (16 per compute unit): rows per tile from that, at least 16 and at
+    // most 65536 (exact 32-bit lane sums).
+    int64_t rows_per = (H * ncol + 4095) / 4096;
+    if (rows_per < 16) rows_per = 16;
+    if (rows_per > 65536) rows_per = 65536;
+    const int64_t nrow = (H + rows_per - 1) / rows_per;
+    hipLaunchKernelGGL((column_totals_kernel<T, SQ>), dim3(static_cast<unsigned>(ncol * nrow)), dim3(64), 0, stream,
+                       static_cast<const T *>(img), static_cast<long long>(H), static_cast<long long>(W),
+                       static_cast<long long>(pitch), static_cast<long long>(rows_per), static_cast<long long>(ncol),
+                       vec16, out, out_q);
+    return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ variants and launch
@@ -1502,11 +1648,12 @@ hipError_t launch_typed(const BuildDesc *descs, int n, const BuildDesc *dev_desc
                                    dim3(256), 0, stream, d, state);
                 const unsigned cb = static_cast<unsigned>((d.Wp + 255) / 256);
                 hipLaunchKernelGGL(colscan_kernel, dim3(cb), dim3(256), 0, stream, state,
-                                   static_cast<long long>(d.state_off), static_cast<long long>(d.Wp), d.nstrips);
+                                   static_cast<long long>(d.state_off), static_cast<long long>(d.Wp), d.nstrips,
+                                   d.carry, d.total, static_cast<long long>(d.W));
                 if (SQ)
                     hipLaunchKernelGGL(colscan_kernel, dim3(cb), dim3(256), 0, stream, state,
                                        static_cast<long long>(d.state_q_off), static_cast<long long>(d.Wp),
-                                       d.nstrips);
+                                       d.nstrips, d.carry_q, d.total_q, static_cast<long long>(d.W));
             }
         }
         hipError_t e = hipGetLastError();
@@ -1618,6 +1765,16 @@ hipError_t launch_build_powers(int bpp, int np, const BuildDesc &d, void *worksp
         }
     }
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_column_totals(int bpp, const void *img, int64_t H, int64_t W, int64_t pitch, int vec16,
+                                const uint64_t *carry, const uint64_t *carry_q, uint64_t *out, uint64_t *out_q,
+                                hipStream_t stream) {
+    if (bpp == 1)
+        return out_q ? launch_totals_typed<uint8_t, true>(img, H, W, pitch, vec16, carry, carry_q, out, out_q, stream)
+                     : launch_totals_typed<uint8_t, false>(img, H, W, pitch, vec16, carry, carry_q, out, out_q, stream);
+    return out_q ? launch_totals_typed<uint16_t, true>(img, H, W, pitch, vec16, carry, carry_q, out, out_q, stream)
+                 : launch_totals_typed<uint16_t, false>(img, H, W, pitch, vec16, carry, carry_q, out, out_q, stream);
 }
 
 int build_variant_count() { return kNumVariants; }

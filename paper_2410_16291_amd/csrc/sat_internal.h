@@ -16,6 +16,10 @@ struct BuildDesc {
     uint64_t *S;          // table of pixels
     uint64_t *Q;          // table of squared pixels, or nullptr
     uint64_t *T3, *T4;    // power builds: tables of pixel^3 and pixel^4, or nullptr
+    const uint64_t *carry, *carry_q;   // band builds: column totals of the rows above the image
+                                       // (W words each), or nullptr (no rows above)
+    uint64_t *total, *total_q;         // band builds: column totals through the image's last row
+                                       // including the carry (W words each), or nullptr
     int64_t H, W, ipitch, spitch;
     int64_t Wp;           // state row length: nblocks * block width
     int64_t state_off;    // first lookback word of this image in the state array (S part)
@@ -32,7 +36,8 @@ struct BuildDesc {
 // Workspace layout: 256-byte control header, then the lookback state.
 struct BuildCtrl {
     unsigned long long ticket;   // next work item
-    unsigned int fault;          // nonzero: a lookback wait hit its spin bound
+    unsigned int fault;          // bit 0: a lookback wait hit its spin bound; bit 1: a carried
+                                 // column total reached 2^62 (band builds)
     unsigned int pad0;
     BuildDesc one;               // descriptor of a single-image build (written by the clear kernel)
     unsigned char pad[256 - 16 - sizeof(BuildDesc)];
@@ -72,6 +77,13 @@ constexpr int kPowStripH = 64;    // its largest strip height
 int power_build_capacity(int bpp, int np);
 hipError_t launch_build_powers(int bpp, int np, const BuildDesc &d, void *workspace, int64_t state_words,
                                hipStream_t stream);
+
+// out = carry + column totals of an H x W image (pixels of bpp bytes, pitch in elements), and
+// out_q = carry_q + totals of its squares when out_q is non-null.  carry / carry_q may be null
+// (zero) or equal to out / out_q.  vec16: the image's rows start 16-byte aligned.
+hipError_t launch_column_totals(int bpp, const void *img, int64_t H, int64_t W, int64_t pitch, int vec16,
+                                const uint64_t *carry, const uint64_t *carry_q, uint64_t *out, uint64_t *out_q,
+                                hipStream_t stream);
 
 // ---------------------------------------------------------------- window gathers
 

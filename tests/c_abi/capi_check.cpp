@@ -9,7 +9,11 @@
 // of 7 x 5 windows at stride 2 (window_sum, uint32), the fused sums of 3 x 3 and 9 x 9 windows at
 // stride 1 (window_sum_multi, uint32), and the mean and std of 4 x 6 windows at stride 3
 // (window_mean_std), and writes, in order: the two tables (H x W uint64 each), the window sums,
-// the two fused outputs, the sums, means and standard deviations, all dense.
+// the two fused outputs, the sums, means and standard deviations, all dense.  Then it builds the
+// table again in two bands of rows, [0, H/2) and [H/2, H) (sat_build_band): the lower band's carry
+// comes from sat_column_totals of the upper rows and is advanced in place by the lower band's
+// build.  It appends the table so assembled (H x W), the upper band's own totals output, the
+// column totals of the upper rows and the final totals (W uint64 each).
 #include <hip/hip_runtime_api.h>
 
 #include <cstdint>
@@ -109,13 +113,45 @@ int main(int argc, char **argv) {
     if ((e = hipMemcpy(mean.data(), d_mean, mean.size() * 8, hipMemcpyDeviceToHost))) return hip_die("copy mean", e);
     if ((e = hipMemcpy(stdv.data(), d_std, stdv.size() * 8, hipMemcpyDeviceToHost))) return hip_die("copy std", e);
 
+    // the same table in two bands
+    const int64_t h1 = H / 2;
+    uint64_t *d_B = nullptr, *d_top = nullptr, *d_carry = nullptr;
+    if ((e = hipMalloc(reinterpret_cast<void **>(&d_B), H * sp * 8))) return hip_die("hipMalloc band table", e);
+    if ((e = hipMalloc(reinterpret_cast<void **>(&d_top), W * 8))) return hip_die("hipMalloc totals", e);
+    if ((e = hipMalloc(reinterpret_cast<void **>(&d_carry), W * 8))) return hip_die("hipMalloc carry", e);
+    const uint8_t *d_lower = static_cast<const uint8_t *>(d_img) + h1 * ip;
+    size_t bwsb = sat_build_workspace_bytes(h1, W, SAT_U8, 0);
+    const size_t lower_wsb = sat_build_workspace_bytes(H - h1, W, SAT_U8, 0);
+    if (bwsb == 0 || lower_wsb == 0) return die("sat_build_workspace_bytes");
+    if (lower_wsb > bwsb) bwsb = lower_wsb;
+    void *d_bws = nullptr;
+    if ((e = hipMalloc(&d_bws, bwsb))) return hip_die("hipMalloc band workspace", e);
+    if (sat_build_band(d_img, SAT_U8, h1, W, ip, nullptr, nullptr, 0, d_B, nullptr, sp, d_top, nullptr, d_bws, bwsb,
+                       nullptr))
+        return die("sat_build_band (upper)");
+    if (sat_column_totals(d_img, SAT_U8, h1, W, ip, nullptr, nullptr, d_carry, nullptr, nullptr))
+        return die("sat_column_totals");
+    if (sat_build_band(d_lower, SAT_U8, H - h1, W, ip, d_carry, nullptr, h1, d_B + h1 * sp, nullptr, sp, d_carry,
+                       nullptr, d_bws, bwsb, nullptr))
+        return die("sat_build_band (lower)");
+    if (sat_workspace_check(d_bws, nullptr)) return die("sat_workspace_check");
+    std::vector<uint64_t> B(H * sp), top(W), upper(W), fin(W);
+    if ((e = hipMemcpy(B.data(), d_B, B.size() * 8, hipMemcpyDeviceToHost))) return hip_die("copy band table", e);
+    if ((e = hipMemcpy(top.data(), d_top, W * 8, hipMemcpyDeviceToHost))) return hip_die("copy totals", e);
+    if ((e = hipMemcpy(fin.data(), d_carry, W * 8, hipMemcpyDeviceToHost))) return hip_die("copy totals", e);
+    // the upper rows' totals once more, from sat_column_totals alone
+    if (sat_column_totals(d_img, SAT_U8, h1, W, ip, nullptr, nullptr, d_carry, nullptr, nullptr))
+        return die("sat_column_totals");
+    if ((e = hipMemcpy(upper.data(), d_carry, W * 8, hipMemcpyDeviceToHost))) return hip_die("copy totals", e);
+
     std::FILE *f = std::fopen(argv[3], "wb");
     if (!f) {
         std::fprintf(stderr, "capi_check: cannot open %s\n", argv[3]);
         return 1;
     }
     const bool ok = append(f, S) && append(f, Q) && append(f, sums) && append(f, m0) && append(f, m1) &&
-                    append(f, s1) && append(f, mean) && append(f, stdv);
+                    append(f, s1) && append(f, mean) && append(f, stdv) && append(f, B) && append(f, top) &&
+                    append(f, upper) && append(f, fin);
     std::fclose(f);
     if (!ok) {
         std::fprintf(stderr, "capi_check: short write\n");
@@ -123,7 +159,8 @@ int main(int argc, char **argv) {
     }
     for (void *p : {d_img, d_ws, static_cast<void *>(d_S), static_cast<void *>(d_Q), static_cast<void *>(d_sum),
                     d_multi[0], d_multi[1], static_cast<void *>(d_s1), static_cast<void *>(d_mean),
-                    static_cast<void *>(d_std)})
+                    static_cast<void *>(d_std), static_cast<void *>(d_B), static_cast<void *>(d_top),
+                    static_cast<void *>(d_carry), d_bws})
         (void)hipFree(p);
     std::printf("capi_check ok: %lld x %lld\n", static_cast<long long>(H), static_cast<long long>(W));
     return 0;

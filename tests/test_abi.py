@@ -215,3 +215,66 @@ def test_powers_and_moments_validation(lib):
     big16 = (P * 3)(SAT, SQ, OUT)
     assert lib.window_moments(big16, 3, SAT_U16, 4096, 4096, 4096, 256, 257, 1, None, None, OUT2, None, 4096,
                               None) == SAT_ERR_OVERFLOW
+
+
+CARRY, CARRY_SQ, TOT, TOT_SQ = (0x10000000000 * k for k in range(8, 12))
+
+
+def band(lib, image=IMG, ptype=SAT_U8, H=64, W=80, ipitch=80, carry=CARRY, carry_sq=None, rows_above=100,
+         sat=SAT, sat_sq=None, spitch=80, total=TOT, total_sq=None, ws=WS, wsb=None):
+    if wsb is None:
+        wsb = lib.sat_build_workspace_bytes(H, W, ptype if ptype in (SAT_U8, SAT_U16) else SAT_U8, int(bool(sat_sq)))
+    return lib.sat_build_band(image, ptype, H, W, ipitch, carry, carry_sq, rows_above, sat, sat_sq, spitch, total,
+                              total_sq, ws, wsb, None)
+
+
+def test_band_build_validation(lib):
+    # everything sat_build checks
+    assert band(lib, image=None) == SAT_ERR_ARG
+    assert band(lib, ipitch=79) == SAT_ERR_ARG
+    assert band(lib, ws=None) == SAT_ERR_WORKSPACE
+    # rows above need a carry; a negative count is refused
+    assert band(lib, carry=None, rows_above=5) == SAT_ERR_ARG
+    assert band(lib, rows_above=-1) == SAT_ERR_ARG
+    # squares: a carry needs carry_sq, carry_sq needs sat_sq and a carry, total_sq needs sat_sq
+    assert band(lib, sat_sq=SQ) == SAT_ERR_ARG
+    assert band(lib, carry_sq=CARRY_SQ) == SAT_ERR_ARG
+    assert band(lib, carry=None, rows_above=0, carry_sq=CARRY_SQ, sat_sq=SQ) == SAT_ERR_ARG
+    assert band(lib, total_sq=TOT_SQ) == SAT_ERR_ARG
+    # totals must not overlap the image, a table or each other; carries must not overlap a table
+    assert band(lib, total=SAT + 8) == SAT_ERR_ARG
+    assert band(lib, total=IMG + 8) == SAT_ERR_ARG
+    assert band(lib, sat_sq=SQ, carry_sq=CARRY_SQ, total_sq=TOT + 16) == SAT_ERR_ARG
+    assert band(lib, carry=SAT + 8) == SAT_ERR_ARG
+    # a carry equals its total (in place) or overlaps no total
+    assert band(lib, carry=TOT + 8) == SAT_ERR_ARG
+    # alignment of carries and totals
+    assert band(lib, carry=CARRY + 4) == SAT_ERR_ARG
+    assert band(lib, total=TOT + 4) == SAT_ERR_ARG
+    # workspace must not overlap a carry or a total
+    assert band(lib, ws=CARRY) == SAT_ERR_ARG
+    assert band(lib, ws=TOT) == SAT_ERR_ARG
+    # the 62-bit bound counts the rows above: 16-bit squares, H + rows_above rows
+    lim = (1 << 62) // (65535 * 65535)
+    assert band(lib, ptype=SAT_U16, H=10, W=1, ipitch=1, spitch=1, sat_sq=SQ, carry_sq=CARRY_SQ,
+                rows_above=lim - 5, wsb=1 << 40) == SAT_ERR_OVERFLOW
+    # rows above are a row count like any height (at most 2^31 - 1); below that only 16-bit
+    # squares can reach 2^62
+    assert band(lib, rows_above=1 << 31, wsb=1 << 40) == SAT_ERR_ARG
+
+
+def test_column_totals_validation(lib):
+    def tot(image=IMG, ptype=SAT_U8, H=64, W=80, ipitch=80, carry=None, carry_sq=None, out=TOT, out_sq=None):
+        return lib.sat_column_totals(image, ptype, H, W, ipitch, carry, carry_sq, out, out_sq, None)
+
+    assert tot(image=None) == SAT_ERR_ARG
+    assert tot(out=None) == SAT_ERR_ARG
+    assert tot(ptype=SAT_U32) == SAT_ERR_ARG
+    assert tot(H=0) == SAT_ERR_ARG
+    assert tot(ipitch=79) == SAT_ERR_ARG
+    assert tot(carry_sq=CARRY_SQ) == SAT_ERR_ARG                    # carry_sq without out_sq
+    assert tot(carry=CARRY, out_sq=TOT_SQ) == SAT_ERR_ARG            # squares with a carry need carry_sq
+    assert tot(out=IMG + 8) == SAT_ERR_ARG                           # output overlaps the image
+    assert tot(out_sq=TOT + 8) == SAT_ERR_ARG                        # outputs overlap
+    assert tot(carry=TOT + 8) == SAT_ERR_ARG                         # partial overlap of a carry
+    assert tot(out=TOT + 4) == SAT_ERR_ARG                           # misaligned

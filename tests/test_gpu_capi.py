@@ -1,8 +1,9 @@
 """libsat.so driven through its C ABI alone: a host program (tests/c_abi/capi_check.cpp, built by
 __graft_entry__.build()) allocates with the HIP runtime, calls sat_build, window_sum,
-window_sum_multi and window_mean_std from include/sat.h on an image with unaligned rows, and
-writes the results; they must match the oracle (integers bit-exact, the mean bit-exact, the std
-within 1e-12 relative)."""
+window_sum_multi and window_mean_std from include/sat.h on an image with unaligned rows, then
+builds the same table in two bands (sat_column_totals, sat_build_band), and writes the results;
+they must match the oracle (integers bit-exact, the mean bit-exact, the std within 1e-12
+relative)."""
 import os
 import subprocess
 
@@ -57,4 +58,10 @@ def test_c_abi_program_matches_oracle(tmp_path):
     nz = ref_std > 0
     assert np.all(std[~nz] == 0.0)
     assert np.max(np.abs(std[nz] - ref_std[nz]) / ref_std[nz]) <= 1e-12
+    h1 = H // 2
+    assert np.array_equal(take(np.uint64, S.shape), S)                        # table from two bands
+    upper = oracle.column_totals(img[:h1])
+    assert np.array_equal(take(np.uint64, (W,)), upper)                       # upper band's totals output
+    assert np.array_equal(take(np.uint64, (W,)), upper)                       # sat_column_totals
+    assert np.array_equal(take(np.uint64, (W,)), oracle.column_totals(img))   # advanced in place
     assert pos == len(raw)

@@ -12,6 +12,7 @@ import oracle
 from oracle import build as oracle_build
 
 import test_oracle as pins
+import test_oracle_bands as bpins
 import test_oracle_moments as mpins
 
 SRC = oracle_build.SRC
@@ -38,6 +39,10 @@ MUTANTS = [
      "kurt[i] = A == 0 ? NAN : (double)C / (a * a);"),
     ("kurtosis with 4 n S1^2 S2", "+ 6 * N * a1 * a1 * a2 - 3 * a1 * a1 * a1 * a1;",
      "+ 4 * N * a1 * a1 * a2 - 3 * a1 * a1 * a1 * a1;"),
+    ("column totals skip the last row", "for (int64_t y = 0; y < H; ++y) {       /* row by row",
+     "for (int64_t y = 0; y < H - 1; ++y) {       /* row by row"),
+    ("column totals drop the carry", "T[x] = carry ? carry[x] : 0;", "T[x] = 0;"),
+    ("column totals of squares add the pixel", "if (T2) T2[x] += v * v;", "if (T2) T2[x] += v;"),
     ("direct window powers skip the first power", "for (int j = 0; j < k; ++j) {\n                p *= v;\n                sums[j] += p;",
      "for (int j = 0; j < k; ++j) {\n                sums[j] += p;\n                p *= v;"),
 ]
@@ -56,6 +61,9 @@ PIN_CALLS = [
     (mpins.test_moments_match_the_central_definition_in_exact_arithmetic, ()),
     (mpins.test_two_valued_windows_follow_the_bernoulli_closed_forms, (3,)),
     (mpins.test_constant_windows_have_no_shape_and_symmetric_ones_no_skew, ()),
+    (bpins.test_column_totals_brute_force, ()),
+    (bpins.test_column_totals_are_differences_of_the_last_table_row, (np.uint8,)),
+    (bpins.test_band_rows_follow_from_the_band_and_the_totals_above, (np.uint16,)),
 ]
 
 
