@@ -133,34 +133,6 @@ int row_align(const void *image, int64_t ipitch, int bpp) {
     return 1;
 }
 
-// align: the least row alignment class over the images (row_align).
-int choose_build_variant(int64_t total_rows, int n_images, int bpp, bool sq, int align) {
-    const int v = g_force[0];
-    if (v >= 0) return v;
-    // Each work item is one strip swept across the full width, so the number of strips is the
-    // parallelism.  Measured choices (ms per build; 8192^2 to 70000 x 85000):
-    //  - one image with 16-byte aligned rows: the helper wave, which stages tiles by 16-byte DMA
-    //    and runs the lookback one block ahead of the compute waves, so the lookback's memory
-    //    round trip never stalls them.  Eight pixels per lane once its 48-row strips fill the
-    //    resident workgroups (9-18 % faster than any lookback variant from 24576^2 up), four
-    //    with 16-bit pixels and squares (the eight-pixel state does not fit the LDS) or fewer
-    //    strips;
-    //  - otherwise, with two 64-row strips per CU or more: lookback with non-temporal table
-    //    stores (the table is read back only after it has left the caches), eight pixels per
-    //    lane for 8-bit images without squares (elsewhere that variant holds one wave per SIMD);
-    //  - with fewer strips each workgroup's own latency decides: the helper wave when rows allow
-    //    its DMA, else 32-row strips.
-    if (n_images == 1 && align == 16) {
-        if (bpp == 2 && sq) return kVarHelperPx4;
-        const int64_t strips48 = (total_rows + 47) / 48;
-        return strips48 >= satk::build_variant_capacity(kVarHelperPx8, bpp, sq) ? kVarHelperPx8 : kVarHelperPx4;
-    }
-    const int64_t want = 2ll * device_cus();
-    const int64_t strips64 = (total_rows + 63 * n_images) / 64;
-    if (strips64 >= want) return (bpp == 1 && !sq) ? kVarNtPx8 : kVarNtPx4;
-    return align >= 4 ? kVarHelperPx4 : kVarShort;
-}
-
 // Strip height of at most th rows for one image: th unless the strips would not fit the `cap`
 // resident workgroups in whole rounds; then the height that spreads them evenly over the fewest
 // rounds (a last round with few strips costs a whole strip sweep).
@@ -173,9 +145,72 @@ int balanced_strip_h(int64_t H, int th, int64_t cap) {
     return static_cast<int>(h < th ? h : th);
 }
 
-int choose_strip_h(int v, int64_t H, int bpp, bool sq) {
+// Plan of the helper-wave build of one image with 16-byte aligned rows.  Where its strips are no
+// more than the compute units, each workgroup sweeps the width alone at one lookback round trip
+// per block, and blocks of eight pixels per lane (512 columns) need half the trips of blocks of
+// four.  So: eight pixels per lane at 48-row strips, or 24-row strips where 48-row ones would
+// leave three quarters of the CUs idle.  Where 48-row strips outnumber the CUs but 64-row strips
+// do not, one 64-row strip per CU at four pixels per lane beats two 48-row strips on some CUs.
+// Taller images take eight pixels per lane at 48 rows, balanced over rounds of resident
+// workgroups once they fill one.  Images narrower than eight 512-column blocks, and 16-bit images
+// with squares (whose eight-pixel tiles do not fit the LDS), take four pixels per lane at the
+// least of 32, 48 or 64 rows that gives at most one strip per CU.
+// Measured (ms per build, previous choice -> this one, bit-exact throughout): 8750 x 85000 u8
+// 2.43 -> 1.79; 17500 x 85000 u8 4.56 -> 3.39; 20000^2 u8 1.28 -> 1.00; 16000^2 u8 0.81 -> 0.63;
+// 2000 x 16000 u8 0.30 -> 0.25; 8192^2 u16 0.24 -> 0.21; 12000^2 u16 with squares 0.83 -> 0.72.
+struct BuildPlan {
+    int v;
+    int strip_h;
+};
+
+int helper_strip_h(int v, int64_t H, int bpp, bool sq) {
+    const int64_t ncu = device_cus();
+    const int64_t cap = satk::build_variant_capacity(v, bpp, sq);
+    const int th = satk::build_variant(v).th();
+    if (v == kVarHelperPx8) {
+        if (4 * ((H + th - 1) / th) <= ncu) return th / 2;
+        return balanced_strip_h(H, th, cap);
+    }
+    for (int h = th / 2; h < th; h += th / 4)
+        if ((H + h - 1) / h <= ncu) return h;
+    return balanced_strip_h(H, th, cap);
+}
+
+BuildPlan helper_plan(int64_t H, int64_t W, int bpp, bool sq) {
+    const int64_t ncu = device_cus();
+    int v = kVarHelperPx4;
+    if (W >= 8 * satk::build_variant(kVarHelperPx8).bw() && satk::build_variant_capacity(kVarHelperPx8, bpp, sq) > 0) {
+        const int64_t n48 = (H + 47) / 48, n64 = (H + 63) / 64;
+        v = (n48 > ncu && n64 <= ncu) ? kVarHelperPx4 : kVarHelperPx8;
+    }
+    return {v, helper_strip_h(v, H, bpp, sq)};
+}
+
+// align: the least row alignment class over the images (row_align).
+int choose_build_variant(int64_t total_rows, int64_t W, int n_images, int bpp, bool sq, int align) {
+    const int v = g_force[0];
+    if (v >= 0) return v;
+    // Each work item is one strip swept across the full width, so the number of strips is the
+    // parallelism.  Measured choices (ms per build; 2000 x 16000 to 70000 x 85000):
+    //  - one image with 16-byte aligned rows: the helper wave, which stages tiles by 16-byte DMA
+    //    and runs the lookback one block ahead of the compute waves (helper_plan below);
+    //  - otherwise, with two 64-row strips per CU or more: lookback with non-temporal table
+    //    stores (the table is read back only after it has left the caches), eight pixels per
+    //    lane for 8-bit images without squares (elsewhere that variant holds one wave per SIMD);
+    //  - with fewer strips each workgroup's own latency decides: the helper wave when rows allow
+    //    its DMA, else 32-row strips.
+    if (n_images == 1 && align == 16) return helper_plan(total_rows, W, bpp, sq).v;
+    const int64_t want = 2ll * device_cus();
+    const int64_t strips64 = (total_rows + 63 * n_images) / 64;
+    if (strips64 >= want) return (bpp == 1 && !sq) ? kVarNtPx8 : kVarNtPx4;
+    return align >= 4 ? kVarHelperPx4 : kVarShort;
+}
+
+// Strip height for variant v on one image of H rows with row alignment class `align`.
+int choose_strip_h(int v, int64_t H, int bpp, bool sq, int align) {
     const satk::BuildVariant &var = satk::build_variant(v);
     if (!satk::build_variant_adaptive(v)) return var.th();
+    if (align == 16 && (v == kVarHelperPx4 || v == kVarHelperPx8)) return helper_strip_h(v, H, bpp, sq);
     const int64_t cap = satk::build_variant_capacity(v, bpp, sq);
     // Few strips (at most half the resident workgroups): 32-row strips, twice as many, all in one
     // round.  Measured at 4096-12000 rows: 3-11 % faster than 64-row strips; 16- and 24-row strips
@@ -218,7 +253,7 @@ int64_t build_state_words(int v, int64_t H, int64_t W, bool sq) {
 int64_t build_state_words_any(int64_t H, int64_t W, int bpp, bool sq) {
     int64_t words = 0;
     for (int align : {16, 4, 1}) {
-        const int64_t w = build_state_words(choose_build_variant(H, 1, bpp, sq, align), H, W, sq);
+        const int64_t w = build_state_words(choose_build_variant(H, W, 1, bpp, sq, align), H, W, sq);
         if (w > words) words = w;
     }
     return words;
@@ -365,11 +400,12 @@ sat_status build_one(const void *image, sat_dtype pixel_type, int64_t H, int64_t
     const Span sw{reinterpret_cast<uintptr_t>(workspace), reinterpret_cast<uintptr_t>(workspace) + workspace_bytes};
     for (const Span *o : {&si, &ss, &sqs, &sc, &scq, &st_, &stq})
         if (overlap(sw, *o)) return fail(SAT_ERR_ARG, "%s: workspace overlaps an input or output", who);
-    const int v = choose_build_variant(H, 1, bpp, sq, row_align(image, image_pitch, bpp));
+    const int align = row_align(image, image_pitch, bpp);
+    const int v = choose_build_variant(H, W, 1, bpp, sq, align);
     if ((st = check_build_variant(v, bpp, sq, who))) return st;
     const satk::BuildVariant &var = satk::build_variant(v);
     satk::BuildDesc d{};
-    const int strip_h = choose_strip_h(v, H, bpp, sq);
+    const int strip_h = choose_strip_h(v, H, bpp, sq, align);
     fill_desc(d, var, image, bpp, H, W, image_pitch, sat, sat_sq, sat_pitch, strip_h);
     d.state_off = 0;
     d.state_q_off = static_cast<int64_t>(d.nstrips) * d.Wp;
@@ -405,7 +441,7 @@ sat_status window_out_shape(int64_t H, int64_t W, int64_t win_h, int64_t win_w, 
 size_t sat_build_workspace_bytes(int64_t H, int64_t W, sat_dtype pixel_type, int with_sq) {
     if (H < 1 || W < 1 || H > kMaxDim || W > kMaxDim) return 0;
     if (pixel_type != SAT_U8 && pixel_type != SAT_U16) return 0;
-    const int v = choose_build_variant(H, 1, bytes_of(pixel_type), with_sq != 0, 16);
+    const int v = choose_build_variant(H, W, 1, bytes_of(pixel_type), with_sq != 0, 16);
     if (v < 0 || v >= satk::build_variant_count()) return 0;
     return sizeof(satk::BuildCtrl) +
            8 * static_cast<size_t>(build_state_words_any(H, W, bytes_of(pixel_type), with_sq != 0));
@@ -711,7 +747,7 @@ size_t sat_batch_workspace_bytes(const sat_batch_item *items, int32_t n, sat_dty
         rows += items[i].H;
     }
     for (int align : {16, 4, 1}) {   // whichever variant the rows' alignment selects
-        const int v = choose_build_variant(rows, n, bytes_of(pixel_type), with_sq != 0, align);
+        const int v = choose_build_variant(rows, 0, n, bytes_of(pixel_type), with_sq != 0, align);
         if (v < 0 || v >= satk::build_variant_count()) return 0;
         const satk::BuildVariant &var = satk::build_variant(v);
         size_t w = 0;
@@ -770,7 +806,7 @@ sat_status sat_build_batched(const sat_batch_item *items, int32_t n, sat_dtype p
         const int a = row_align(items[i].image, items[i].image_pitch, bpp);
         if (a < align) align = a;
     }
-    const int v = choose_build_variant(rows, n, bpp, with_sq, align);
+    const int v = choose_build_variant(rows, 0, n, bpp, with_sq, align);
     if (sat_status st = check_build_variant(v, bpp, with_sq, who)) return st;
     const satk::BuildVariant &var = satk::build_variant(v);
     std::vector<satk::BuildDesc> d(n);
