@@ -1471,48 +1471,63 @@ __global__ __launch_bounds__(256) void totals_init_kernel(const uint64_t *carry,
     if (out_q) out_q[x] = carry_q ? carry_q[x] : 0;
 }
 
-// Column totals of an image added to out (and of its squares to out_q): the prepass a strip of
-// rows needs before its band build when the strips above are built elsewhere.  A workgroup is one
-// wave over a tile of kTotRowBytes-byte columns and rows_per rows (<= 65536, so that a lane's
-// 32-bit sums of pixels, of 8-bit squares, are exact); each lane sums its columns down the rows
-// in registers and adds them to out with 64-bit atomics.  Tiles wholly inside the image with
-// 16-byte aligned rows give each lane 16 contiguous bytes (one 16-byte load per row); other
-// tiles give lane l the columns l, l + 64, ... (one coalesced element load per column group).
+// Column totals of an image added to out (and of its squares to out_q): the prepass a band of
+// rows needs before its build when the rows above it are built elsewhere.  A workgroup is four
+// waves over a tile of kTotRowBytes-byte columns and rows_per rows; wave w sums the rows
+// y0 + w, y0 + w + 4, ... of the tile in registers, kTotBatch rows' loads in flight at a time.  A
+// wave sums at most 16384 rows, so its 32-bit sums of pixels and of 8-bit squares are exact; the
+// four waves' sums meet in LDS, and each column's total goes to out with one 64-bit atomic add.
+// Tiles wholly inside the image with 16-byte aligned rows give each lane 16 contiguous bytes of a
+// row; other tiles give lane l the columns l, l + 64, ... (coalesced element loads).
 constexpr int kTotRowBytes = 1024;
+constexpr int kTotWaves = 4;
+constexpr int kTotBatch = 8;
+constexpr long long kTotMaxRows = 65536;   // rows per tile: 16384 per wave
 
 template <typename T, bool SQ>
-__global__ __launch_bounds__(64) void column_totals_kernel(const T *__restrict__ img, long long H, long long W,
-                                                           long long pitch, long long rows_per, long long ncol,
-                                                           int vec16, uint64_t *out, uint64_t *out_q) {
-    constexpr int VEC = 16 / static_cast<int>(sizeof(T));   // columns per lane
+__global__ __launch_bounds__(64 * kTotWaves) void column_totals_kernel(const T *__restrict__ img, long long H,
+                                                                       long long W, long long pitch,
+                                                                       long long rows_per, long long ncol, int vec16,
+                                                                       uint64_t *out, uint64_t *out_q) {
+    constexpr int VEC = 16 / static_cast<int>(sizeof(T));            // columns per lane
     constexpr int CW = kTotRowBytes / static_cast<int>(sizeof(T));   // columns per tile
     using QT = typename std::conditional<sizeof(T) == 1, uint32_t, uint64_t>::type;
+    __shared__ uint32_t red[kTotWaves * CW];
+    __shared__ QT red_q[SQ ? kTotWaves * CW : 1];
     const long long cb = static_cast<long long>(blockIdx.x) % ncol, rb = static_cast<long long>(blockIdx.x) / ncol;
     const long long y0 = rb * rows_per;
     const long long y1 = y0 + rows_per < H ? y0 + rows_per : H;
     const long long xw = cb * CW;
-    const int lane = static_cast<int>(threadIdx.x);
+    const int lane = static_cast<int>(threadIdx.x) & 63, wave = static_cast<int>(threadIdx.x) >> 6;
     uint32_t sum[VEC];
     QT sq[VEC];
 #pragma unroll
     for (int k = 0; k < VEC; ++k) { sum[k] = 0; sq[k] = 0; }
-    const bool fast = vec16 && xw + CW <= W;   // uniform over the workgroup
-    if (fast) {
-        const T *p = img + y0 * pitch + xw + lane * VEC;
-#pragma unroll 4
-        for (long long y = y0; y < y1; ++y, p += pitch) {
-            const u32x4 t = *reinterpret_cast<const u32x4 *>(p);
-            const uint32_t wd[4] = {t.x, t.y, t.z, t.w};
+    auto add16 = [&](const u32x4 t) {
+        const uint32_t wd[4] = {t.x, t.y, t.z, t.w};
 #pragma unroll
-            for (int k = 0; k < VEC; ++k) {
-                const uint32_t v = sizeof(T) == 1 ? (wd[k >> 2] >> (8 * (k & 3))) & 0xffu
-                                                  : (wd[k >> 1] >> (16 * (k & 1))) & 0xffffu;
-                sum[k] += v;
-                if (SQ) sq[k] += static_cast<QT>(v) * v;
-            }
+        for (int k = 0; k < VEC; ++k) {
+            const uint32_t v = sizeof(T) == 1 ? (wd[k >> 2] >> (8 * (k & 3))) & 0xffu
+                                              : (wd[k >> 1] >> (16 * (k & 1))) & 0xffffu;
+            sum[k] += v;
+            if (SQ) sq[k] += static_cast<QT>(v) * v;
         }
+    };
+    const bool fast = vec16 && xw + CW <= W;   // uniform over the workgroup
+    long long y = y0 + wave;
+    if (fast) {
+        const T *base = img + xw + lane * VEC;
+        for (; y + (kTotBatch - 1) * kTotWaves < y1; y += kTotBatch * kTotWaves) {
+            u32x4 t[kTotBatch];
+#pragma unroll
+            for (int b = 0; b < kTotBatch; ++b)
+                t[b] = *reinterpret_cast<const u32x4 *>(base + (y + b * kTotWaves) * pitch);
+#pragma unroll
+            for (int b = 0; b < kTotBatch; ++b) add16(t[b]);
+        }
+        for (; y < y1; y += kTotWaves) add16(*reinterpret_cast<const u32x4 *>(base + y * pitch));
     } else {
-        for (long long y = y0; y < y1; ++y) {
+        for (; y < y1; y += kTotWaves) {
             const T *row = img + y * pitch + xw + lane;
 #pragma unroll
             for (int k = 0; k < VEC; ++k) {
@@ -1524,10 +1539,22 @@ __global__ __launch_bounds__(64) void column_totals_kernel(const T *__restrict__
     }
 #pragma unroll
     for (int k = 0; k < VEC; ++k) {
-        const long long x = fast ? xw + lane * VEC + k : xw + lane + 64 * k;
+        const int c = fast ? lane * VEC + k : lane + 64 * k;   // column within the tile
+        red[wave * CW + c] = sum[k];
+        if (SQ) red_q[wave * CW + c] = sq[k];
+    }
+    __syncthreads();
+    for (int c = static_cast<int>(threadIdx.x); c < CW; c += 64 * kTotWaves) {
+        const long long x = xw + c;
         if (x < W) {
-            atomicAdd(reinterpret_cast<unsigned long long *>(out + x), static_cast<unsigned long long>(sum[k]));
-            if (SQ) atomicAdd(reinterpret_cast<unsigned long long *>(out_q + x), static_cast<unsigned long long>(sq[k]));
+            uint64_t s = 0, q = 0;
+#pragma unroll
+            for (int w = 0; w < kTotWaves; ++w) {
+                s += red[w * CW + c];
+                if (SQ) q += red_q[w * CW + c];
+            }
+            atomicAdd(reinterpret_cast<unsigned long long *>(out + x), static_cast<unsigned long long>(s));
+            if (SQ) atomicAdd(reinterpret_cast<unsigned long long *>(out_q + x), static_cast<unsigned long long>(q));
         }
     }
 }
@@ -1541,15 +1568,16 @@ hipError_t launch_totals_typed(const void *img, int64_t H, int64_t W, int64_t pi
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     constexpr int CW = kTotRowBytes / static_cast<int>(sizeof(T));
+    constexpr int64_t kStep = kTotWaves * kTotBatch;
     const int64_t ncol = (W + CW - 1) / CW;
-    // About 4096 workgroups (16 per compute unit): rows per tile from that, at least 16 and at
-    // most 65536 (exact 32-bit lane sums).
-    int64_t rows_per = (H * ncol + 4095) / 4096;
-    if (rows_per < 16) rows_per = 16;
-    if (rows_per > 65536) rows_per = 65536;
+    // About 2048 workgroups (eight per compute unit, two rounds of four-wave groups): rows per
+    // tile from that, a whole number of load batches, at most kTotMaxRows.
+    int64_t rows_per = (H * ncol + 2047) / 2048;
+    rows_per = (rows_per + kStep - 1) / kStep * kStep;
+    if (rows_per > kTotMaxRows) rows_per = kTotMaxRows;
     const int64_t nrow = (H + rows_per - 1) / rows_per;
-    hipLaunchKernelGGL((column_totals_kernel<T, SQ>), dim3(static_cast<unsigned>(ncol * nrow)), dim3(64), 0, stream,
-                       static_cast<const T *>(img), static_cast<long long>(H), static_cast<long long>(W),
+    hipLaunchKernelGGL((column_totals_kernel<T, SQ>), dim3(static_cast<unsigned>(ncol * nrow)), dim3(64 * kTotWaves),
+                       0, stream, static_cast<const T *>(img), static_cast<long long>(H), static_cast<long long>(W),
                        static_cast<long long>(pitch), static_cast<long long>(rows_per), static_cast<long long>(ncol),
                        vec16, out, out_q);
     return hipGetLastError();
