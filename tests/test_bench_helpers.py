@@ -25,11 +25,9 @@ def touched_entries(H, W, hs):
     return int(seen.sum())
 
 
-@pytest.mark.parametrize("H,W,hs", [(9, 7, (1,)), (9, 7, (3,)), (9, 7, (9, 7)), (12, 15, (2, 5)), (6, 6, (6,)),
+@pytest.mark.parametrize("H,W,hs", [(9, 7, (1,)), (9, 7, (3,)), (9, 7, (7, 5)), (12, 15, (2, 5)), (6, 6, (6,)),
                                     (20, 11, (4, 10))])
 def test_window_bytes_count_every_touched_entry_once(H, W, hs):
-    if any(h > min(H, W) for h in hs):
-        pytest.skip("window larger than the image")
     outs = sum((H - h + 1) * (W - h + 1) for h in hs)
     assert bench.alg_bytes_windows(H, W, hs) == touched_entries(H, W, hs) * 8 + outs * 4
 
