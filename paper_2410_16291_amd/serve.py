@@ -297,8 +297,8 @@ class GpuExecutor:
         return H * table_pitch(W) * 8
 
     def build_transient_bytes(self, H: int, W: int) -> int:
-        from .api import build_workspace_bytes
-        return H * W + build_workspace_bytes(H, W, 1, False)
+        from .api import build_workspace_bytes, image_pitch
+        return H * image_pitch(W, self.torch.uint8) + build_workspace_bytes(H, W, 1, False)
 
     def query_transient_bytes(self, req: Request, r: Resident) -> int:
         import torch
@@ -315,7 +315,9 @@ class GpuExecutor:
         torch = self.torch
         s = self.streams[slot]
         with torch.cuda.stream(s):
-            img = synth.thomas_mask_device(req.H, req.W, req.image_seed, self.dev)
+            # the image lands on 128-byte row lines, the layout the build stages fastest
+            img = synth.thomas_mask_device(req.H, req.W, req.image_seed, self.dev,
+                                           out=api.empty_image(req.H, req.W, torch.uint8, self.dev))
             r.tables = api.sat_build(img, stream=s)
             ev = torch.cuda.Event()
             ev.record(s)

@@ -152,10 +152,17 @@ def lognormal_u16_device(H: int, W: int, seed: int, device, mu: float = 6.0, sig
 
 
 def thomas_mask_device(H: int, W: int, seed: int, device, parent_density: float = 2e-6, children: int = 200,
-                       sigma: float = 40.0):
-    """thomas_mask drawn on the host (the same points) and scattered into a device uint8 image."""
+                       sigma: float = 40.0, out=None):
+    """thomas_mask drawn on the host (the same points) and scattered into a device uint8 image:
+    a new contiguous one, or `out` (an H x W uint8 device view of any row pitch, overwritten)."""
     import torch
     ys, xs = thomas_points(H, W, parent_density, children, sigma, seed)
-    img = torch.zeros((H, W), dtype=torch.uint8, device=device)
-    img.view(-1)[torch.from_numpy(ys * W + xs).to(device)] = 1
-    return img
+    if out is None:
+        img = torch.zeros((H, W), dtype=torch.uint8, device=device)
+        img.view(-1)[torch.from_numpy(ys * W + xs).to(device)] = 1
+        return img
+    if tuple(out.shape) != (H, W) or out.dtype != torch.uint8:
+        raise ValueError("out must be an H x W uint8 tensor")
+    out.zero_()
+    out[torch.from_numpy(ys).to(out.device), torch.from_numpy(xs).to(out.device)] = 1
+    return out
