@@ -14,7 +14,10 @@
  *   window_sum_multi several window sizes from one table in one pass (Sec. I, Sec. V);
  *   *_batched        the same over many images in one launch;
  *   sat_build_band   the table of a band of rows of a taller image, from the band and the column
- *                    totals of the rows above it (sat_column_totals).
+ *                    totals of the rows above it (sat_column_totals);
+ *   sat_build_powers the tables of pixel^1 .. pixel^k in one pass, and window_moments the window
+ *                    mean, deviation, skewness and excess kurtosis from them (further
+ *                    sliding-window statistics, left to future work in Sec. V).
  *
  * Conventions shared by every call:
  *   - Images are row-major, 8- or 16-bit unsigned, with a row pitch in ELEMENTS (>= width; the
