@@ -146,10 +146,10 @@ int balanced_strip_h(int64_t H, int th, int64_t cap) {
 }
 
 // Plan of the helper-wave build of one image with 16-byte aligned rows.  Where its strips are no
-// more than the compute units, each workgroup sweeps the width alone at one lookback round trip
-// per block, and blocks of eight pixels per lane (512 columns) need half the trips of blocks of
-// four.  So: eight pixels per lane at 48-row strips, or 24-row strips where 48-row ones would
-// leave three quarters of the CUs idle.  Where 48-row strips outnumber the CUs but 64-row strips
+// more than the compute units, each workgroup sweeps the width alone, block by block, and blocks
+// of eight pixels per lane (512 columns) take half the steps of blocks of four.  So: eight pixels
+// per lane at 48-row strips, or 24-row strips where 48-row ones would leave three quarters of the
+// CUs idle.  Where 48-row strips outnumber the CUs but 64-row strips
 // do not, one 64-row strip per CU at four pixels per lane beats two 48-row strips on some CUs.
 // Taller images take eight pixels per lane at 48 rows, balanced over rounds of resident
 // workgroups once they fill one.  Images narrower than eight 512-column blocks, and 16-bit images
