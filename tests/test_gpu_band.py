@@ -63,6 +63,21 @@ def test_column_totals_pitched_rows_with_a_ragged_tile():
         assert np.array_equal(host_u64(T), ref_T) and np.array_equal(host_u64(TQ), ref_TQ)
 
 
+@pytest.mark.parametrize("dtype,value", [(np.uint8, 255), (np.uint16, 65535)])
+def test_column_totals_tiles_at_their_row_limit(dtype, value):
+    """A 140-million-row column: the totals kernel's tiles reach their 65536-row cap (16384 rows per
+    wave), the largest lane sums it forms, here all of the largest pixel value."""
+    H = 140_000_000
+    print("case: column totals, one column of", H, "rows,", np.dtype(dtype).name, flush=True)
+    tdt = torch.uint8 if dtype == np.uint8 else torch.uint16
+    img = torch.full((H, 1), value if dtype == np.uint8 else -1, dtype=torch.uint8 if dtype == np.uint8 else
+                     torch.int16, device="cuda:0").view(tdt)
+    T, TQ = api.column_totals(img, squares=True)
+    ref_T, ref_TQ = oracle.column_totals(np.full((H, 1), value, dtype), squares=True)
+    assert np.array_equal(host_u64(T), ref_T) and np.array_equal(host_u64(TQ), ref_TQ)
+    assert int(ref_T[0]) == value * H and int(ref_TQ[0]) == value * value * H
+
+
 # ------------------------------------------------------------------ band builds
 
 SPLITS = [0, 1, 97, 500, 1099, 1100]   # bands of 1, 96, 403, 599 and 1 rows of a 1100-row image
