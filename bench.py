@@ -274,7 +274,10 @@ def serving_section(torch, dev, seconds, burst_seconds):
         torch.cuda.empty_cache()
         return rep.as_dict()
 
-    run(50.0, 0.5, 4)                     # warm-up: library load, allocator, first launches
+    # warm-up: library load, allocator, and the first launch of every kernel the mix uses (a
+    # kernel's code is loaded at its first launch, tens of milliseconds once); a second of the
+    # burst rate draws every request kind of the stream
+    run(500.0, 1.0, 4)
     out = {"workload": "Poisson arrivals; 20% builds of uint8 Thomas-cluster masks with sides uniform on "
                        "2000..16000, 80% window queries (sides 16..512, strides 1..8, 25% mean/std) on "
                        "resident tables; 200 GB admission budget; seed 4",
