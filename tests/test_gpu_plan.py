@@ -30,6 +30,10 @@ CASES = [
     (12000, 1000, np.uint16, True, "16-bit with squares: 4 px/lane, 48-row strips"),
     (20000, 1000, np.uint16, True, "16-bit with squares: balanced heights"),
     (6000, 5000, np.uint16, False, "16-bit without squares: 8 px/lane, 48-row strips"),
+    (1, 4096, np.uint8, True, "one row: 8 px/lane, one strip"),
+    (5, 8200, np.uint16, True, "five rows, 16-bit with squares, ragged"),
+    (1, 1, np.uint8, False, "one pixel: narrow, 4 px/lane"),
+    (47, 4096, np.uint16, False, "one strip just short of 48 rows"),
 ]
 
 
