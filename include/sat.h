@@ -205,7 +205,11 @@ sat_status sat_build_batched(const sat_batch_item *items, int32_t n, sat_dtype p
                              void *workspace, size_t workspace_bytes, void *stream);
 
 /* window_mean_std over n images in one launch, one window size and stride for all.  Items
- * whose image is smaller than the window are an error (SAT_ERR_WINDOW, index in the message). */
+ * whose image is smaller than the window are an error (SAT_ERR_WINDOW, index in the message).
+ * workspace: device, 256-byte aligned, at least 256 + 256 * n bytes (sat_batch_workspace_bytes
+ * of the same items is enough); the call writes its descriptor table after the first 256 bytes,
+ * so a workspace shared with a preceding build keeps that build's fault word for
+ * sat_workspace_check.  items is a host array read before the call returns. */
 sat_status window_mean_std_batched(const sat_batch_item *items, int32_t n, int64_t win_h,
                                    int64_t win_w, int64_t stride, void *workspace,
                                    size_t workspace_bytes, void *stream);

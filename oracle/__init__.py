@@ -44,6 +44,12 @@ def _load():
         lib.oracle_moments.restype = None
         lib.oracle_stream.argtypes = ([_p, ctypes.c_int, _i64, _i64, _i64, ctypes.c_int, _i64, _p, _p,
                                        _i64, _p, _p, _p, _i64, _p, _p, _p])
+        lib.oracle_stream_open.argtypes = [_p, ctypes.c_int, _i64, _i64, _i64, ctypes.c_int, _i64, _p, _p, _i64,
+                                           _i64, _p]
+        lib.oracle_stream_open.restype = _p
+        lib.oracle_stream_next.argtypes = [_p, _i64, _p, _p, _p, _p]
+        lib.oracle_stream_close.argtypes = [_p]
+        lib.oracle_stream_close.restype = None
         _lib = lib
     return _lib
 
@@ -197,6 +203,78 @@ def stream(img, windows, s, rows, sat_rows=(), squares=False):
         outs.append(out[pos:pos + n * o].reshape(n, o))
         pos += n * o
     return outs, sat_out, total.value
+
+
+class Stream:
+    """The streamed table (oracle_stream's recurrence) started at image row r0 and advanced band by
+    band: table row r0-1 is the running sum along x of `carry`, the column totals of rows 0..r0-1
+    (uint64, W entries; None when r0 == 0).  Several streams started at different rows cover one
+    image independently.
+
+        st = Stream(img, [(100, 100), (250, 250)], s=1, r0=r0, carry=carry)
+        sat_rows, outs = st.next(r1)   # table rows st.cur..r1-1; per window (k_first, rows)
+        st.close()
+
+    For window i, next() returns the output rows whose windows lie in rows r0..r1-1 and were not
+    returned before, as (index of the first, a (n, ow_i) uint64 array).  `img` is the whole
+    image (it is held, not copied, while the stream is open).
+    """
+
+    def __init__(self, img, windows, s=1, r0=0, carry=None, squares=False):
+        self._img, bpp, pitch = _image(img)
+        self.H, self.W = self._img.shape
+        self.windows = [(int(h), int(w)) for h, w in windows]
+        self.s = int(s)
+        self.cur = int(r0)
+        self.ows = []
+        for h, w in self.windows:
+            shape = window_shape(self.H, self.W, h, w, self.s)
+            if shape is None:
+                raise ValueError("window does not fit")
+            self.ows.append(shape[1])
+        self._carry = None if carry is None else np.ascontiguousarray(carry, dtype=np.uint64)
+        if self._carry is not None and self._carry.shape != (self.W,):
+            raise ValueError("carry must have W entries")
+        n = len(self.windows)
+        wh = np.array([h for h, _ in self.windows] or [0], np.int64)
+        ww = np.array([w for _, w in self.windows] or [0], np.int64)
+        self._h = _load().oracle_stream_open(_ptr(self._img), bpp, self.H, self.W, pitch, int(squares), n,
+                                             _ptr(wh), _ptr(ww), self.s, self.cur,
+                                             _ptr(self._carry) if self._carry is not None else None)
+        if not self._h:
+            raise ValueError("oracle_stream_open rejected its arguments")
+
+    def next(self, r1, want_sat=True):
+        """Advance through row r1-1: (table rows cur..r1-1 as an (r1-cur, W) uint64 array or None,
+        [(k_first, outputs) per window])."""
+        if self._h is None:
+            raise ValueError("stream closed")
+        r1 = int(r1)
+        if r1 < self.cur or r1 > self.H:
+            raise ValueError("r1 out of range")
+        n = len(self.windows)
+        sat = np.empty((r1 - self.cur, self.W), np.uint64) if want_sat else None
+        cap = (r1 - self.cur + self.s - 1) // self.s + 1
+        bufs = [np.empty((cap, ow), np.uint64) for ow in self.ows]
+        ptrs = (ctypes.c_void_p * max(n, 1))(*[b.ctypes.data for b in bufs])
+        k_first = np.zeros(max(n, 1), np.int64)
+        n_out = np.zeros(max(n, 1), np.int64)
+        if _load().oracle_stream_next(self._h, r1, _ptr(sat) if sat is not None else None, ptrs, _ptr(k_first),
+                                      _ptr(n_out)):
+            raise ValueError("oracle_stream_next rejected its arguments")
+        self.cur = r1
+        return sat, [(int(k_first[i]), bufs[i][:int(n_out[i])]) for i in range(n)]
+
+    def close(self):
+        if self._h is not None:
+            _load().oracle_stream_close(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # ---- higher window moments (tables of pixel powers; the method applied to I^k)

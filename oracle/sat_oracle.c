@@ -260,6 +260,134 @@ int oracle_stream(const void *img, int bpp, int64_t H, int64_t W, int64_t pitch,
     return 0;
 }
 
+/* ---- The streamed integral image, resumable and started part-way down the image.
+ *
+ * The same serial recurrence as oracle_sat / oracle_stream, begun at image row r0 instead of row
+ * 0.  The rows above r0 enter only through their column totals carry[x] = sum_{y<r0} I[y][x]: by
+ * the definition of the table (Sec. II-B) the table row just above the start is
+ *   S[r0-1][x] = sum_{j<=x} carry[j],
+ * and every later row follows from it by the recurrence S[y][x] = S[y-1][x] + sum_{j<=x} I[y][j].
+ * The stream keeps that recurrence's last hmax+1 rows (a ring) between calls, so a caller walks
+ * the image in bands of rows; several streams started at different rows cover one image in
+ * parallel, each from the column totals of the rows above its start.
+ *
+ * Window sums are emitted by the four-corner lookup of oracle_window_sum_sat as soon as the
+ * bottom row of a window exists, for every window whose rows all lie at or below r0 (the row
+ * above such a window, r0-1 at the highest, is in the ring). */
+typedef struct {
+    const void *img;
+    int bpp, squares;
+    int64_t H, W, pitch, s, r0, cur, ring, nwin;
+    int64_t win_h[8], win_w[8], next_k[8];
+    uint64_t *T;       /* ring of table rows: row y lives at slot y % ring */
+} oracle_stream_state;
+
+/* Start a stream at image row r0 (0 <= r0 <= H; r0 == H gives a stream with nothing to do).
+ * img points at row 0 of the whole H x W image (pitch in elements).  carry: column totals of rows
+ * 0..r0-1 (of the squared pixels when `squares`), W entries, required when r0 > 0 and ignored
+ * otherwise.  Up to 8 windows (win_h[i], win_w[i]) sharing stride s, each fitting the image.
+ * Returns NULL on bad arguments or allocation failure. */
+void *oracle_stream_open(const void *img, int bpp, int64_t H, int64_t W, int64_t pitch, int squares,
+                         int64_t nwin, const int64_t *win_h, const int64_t *win_w, int64_t s, int64_t r0,
+                         const uint64_t *carry) {
+    if (!img || H < 1 || W < 1 || pitch < W || (bpp != 1 && bpp != 2) || s < 1) return NULL;
+    if (nwin < 0 || nwin > 8 || r0 < 0 || r0 > H || (r0 > 0 && !carry)) return NULL;
+    oracle_stream_state *st = (oracle_stream_state *)calloc(1, sizeof(oracle_stream_state));
+    if (!st) return NULL;
+    int64_t hmax = 1;
+    for (int64_t i = 0; i < nwin; ++i) {
+        int64_t oh, ow;
+        if (oracle_window_shape(H, W, win_h[i], win_w[i], s, &oh, &ow)) {
+            free(st);
+            return NULL;
+        }
+        st->win_h[i] = win_h[i];
+        st->win_w[i] = win_w[i];
+        st->next_k[i] = (r0 + s - 1) / s;      /* first window whose top row is at or below r0 */
+        if (win_h[i] > hmax) hmax = win_h[i];
+    }
+    st->img = img;
+    st->bpp = bpp;
+    st->squares = squares;
+    st->H = H;
+    st->W = W;
+    st->pitch = pitch;
+    st->s = s;
+    st->r0 = r0;
+    st->cur = r0;
+    st->nwin = nwin;
+    st->ring = hmax + 1;
+    st->T = (uint64_t *)malloc((size_t)(st->ring * W) * sizeof(uint64_t));
+    if (!st->T) {
+        free(st);
+        return NULL;
+    }
+    if (r0 > 0) {      /* table row r0 - 1: the running sum along x of the totals above */
+        uint64_t *above = st->T + ((r0 - 1) % st->ring) * W, run = 0;
+        for (int64_t x = 0; x < W; ++x) {
+            run += carry[x];
+            above[x] = run;
+        }
+    }
+    return st;
+}
+
+/* Continue the stream through image row r1 - 1 (st's current row <= r1 <= H).  Table rows
+ * cur .. r1-1 are copied to sat_out (W entries each) when it is non-NULL.  For window i, the output
+ * rows k whose window lies in rows r0 .. r1-1 and was not emitted before are written to outs[i]
+ * consecutively (ow_i entries each; outs may be NULL when there are no windows); k_first[i] and
+ * n_out[i] (may be NULL) receive the first such row index and their number.  Returns 0, or 1 on
+ * bad arguments. */
+int oracle_stream_next(void *handle, int64_t r1, uint64_t *sat_out, uint64_t *const *outs, int64_t *k_first,
+                       int64_t *n_out) {
+    oracle_stream_state *st = (oracle_stream_state *)handle;
+    if (!st || r1 < st->cur || r1 > st->H || (st->nwin > 0 && !outs)) return 1;
+    const int64_t W = st->W, s = st->s;
+    int64_t emitted[8] = {0};
+    for (int64_t i = 0; i < st->nwin; ++i)
+        if (k_first) k_first[i] = st->next_k[i];
+    for (int64_t y = st->cur; y < r1; ++y) {
+        uint64_t *cur = st->T + (y % st->ring) * W;
+        const uint64_t *up = y > 0 ? st->T + ((y - 1) % st->ring) * W : NULL;
+        uint64_t run = 0;
+        for (int64_t x = 0; x < W; ++x) {
+            uint64_t v = pixel(st->img, st->bpp, st->pitch, y, x);
+            run += st->squares ? v * v : v;
+            cur[x] = (up ? up[x] : 0) + run;
+        }
+        if (sat_out) memcpy(sat_out + (y - st->cur) * W, cur, (size_t)W * sizeof(uint64_t));
+        for (int64_t i = 0; i < st->nwin; ++i) {
+            int64_t h = st->win_h[i], w = st->win_w[i], oh, ow;
+            oracle_window_shape(st->H, W, h, w, s, &oh, &ow);
+            int64_t k = st->next_k[i];
+            if (k >= oh || k * s + h - 1 != y) continue;   /* window k ends on a later row */
+            int64_t y0 = k * s, y1 = y;
+            const uint64_t *bot = st->T + (y1 % st->ring) * W;
+            const uint64_t *top = y0 > 0 ? st->T + ((y0 - 1) % st->ring) * W : NULL;
+            uint64_t *o = outs[i] + emitted[i] * ow;
+            for (int64_t l = 0; l < ow; ++l) {
+                int64_t x0 = l * s, x1 = x0 + w - 1;
+                uint64_t b1 = bot[x1], b0 = x0 > 0 ? bot[x0 - 1] : 0;
+                uint64_t t1 = top ? top[x1] : 0, t0 = (top && x0 > 0) ? top[x0 - 1] : 0;
+                o[l] = b1 - t1 - b0 + t0;
+            }
+            ++emitted[i];
+            st->next_k[i] = k + 1;
+        }
+    }
+    for (int64_t i = 0; i < st->nwin; ++i)
+        if (n_out) n_out[i] = emitted[i];
+    st->cur = r1;
+    return 0;
+}
+
+void oracle_stream_close(void *handle) {
+    oracle_stream_state *st = (oracle_stream_state *)handle;
+    if (!st) return;
+    free(st->T);
+    free(st);
+}
+
 /* ---- Higher window moments from tables of pixel powers (the method applied to I^k).
  *
  * The paper lists further sliding-window statistics as future work (Sec. V) and builds every

@@ -36,13 +36,21 @@ def _require_cuda(t: torch.Tensor, name: str) -> None:
 
 
 def workspace(nbytes: int, device: torch.device, stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:
-    """A cached device workspace of at least nbytes for builds on this stream."""
-    key = (device.index if device.index is not None else torch.cuda.current_device(),
-           _stream_handle(device, stream))
+    """A cached device workspace of at least nbytes for builds on this stream.
+
+    The buffer is allocated on the stream the builds run on, so torch's caching allocator orders
+    its reuse after them.  A larger request replaces the cached buffer; the old one is first
+    recorded on that stream, so its memory is not handed out again before the launches that used
+    it have run."""
+    s = stream if stream is not None else torch.cuda.current_stream(device)
+    key = (device.index if device.index is not None else torch.cuda.current_device(), s.cuda_stream)
     ws = _workspaces.get(key)
     if ws is None or ws.numel() < nbytes:
-        ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
-        _workspaces[key] = ws
+        with torch.cuda.stream(s):
+            new = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+        if ws is not None:
+            ws.record_stream(s)
+        _workspaces[key] = ws = new
     return ws
 
 

@@ -831,8 +831,8 @@ sat_status sat_build_batched(const sat_batch_item *items, int32_t n, sat_dtype p
     if (dev_desc + desc_bytes > base + workspace_bytes)
         return fail(SAT_ERR_WORKSPACE, "%s: workspace too small for the descriptor table", who);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    hipError_t e = hipMemcpyAsync(dev_desc, d.data(), static_cast<size_t>(n) * sizeof(satk::BuildDesc),
-                                  hipMemcpyHostToDevice, s);
+    static_assert(sizeof(satk::BuildDesc) % 8 == 0, "descriptors move as 64-bit words");
+    hipError_t e = satk::upload_words(d.data(), static_cast<size_t>(n) * sizeof(satk::BuildDesc), dev_desc, s);
     if (e != hipSuccess) return hip_fail(e, who);
     e = satk::launch_build(v, bpp, with_sq, d.data(), n, reinterpret_cast<satk::BuildDesc *>(dev_desc), items_total,
                            workspace, off, s);
@@ -847,10 +847,12 @@ sat_status window_mean_std_batched(const sat_batch_item *items, int32_t n, int64
     if (!workspace) return fail(SAT_ERR_WORKSPACE, "%s: workspace must be non-NULL", who);
     if (reinterpret_cast<uintptr_t>(workspace) % 256)
         return fail(SAT_ERR_ARG, "%s: workspace must be 256-byte aligned", who);
+    // the descriptor table goes after the control header, which keeps the fault word of a build
+    // that shared this workspace intact for sat_workspace_check
     const size_t desc_bytes = round256(static_cast<size_t>(n) * sizeof(satk::GatherDesc));
-    if (workspace_bytes < desc_bytes)
+    if (workspace_bytes < sizeof(satk::BuildCtrl) + desc_bytes)
         return fail(SAT_ERR_WORKSPACE, "%s: workspace of %zu bytes is below the %zu needed", who, workspace_bytes,
-                    desc_bytes);
+                    sizeof(satk::BuildCtrl) + desc_bytes);
     std::vector<satk::GatherDesc> d(n);
     const Span sw{reinterpret_cast<uintptr_t>(workspace), reinterpret_cast<uintptr_t>(workspace) + workspace_bytes};
     std::vector<Span> outs;
@@ -886,10 +888,11 @@ sat_status window_mean_std_batched(const sat_batch_item *items, int32_t n, int64
     }
     if (total > 0xffffffffll) return fail(SAT_ERR_ARG, "%s: too many work items", who);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    hipError_t e = hipMemcpyAsync(workspace, d.data(), static_cast<size_t>(n) * sizeof(satk::GatherDesc),
-                                  hipMemcpyHostToDevice, s);
+    static_assert(sizeof(satk::GatherDesc) % 8 == 0, "descriptors move as 64-bit words");
+    auto *dev_desc = reinterpret_cast<satk::GatherDesc *>(static_cast<char *>(workspace) + sizeof(satk::BuildCtrl));
+    hipError_t e = satk::upload_words(d.data(), static_cast<size_t>(n) * sizeof(satk::GatherDesc), dev_desc, s);
     if (e != hipSuccess) return hip_fail(e, who);
-    e = satk::launch_mean_std(v, d.data(), n, static_cast<satk::GatherDesc *>(workspace), total, s);
+    e = satk::launch_mean_std(v, d.data(), n, dev_desc, total, s);
     if (e != hipSuccess) return hip_fail(e, who);
     return ok();
 }

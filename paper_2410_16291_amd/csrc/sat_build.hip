@@ -1396,6 +1396,19 @@ void build_kernel(const BuildDesc *__restrict__ many, int n, long long total_ite
     }
 }
 
+// A few KiB of host data (descriptor tables) written to device memory from kernel arguments:
+// the launch copies the arguments when it is enqueued, so the caller's host buffer is free once
+// the launch returns (an asynchronous copy from pageable memory gives no such guarantee).
+constexpr int kChunkWords = 448;   // 3.5 KiB per launch, inside the kernel-argument limit
+struct WordChunk {
+    uint64_t w[kChunkWords];
+};
+
+__global__ __launch_bounds__(512) void words_write_kernel(WordChunk c, uint64_t *dst, int nwords) {
+    const int i = static_cast<int>(threadIdx.x);
+    if (i < nwords) dst[i] = c.w[i];
+}
+
 // Zero the lookback words and reset the control header.
 // When `slot` is non-null the single-image descriptor `one` is written there as well.
 __global__ void clear_kernel(uint64_t *state, long long nwords, BuildCtrl *ctrl, BuildDesc one, BuildDesc *slot) {
@@ -1803,6 +1816,22 @@ hipError_t launch_column_totals(int bpp, const void *img, int64_t H, int64_t W, 
                      : launch_totals_typed<uint8_t, false>(img, H, W, pitch, vec16, carry, carry_q, out, out_q, stream);
     return out_q ? launch_totals_typed<uint16_t, true>(img, H, W, pitch, vec16, carry, carry_q, out, out_q, stream)
                  : launch_totals_typed<uint16_t, false>(img, H, W, pitch, vec16, carry, carry_q, out, out_q, stream);
+}
+
+hipError_t upload_words(const void *src, size_t bytes, void *dst, hipStream_t stream) {
+    if (bytes % 8 || reinterpret_cast<uintptr_t>(dst) % 8) return hipErrorInvalidValue;
+    const uint64_t *w = static_cast<const uint64_t *>(src);
+    uint64_t *d = static_cast<uint64_t *>(dst);
+    const size_t n = bytes / 8;
+    for (size_t i = 0; i < n; i += kChunkWords) {
+        WordChunk c{};
+        const int k = static_cast<int>(n - i < static_cast<size_t>(kChunkWords) ? n - i : kChunkWords);
+        for (int j = 0; j < k; ++j) c.w[j] = w[i + j];
+        hipLaunchKernelGGL(words_write_kernel, dim3(1), dim3(512), 0, stream, c, d + i, k);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 int build_variant_count() { return kNumVariants; }

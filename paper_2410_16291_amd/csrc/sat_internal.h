@@ -70,6 +70,11 @@ hipError_t launch_build(int variant, int bpp, bool sq, const BuildDesc *descs, i
                         const BuildDesc *dev_descs, int64_t total_items, void *workspace,
                         int64_t state_words, hipStream_t stream);
 
+// Copy `bytes` (a multiple of 8) of host data to the 8-byte aligned device address `dst`, in
+// stream order, by kernels that take the data as by-value arguments: the host buffer may be
+// released as soon as the call returns, and nothing is staged through pageable memory.
+hipError_t upload_words(const void *src, size_t bytes, void *dst, hipStream_t stream);
+
 // Tables of pixel^1..pixel^np of one image (S, Q, T3, T4 of the descriptor) in one pass: the
 // helper-wave build with np lookback planes of nstrips * Wp words each (state_off: the first).
 constexpr int kPowBlockW = 256;   // block width (columns) of the power build

@@ -148,6 +148,24 @@ def test_multi_and_batch_validation(lib):
     assert b"item 1" in lib.sat_last_error()
 
 
+def test_batched_mean_std_workspace_keeps_the_control_header(lib):
+    """window_mean_std_batched puts its descriptor table after the 256-byte control header (whose
+    fault word sat_workspace_check reads), so it needs 256 bytes more than the table itself; the
+    batch workspace size covers both calls."""
+    n = 3
+    items = (BatchItem * n)()
+    for i in range(n):
+        b = 0x100000000 * (i + 1)
+        items[i].image, items[i].H, items[i].W, items[i].image_pitch = IMG + b, 100, 120, 128
+        items[i].sat, items[i].sat_sq, items[i].sat_pitch = SAT + b, SQ + b, 128
+        items[i].mean_out, items[i].std_out, items[i].out_pitch = OUT + b, OUT2 + b, 64
+    table = (n * 128 + 255) // 256 * 256                            # 128-byte descriptors
+    assert lib.window_mean_std_batched(items, n, 8, 8, 2, WS, table, None) == SAT_ERR_WORKSPACE
+    assert lib.window_mean_std_batched(items, n, 8, 8, 2, WS, 256 + table - 1, None) == SAT_ERR_WORKSPACE
+    assert lib.sat_batch_workspace_bytes(items, n, SAT_U16, 1) >= 256 + 256 * n
+    assert lib.window_mean_std_batched(items, n, 8, 8, 2, WS + 8, 4096, None) == SAT_ERR_ARG   # alignment
+
+
 def test_variants(lib):
     nb, ng = lib.sat_variant_count(0), lib.sat_variant_count(1)
     assert nb >= 5 and ng >= 3

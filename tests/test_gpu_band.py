@@ -189,22 +189,27 @@ def test_streamed_whole_table_u16_with_squares():
 
 
 @pytest.mark.slow
-def test_full_scale_eight_row_shards_of_70000x85000():
+def test_full_scale_eight_row_shards_of_70000x85000(capsys):
     """The bench image as eight shards of 8750 rows, each built as one GPU would build its share:
     its carry is the column totals of the rows above (sat_column_totals), its band build writes its
-    rows of the table and its totals.  The assembled table equals the one-call build everywhere;
-    every shard's totals and last table row match the oracle's totals chained over the shards."""
+    rows of the table and its totals.  Every row of the assembled table is compared with the
+    streamed oracle, band by band; every shard's totals match the oracle's totals chained over the
+    shards."""
+    import banded_compare
     H, W, n = 70000, 85000, 8
     dev = torch.device("cuda:0")
-    print("case: full scale shards, device mask", flush=True)
-    mask = synth.thomas_mask_device(H, W, 2, dev)
+
+    def say(msg):
+        with capsys.disabled():
+            print("full scale shards: " + msg, flush=True)
+
+    say("host mask")
+    img_np = synth.thomas_mask(H, W, seed=2)
     img = api.empty_image(H, W, torch.uint8, dev)          # the bench's layout: rows on 128-byte lines
-    img.copy_(mask)
-    del mask
+    img.copy_(torch.from_numpy(img_np))
     S = api.empty_table(H, W, dev)
     shard = H // n
-    need = max(api.build_workspace_bytes(rows, W, 1, False) for rows in (H, shard))
-    ws = torch.empty(need, dtype=torch.uint8, device=dev)
+    ws = torch.empty(api.build_workspace_bytes(shard, W, 1, False), dtype=torch.uint8, device=dev)
     totals = []
     for k in range(n):
         r0, r1 = k * shard, (k + 1) * shard
@@ -212,18 +217,13 @@ def test_full_scale_eight_row_shards_of_70000x85000():
         _, T = api.sat_build_band(img[r0:r1], carry=carry, rows_above=r0, sat=S[r0:r1], ws=ws)
         api.workspace_check(ws)
         totals.append(T)
-    one = api.empty_table(H, W, dev)
-    api.sat_build(img, sat=one, ws=ws)
-    api.workspace_check(ws)
-    print("case: full scale shards, against the one-call build", flush=True)
-    assert torch.equal(S.view(torch.int64), one.view(torch.int64))
-    del one
-    torch.cuda.empty_cache()
-    print("case: full scale shards, oracle totals", flush=True)
-    img_np = to_host(img)
+    del img, ws
+    torch.cuda.synchronize()
+    say("shards built; comparing every table row with the streamed oracle")
+    counts = banded_compare.compare(img_np, [], 1, table=lambda a, b: to_host(S[a:b]), progress=say)
+    assert counts["table_rows"] == H
     c = None
     for k in range(n):
         r0, r1 = k * shard, (k + 1) * shard
         c = oracle.column_totals(img_np[r0:r1], carry=c)
         assert np.array_equal(host_u64(totals[k]), c), k
-        assert np.array_equal(to_host(S[r1 - 1]), np.cumsum(c, dtype=np.uint64)), k

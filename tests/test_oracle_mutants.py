@@ -14,6 +14,7 @@ from oracle import build as oracle_build
 import test_oracle as pins
 import test_oracle_bands as bpins
 import test_oracle_moments as mpins
+import test_oracle_stream as spins
 
 SRC = oracle_build.SRC
 
@@ -45,6 +46,25 @@ MUTANTS = [
     ("column totals of squares add the pixel", "if (T2) T2[x] += v * v;", "if (T2) T2[x] += v;"),
     ("direct window powers skip the first power", "for (int j = 0; j < k; ++j) {\n                p *= v;\n                sums[j] += p;",
      "for (int j = 0; j < k; ++j) {\n                sums[j] += p;\n                p *= v;"),
+    ("resumed stream seeds the row above with the totals, not their running sum",
+     "run += carry[x];\n            above[x] = run;", "above[x] = carry[x];"),
+    ("resumed stream starts at the window straddling its first row",
+     "st->next_k[i] = (r0 + s - 1) / s;", "st->next_k[i] = r0 / s;"),
+    ("resumed stream drops the row above in the recurrence",
+     "run += st->squares ? v * v : v;\n            cur[x] = (up ? up[x] : 0) + run;",
+     "run += st->squares ? v * v : v;\n            cur[x] = run;"),
+    ("resumed stream squares use the pixel", "run += st->squares ? v * v : v;", "run += v;"),
+    ("resumed stream drops the top-left corner",
+     "uint64_t *o = outs[i] + emitted[i] * ow;\n            for (int64_t l = 0; l < ow; ++l) {\n"
+     "                int64_t x0 = l * s, x1 = x0 + w - 1;\n"
+     "                uint64_t b1 = bot[x1], b0 = x0 > 0 ? bot[x0 - 1] : 0;\n"
+     "                uint64_t t1 = top ? top[x1] : 0, t0 = (top && x0 > 0) ? top[x0 - 1] : 0;\n"
+     "                o[l] = b1 - t1 - b0 + t0;",
+     "uint64_t *o = outs[i] + emitted[i] * ow;\n            for (int64_t l = 0; l < ow; ++l) {\n"
+     "                int64_t x0 = l * s, x1 = x0 + w - 1;\n"
+     "                uint64_t b1 = bot[x1], b0 = x0 > 0 ? bot[x0 - 1] : 0;\n"
+     "                uint64_t t1 = top ? top[x1] : 0, t0 = (top && x0 > 0) ? top[x0 - 1] : 0;\n"
+     "                o[l] = b1 - t1 - b0;"),
 ]
 
 # The pins, called as plain functions with fixed arguments.
@@ -64,6 +84,9 @@ PIN_CALLS = [
     (bpins.test_column_totals_brute_force, ()),
     (bpins.test_column_totals_are_differences_of_the_last_table_row, (np.uint8,)),
     (bpins.test_band_rows_follow_from_the_band_and_the_totals_above, (np.uint16,)),
+    (spins.test_stream_from_any_row_matches_numpy, (np.uint16, True)),
+    (spins.test_partition_of_rows_covers_every_output_once, ()),
+    (spins.test_stream_wraps_mod_2_64_with_a_large_carry, ()),
 ]
 
 
