@@ -12,8 +12,9 @@ HBM; the timed region contains only the kernels.  Prints ONE JSON line.
 dominant kernel's algorithmic bytes over its average launch duration (HIP events around each
 launch, on the launch stream, inside the timed region) against the 8 TB/s HBM peak, and the HBM
 traffic rocprofv3 counted for that kernel when the committed counter summary was taken from the
-current kernel source.  `cpu_baseline` times the oracle (serial C, one core) on a bounded band of
-the same image and scales it to the same unit.
+current kernel source.  `cpu_baseline` times the oracle on a bounded band of rows of the same
+image on all host cores (and on one core), beside a multi-core OpenMP baseline, scaled to the same
+unit.
 """
 import argparse
 import hashlib
@@ -99,35 +100,123 @@ def committed_traffic(H, W):
     return float(m_val.group(1))
 
 
+def host_cpu():
+    """(CPU model name, logical CPUs this process may run on)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return model, n
+
+
 def cpu_baseline(H, W, seconds_target):
-    """The oracle (serial C) on the first rows of the same image: table + the three windows."""
+    """The oracle on the first rows of the same image (table + the three windows), timed three ways
+    on the host: the oracle on all host cores (the sample's rows in parts, each part streamed by the
+    oracle from the column totals of the rows above it, one thread per part), the oracle on one
+    core, and the multi-core OpenMP baseline (row-band table build, then the window sums)."""
+    from concurrent.futures import ThreadPoolExecutor
+
     import numpy as np
 
+    import cpu_baseline as omp
     import oracle
     from paper_2410_16291_amd import synth
 
+    model, ncpu = host_cpu()
+    threads = max(1, min(ncpu, int(os.environ.get("OMP_NUM_THREADS", ncpu) or ncpu)))
     ys, xs = synth.thomas_points(H, W, seed=2)
+    hmax = max(WINDOWS)
+    wins = [(h, h) for h in WINDOWS]
 
-    def run(R):
-        slab = np.zeros((R, W), np.uint8)
+    def slab(R):
+        a = np.zeros((R, W), np.uint8)
         keep = ys < R
-        slab[ys[keep], xs[keep]] = 1
+        a[ys[keep], xs[keep]] = 1
+        return a
+
+    def one_core(img):
         t0 = time.perf_counter()
-        S = oracle.sat(slab)
+        S = oracle.sat(img)
         for h in WINDOWS:
-            if h <= R:
+            if h <= img.shape[0]:
                 oracle.window_sum_sat(S, h, h, 1)
         return time.perf_counter() - t0
 
-    R = 1024
-    t = run(R)
-    R2 = int(min(H, max(1024, R * seconds_target / max(t, 1e-3))))
-    R2 = max(R2, 2 * max(WINDOWS))
-    t2 = run(R2)
-    return {"value": round(R2 * W / t2 / 1e9, 5), "unit": "Gpix/s", "cores": 1, "kind": "oracle",
-            "sample": "rows 0..%d of the %dx%d image (%.1f Mpx): serial table build + window sums %s "
-                      "by corner lookup, uint64, one thread, %.1f s" % (R2 - 1, H, W, R2 * W / 1e6,
-                                                                       "/".join(map(str, WINDOWS)), t2)}
+    def all_cores(img, parts):
+        """The oracle's own stream, started at each part's first row from the column totals of the
+        rows above (oracle.column_totals), every output row of each part's windows emitted."""
+        R = img.shape[0]
+        bounds = [R * i // parts for i in range(parts + 1)]
+        segs = list(zip(bounds[:-1], bounds[1:]))
+        t0 = time.perf_counter()
+        with ThreadPoolExecutor(parts) as ex:
+            totals = list(ex.map(lambda ab: oracle.column_totals(img[ab[0]:ab[1]]), segs))
+        carries, run = [], np.zeros(W, np.uint64)
+        for t in totals:
+            carries.append(run.copy())
+            run = run + t
+
+        def part(i):
+            a, b = segs[i]
+            st = oracle.Stream(img, wins, 1, r0=a, carry=carries[i] if a else None)
+            end, cur = min(R, b + hmax - 1), a
+            while cur < end:
+                cur = min(end, cur + 512)
+                st.next(cur, want_sat=False)
+            st.close()
+
+        with ThreadPoolExecutor(parts) as ex:
+            list(ex.map(part, range(len(segs))))
+        return time.perf_counter() - t0
+
+    def openmp(img, S, outs):
+        t0 = time.perf_counter()
+        _, n = omp.sat_u8(img, threads, out=S)
+        for h, o in zip(WINDOWS, outs):
+            omp.window_sum_u32(S, h, h, 1, threads, out=o)
+        return time.perf_counter() - t0, n
+
+    share = seconds_target / 3.0
+    # one core: scale a 1024-row trial to the time share
+    t = one_core(slab(1024))
+    R1 = int(min(H, max(2 * hmax, 1024 * share / max(t, 1e-3))))
+    t1 = one_core(slab(R1))
+    # all cores: parts of at least 4 * hmax rows so the rows each part re-reads below it stay small
+    R = int(min(H, max(threads * 4 * hmax, 16384)))
+    img = slab(R)
+    t = all_cores(img, threads)
+    reps = max(1, int(share / max(t, 1e-3)))
+    tp = min(all_cores(img, threads) for _ in range(reps))
+    # OpenMP: the same sample, buffers reused (the first run touches their pages)
+    Ro = min(R, 8192)
+    imgo = np.ascontiguousarray(img[:Ro])
+    S = np.empty((Ro, W), np.uint64)
+    outs = [np.empty((Ro - h + 1, W - h + 1), np.uint32) for h in WINDOWS]
+    t, n_omp = openmp(imgo, S, outs)
+    reps = max(1, int(share / max(t, 1e-3)))
+    to = min(openmp(imgo, S, outs)[0] for _ in range(reps))
+    return {"value": round(R * W / tp / 1e9, 5), "unit": "Gpix/s", "cores": threads, "kind": "oracle",
+            "sample": "rows 0..%d of the %dx%d image (%.1f Mpx) in %d parts, one thread each: the serial "
+                      "oracle's streamed table and the window sums %s by corner lookup (uint64) from the "
+                      "oracle's column totals of the rows above each part; best of %d runs, %.2f s" %
+                      (R - 1, H, W, R * W / 1e6, threads, "/".join(map(str, WINDOWS)), reps, tp),
+            "cpu_model": model, "host_cpus": ncpu,
+            "one_core": {"value": round(R1 * W / t1 / 1e9, 5), "cores": 1, "kind": "oracle",
+                         "sample": "rows 0..%d (%.1f Mpx): serial table build + the three window sums, "
+                                   "one thread, %.1f s" % (R1 - 1, R1 * W / 1e6, t1)},
+            "openmp": {"value": round(Ro * W / to / 1e9, 5), "cores": n_omp, "kind": "openmp",
+                       "sample": "rows 0..%d (%.1f Mpx): row-band table build on %d threads, then the "
+                                 "three uint32 window sums, buffers reused; best of %d runs, %.3f s" %
+                                 (Ro - 1, Ro * W / 1e6, n_omp, reps, to)}}
 
 
 def batched_section(torch, dev, n_images):
