@@ -25,7 +25,8 @@
  *     most 2^31-1 rows.  Tables are uint64_t, row-major, pitch in
  *     elements.  Outputs are row-major with a pitch in elements.
  *   - Every data pointer (image, tables, outputs, workspace) is a DEVICE pointer owned by the
- *     caller; the library never allocates, frees or keeps device memory.
+ *     caller; the library never allocates or frees device memory.  The one piece it keeps is the
+ *     fixed scratch array of sat_build_noalloc, part of its code object on each device.
  *   - Every compute call is asynchronous on `stream` (a hipStream_t passed as void*; NULL is the
  *     default stream).  Results are valid once the stream has been synchronised.
  *   - Arguments are validated completely, on the host, before any HIP call.  On any error the
@@ -96,6 +97,22 @@ size_t sat_build_workspace_bytes(int64_t H, int64_t W, sat_dtype pixel_type, int
 sat_status sat_build(const void *image, sat_dtype pixel_type, int64_t H, int64_t W,
                      int64_t image_pitch, uint64_t *sat, uint64_t *sat_sq, int64_t sat_pitch,
                      void *workspace, size_t workspace_bytes, void *stream);
+
+/* sat_build for callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the same table, from the same kernels, with
+ * the workspace taken from a fixed scratch array inside the library (128 MiB per device, held
+ * from the first call on a device until the process ends) instead of an argument.  The caller
+ * still passes the image and the tables.  The call allocates and frees nothing.
+ * Builds whose sat_build_workspace_bytes(H, W, pixel_type, sat_sq != NULL) exceeds 128 MiB (e.g.
+ * 8-bit images beyond about 16000 x 16000, or 16-bit ones with squares beyond about 11500 x 11500)
+ * are refused with SAT_ERR_WORKSPACE before anything is enqueued.  Every call on one device uses
+ * that device's one scratch array: calls that overlap on a device (two streams, or two threads)
+ * race and may corrupt each other's tables; calls in order on one stream are safe.  The scratch
+ * array lives on the device of `stream` (the current device for NULL).  Other arguments and
+ * errors as sat_build. */
+sat_status sat_build_noalloc(const void *image, sat_dtype pixel_type, int64_t H, int64_t W,
+                             int64_t image_pitch, uint64_t *sat, uint64_t *sat_sq, int64_t sat_pitch,
+                             void *stream);
 
 /* ---- Bands of a taller image.  The integral image is a prefix sum down the columns of the
  * row-wise prefix sums (Sec. II-B), so the table rows of a band of image rows r0 .. r0+H-1 follow

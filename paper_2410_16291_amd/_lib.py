@@ -54,6 +54,7 @@ def load(path: str = LIB_PATH):
             "window_out_shape": (_st, [_i64, _i64, _i64, _i64, _i64, _p, _p]),
             "sat_build_workspace_bytes": (_sz, [_i64, _i64, ctypes.c_int, ctypes.c_int]),
             "sat_build": (_st, [_p, ctypes.c_int, _i64, _i64, _i64, _p, _p, _i64, _p, _sz, _p]),
+            "sat_build_noalloc": (_st, [_p, ctypes.c_int, _i64, _i64, _i64, _p, _p, _i64, _p]),
             "sat_build_band": (_st, [_p, ctypes.c_int, _i64, _i64, _i64, _p, _p, _i64, _p, _p, _i64, _p, _p, _p,
                                      _sz, _p]),
             "sat_column_totals": (_st, [_p, ctypes.c_int, _i64, _i64, _i64, _p, _p, _p, _p, _p]),

@@ -454,6 +454,23 @@ sat_status sat_build(const void *image, sat_dtype pixel_type, int64_t H, int64_t
                      nullptr, workspace, workspace_bytes, stream, "sat_build");
 }
 
+sat_status sat_build_noalloc(const void *image, sat_dtype pixel_type, int64_t H, int64_t W, int64_t image_pitch,
+                             uint64_t *sat, uint64_t *sat_sq, int64_t sat_pitch, void *stream) {
+    const char *who = "sat_build_noalloc";
+    sat_status st = validate_build_item(image, pixel_type, H, W, image_pitch, sat, sat_sq, sat_pitch, who);
+    if (st) return st;
+    const size_t need = sat_build_workspace_bytes(H, W, pixel_type, sat_sq != nullptr);
+    if (need == 0 || need > satk::kNoAllocScratchBytes)
+        return fail(SAT_ERR_WORKSPACE, "%s: a %lld x %lld build%s needs %zu bytes of scratch, above the library's "
+                    "fixed %zu; call sat_build with a workspace", who, (long long)H, (long long)W,
+                    sat_sq ? " with squares" : "", need, satk::kNoAllocScratchBytes);
+    void *ws = nullptr;
+    const hipError_t e = satk::noalloc_scratch(static_cast<hipStream_t>(stream), &ws);
+    if (e != hipSuccess) return hip_fail(e, who);
+    return build_one(image, pixel_type, H, W, image_pitch, nullptr, nullptr, 0, sat, sat_sq, sat_pitch, nullptr,
+                     nullptr, ws, satk::kNoAllocScratchBytes, stream, who);
+}
+
 sat_status sat_build_band(const void *image, sat_dtype pixel_type, int64_t H, int64_t W, int64_t image_pitch,
                           const uint64_t *carry, const uint64_t *carry_sq, int64_t rows_above, uint64_t *sat,
                           uint64_t *sat_sq, int64_t sat_pitch, uint64_t *total_out, uint64_t *total_sq_out,

@@ -41,6 +41,7 @@
 // overflow for a block (BW * 65535 < 2^32); the 64-bit carries are added once per pixel.
 #include "sat_internal.h"
 
+#include <mutex>
 #include <type_traits>
 
 namespace satk {
@@ -1816,6 +1817,46 @@ hipError_t launch_column_totals(int bpp, const void *img, int64_t H, int64_t W, 
                      : launch_totals_typed<uint8_t, false>(img, H, W, pitch, vec16, carry, carry_q, out, out_q, stream);
     return out_q ? launch_totals_typed<uint16_t, true>(img, H, W, pitch, vec16, carry, carry_q, out, out_q, stream)
                  : launch_totals_typed<uint16_t, false>(img, H, W, pitch, vec16, carry, carry_q, out, out_q, stream);
+}
+
+}  // namespace satk
+
+// Workspace of sat_build_noalloc: lookback words and the control header of one build at a time per
+// device.  Host code never passes this name to a kernel or a copy (on the host it stands for the
+// symbol, not for device memory): it takes the device address from hipGetSymbolAddress below.
+static __device__ __align__(256) unsigned char scratch[satk::kNoAllocScratchBytes];
+
+namespace satk {
+
+hipError_t noalloc_scratch(hipStream_t stream, void **ptr) {
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static void *addr[kMaxDevices] = {};
+    int cur = 0, dev = 0;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    dev = cur;
+    if (stream) {
+        hipDevice_t sd;
+        if ((e = hipStreamGetDevice(stream, &sd)) != hipSuccess) return e;
+        dev = static_cast<int>(sd);
+    }
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        // the symbol's address on `dev`: looked up with that device current
+        if (dev != cur && (e = hipSetDevice(dev)) != hipSuccess) return e;
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (dev != cur) {
+            const hipError_t r = hipSetDevice(cur);
+            if (e == hipSuccess) e = r;
+        }
+        if (e != hipSuccess) return e;
+        addr[dev] = p;
+    }
+    *ptr = addr[dev];
+    return hipSuccess;
 }
 
 hipError_t upload_words(const void *src, size_t bytes, void *dst, hipStream_t stream) {

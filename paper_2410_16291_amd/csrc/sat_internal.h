@@ -70,6 +70,13 @@ hipError_t launch_build(int variant, int bpp, bool sq, const BuildDesc *descs, i
                         const BuildDesc *dev_descs, int64_t total_items, void *workspace,
                         int64_t state_words, hipStream_t stream);
 
+// The library's own device scratch for callers that cannot allocate (sat_build_noalloc): a
+// fixed array in the code object, one copy per device.  noalloc_scratch returns the address of
+// the copy on the device `stream` belongs to (the current device for the null stream), looked up
+// once per device with that device current and kept; it allocates nothing.
+constexpr size_t kNoAllocScratchBytes = size_t(128) << 20;
+hipError_t noalloc_scratch(hipStream_t stream, void **ptr);
+
 // Copy `bytes` (a multiple of 8) of host data to the 8-byte aligned device address `dst`, in
 // stream order, by kernels that take the data as by-value arguments: the host buffer may be
 // released as soon as the call returns, and nothing is staged through pageable memory.

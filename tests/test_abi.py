@@ -89,6 +89,31 @@ def test_sat_build_validation(lib):
         SAT_ERR_OVERFLOW, SAT_ERR_ARG)
 
 
+def test_sat_build_noalloc_validation(lib):
+    """The entry point without a workspace argument: argument errors as sat_build, and builds whose
+    workspace would exceed the library's fixed 128 MiB scratch are refused, all before any HIP
+    call (so these run without a GPU)."""
+    def nb(image=IMG, ptype=SAT_U8, H=64, W=80, ipitch=80, sat=SAT, sat_sq=None, spitch=80):
+        return lib.sat_build_noalloc(image, ptype, H, W, ipitch, sat, sat_sq, spitch, None)
+    assert nb(image=None) == SAT_ERR_ARG
+    assert nb(sat=None) == SAT_ERR_ARG
+    assert nb(ptype=SAT_U64) == SAT_ERR_ARG
+    assert nb(H=0) == SAT_ERR_ARG
+    assert nb(ipitch=79) == SAT_ERR_ARG
+    assert nb(sat_sq=SAT) == SAT_ERR_ARG
+    assert nb(sat=IMG + 16) == SAT_ERR_ARG
+    limit = 128 << 20
+    # the largest square 8-bit image whose workspace fits, and the next size up that does not
+    for ptype, sq in ((SAT_U8, 0), (SAT_U16, 1)):
+        fits = [n for n in range(8000, 17000, 100) if lib.sat_build_workspace_bytes(n, n, ptype, sq) <= limit]
+        assert fits, ptype
+        big = max(fits) + 100
+        assert lib.sat_build_workspace_bytes(big, big, ptype, sq) > limit
+        assert nb(ptype=ptype, H=big, W=big, ipitch=big, spitch=big, sat_sq=SQ if sq else None) == SAT_ERR_WORKSPACE
+        assert b"scratch" in lib.sat_last_error()
+    assert lib.sat_build_workspace_bytes(8192, 8192, SAT_U16, 1) <= limit     # 8192^2 16-bit with squares fits
+
+
 def test_window_sum_validation(lib):
     def call(sat=SAT, ptype=SAT_U8, H=100, W=120, sp=120, h=10, w=10, s=1, out=OUT, ot=SAT_U32, op=111):
         return lib.window_sum(sat, ptype, H, W, sp, h, w, s, out, ot, op, None)
