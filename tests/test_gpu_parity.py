@@ -443,9 +443,46 @@ def test_device_generator_through_the_path():
 
 # ------------------------------------------------------------------ serving
 
+def check_served_against_oracle(srv, label):
+    """Every query answered in the mix equals the same query run alone on a fresh table and the
+    oracle's result for it: sums bit-exact, mean bit-exact, std within 1e-12 (the masks are 0/1,
+    so the table of squares is the table itself)."""
+    from paper_2410_16291_amd import serve
+    gpu_tables, ref_tables = {}, {}
+    n_sum = n_stats = 0
+    for j in srv.done:
+        if j.req.kind != "query":
+            continue
+        iid = serve.image_id(j.req)
+        b = srv.builds[iid]
+        if iid not in gpu_tables:
+            gpu_tables[iid] = api.sat_build(synth.thomas_mask_device(b.H, b.W, b.image_seed, "cuda:0"))
+            ref_tables[iid] = oracle.sat(synth.thomas_mask(b.H, b.W, seed=b.image_seed))
+        S, ref_S = gpu_tables[iid], ref_tables[iid]
+        h, w, st = min(j.req.win_h, b.H), min(j.req.win_w, b.W), j.req.stride
+        sums = oracle.window_sum_sat(ref_S, h, w, st)
+        if j.req.op == "sum":
+            alone = api.window_sum(S, h, w, st, pixel_type="u8")
+            got = to_host(j.result)
+            assert np.array_equal(to_host(alone), got), (label, j.idx)
+            assert np.array_equal(got.astype(np.uint64), sums), (label, j.idx)
+            n_sum += 1
+        else:
+            alone = api.window_mean_std(S, S, h, w, st)
+            for a, g in zip(alone, j.result):
+                assert np.array_equal(to_host(a), to_host(g)), (label, j.idx)
+            ref_mean, ref_std = oracle.mean_std(sums, sums, h * w)
+            g_sum, g_mean, g_std = (to_host(t) for t in j.result)
+            assert np.array_equal(g_sum, sums), (label, j.idx)
+            assert np.array_equal(g_mean, ref_mean), (label, j.idx)
+            check_std(g_std, ref_std)
+            n_stats += 1
+    return n_sum, n_stats
+
+
 def test_serving_results_same_alone_and_in_mix():
     """Requests served concurrently (4 streams, evictions under a tight budget) give exactly the
-    results of the same requests run alone, one at a time; some are checked against the oracle."""
+    results of the same requests run alone, one at a time, and the oracle's, for every query."""
     import time
     from paper_2410_16291_amd import serve
     reqs = synth.request_stream(rate=300.0, duration=0.5, seed=22, side_lo=200, side_hi=1200,
@@ -456,30 +493,30 @@ def test_serving_results_same_alone_and_in_mix():
     torch.cuda.synchronize()
     print("case: serving", rep.as_dict(), flush=True)
     assert rep.n == len(reqs) and rep.max_in_flight > 1 and rep.peak_bytes <= 40e6
-    tables = {}
-    checked = 0
-    for j in srv.done:
-        if j.req.kind != "query":
-            continue
-        iid = serve.image_id(j.req)
-        b = srv.builds[iid]
-        if iid not in tables:
-            tables[iid] = api.sat_build(synth.thomas_mask_device(b.H, b.W, b.image_seed, "cuda:0"))
-        S = tables[iid]
-        h, w = min(j.req.win_h, b.H), min(j.req.win_w, b.W)
-        if j.req.op == "sum":
-            alone = api.window_sum(S, h, w, j.req.stride, pixel_type="u8")
-            assert np.array_equal(to_host(alone), to_host(j.result)), j.idx
-            if checked < 4:
-                ref = oracle.window_sum_direct(synth.thomas_mask(b.H, b.W, seed=b.image_seed), h, w, j.req.stride)
-                assert np.array_equal(to_host(alone).astype(np.uint64), ref), j.idx
-                checked += 1
-        else:
-            got = j.result
-            alone = api.window_mean_std(S, S, h, w, j.req.stride)
-            for a, g in zip(alone, got):
-                assert np.array_equal(to_host(a), to_host(g)), j.idx
-    assert checked > 0
+    n_sum, n_stats = check_served_against_oracle(srv, "small")
+    assert n_sum > 10 and n_stats > 3
+
+
+@pytest.mark.slow
+def test_serving_full_size_images_every_query():
+    """The serving workload's own sizes: 8-bit cluster masks with sides on 2000..16000 (builds on
+    128-byte row lines, taking the helper-wave plans), windows 16..512 at strides 1..8, a quarter
+    of them mean/std, under a budget that forces evictions and rebuilds.  Every query in the mix is
+    compared with the same query alone and with the oracle."""
+    import time
+    from paper_2410_16291_amd import serve
+    reqs = synth.request_stream(rate=60.0, duration=0.6, seed=31)
+    builds = [r for r in reqs if r.kind == "build"]
+    assert max(max(r.H, r.W) for r in builds) > 14000 and min(min(r.H, r.W) for r in builds) < 2500
+    ex = serve.GpuExecutor("cuda:0", slots=4)
+    srv = serve.Server(ex, budget_bytes=3e9, slots=4, keep_results=True)
+    rep = srv.run(reqs, idle=lambda: time.sleep(2e-5))
+    torch.cuda.synchronize()
+    print("case: serving full size", rep.as_dict(), flush=True)
+    assert rep.n == len(reqs) and rep.max_in_flight > 1 and rep.peak_bytes <= 3e9
+    assert rep.evictions > 0
+    n_sum, n_stats = check_served_against_oracle(srv, "full size")
+    assert n_sum + n_stats == len(reqs) - len(builds) and n_stats >= 5
 
 
 # ------------------------------------------------------------------ full size
