@@ -194,7 +194,7 @@ def cpu_baseline(H, W, seconds_target):
     R = int(min(H, max(threads * 4 * hmax, 16384)))
     img = slab(R)
     t = all_cores(img, threads)
-    reps = max(1, int(share / max(t, 1e-3)))
+    reps = max(1, min(5, int(share / max(t, 1e-3))))
     tp = min(all_cores(img, threads) for _ in range(reps))
     # OpenMP: the same sample, buffers reused (the first run touches their pages)
     Ro = min(R, 8192)
@@ -202,7 +202,7 @@ def cpu_baseline(H, W, seconds_target):
     S = np.empty((Ro, W), np.uint64)
     outs = [np.empty((Ro - h + 1, W - h + 1), np.uint32) for h in WINDOWS]
     t, n_omp = openmp(imgo, S, outs)
-    reps = max(1, int(share / max(t, 1e-3)))
+    reps = max(1, min(5, int(share / max(t, 1e-3))))
     to = min(openmp(imgo, S, outs)[0] for _ in range(reps))
     return {"value": round(R * W / tp / 1e9, 5), "unit": "Gpix/s", "cores": threads, "kind": "oracle",
             "sample": "rows 0..%d of the %dx%d image (%.1f Mpx) in %d parts, one thread each: the serial "

@@ -121,6 +121,12 @@ constexpr int kVarNtPx4 = 9;        // lookback, non-temporal stores, 4 pixels p
 constexpr int kVarHelperPx4 = 10;   // helper wave (DMA tiles, lookback a block ahead), 4 pixels per lane
 constexpr int kVarHelperPx8 = 11;   // helper wave, 8 pixels per lane, 48-row strips
 constexpr int kVarShort = 2;        // lookback, 32-row strips
+constexpr int kVarHelper3Px4 = 12;  // helper wave, lookback only (column sums on the compute waves), 4 pixels per lane
+constexpr int kVarHelper3Px8 = 13;  // the same, 8 pixels per lane, 48-row strips
+
+bool helper_variant(int v) {
+    return v == kVarHelperPx4 || v == kVarHelperPx8 || v == kVarHelper3Px4 || v == kVarHelper3Px8;
+}
 
 // Row alignment class of an image: 16 when every row start allows 16-byte loads, 4 when it
 // allows 4-byte loads, else 1.  The helper wave's LDS DMA needs 4; below 16 it moves a dword
@@ -167,7 +173,7 @@ int helper_strip_h(int v, int64_t H, int bpp, bool sq) {
     const int64_t ncu = device_cus();
     const int64_t cap = satk::build_variant_capacity(v, bpp, sq);
     const int th = satk::build_variant(v).th();
-    if (v == kVarHelperPx8) {
+    if (v == kVarHelperPx8 || v == kVarHelper3Px8) {
         if (4 * ((H + th - 1) / th) <= ncu) return th / 2;
         return balanced_strip_h(H, th, cap);
     }
@@ -183,6 +189,15 @@ BuildPlan helper_plan(int64_t H, int64_t W, int bpp, bool sq) {
         const int64_t n48 = (H + 47) / 48, n64 = (H + 63) / 64;
         v = (n48 > ncu && n64 <= ncu) ? kVarHelperPx4 : kVarHelperPx8;
     }
+    // The three-stage helper pipeline (column sums on the compute waves, the helper's lookback
+    // overlapping their block) shortens each block where the helper's path sets the pace, at the
+    // cost of a third tile buffer (one workgroup per CU for 8-bit 512-column tiles).  Measured
+    // (ms, two-stage -> three-stage): 8192^2 u16 with squares 0.346 -> 0.311, 12000^2 0.712 ->
+    // 0.682, 16000^2 u8 0.594 -> 0.552, 2000 x 16000 u8 0.255 -> 0.227, 20000^2 u8 0.969 -> 0.928;
+    // rows of 85000 pixels (166 blocks per strip) kept the two-stage pipeline: 8750 rows 1.709 vs
+    // 1.740, 70000 rows 11.27 vs 11.77.
+    const int v3 = v == kVarHelperPx4 ? kVarHelper3Px4 : kVarHelper3Px8;
+    if (W <= 32768 && satk::build_variant_capacity(v3, bpp, sq) > 0) v = v3;
     return {v, helper_strip_h(v, H, bpp, sq)};
 }
 
@@ -210,7 +225,7 @@ int choose_build_variant(int64_t total_rows, int64_t W, int n_images, int bpp, b
 int choose_strip_h(int v, int64_t H, int bpp, bool sq, int align) {
     const satk::BuildVariant &var = satk::build_variant(v);
     if (!satk::build_variant_adaptive(v)) return var.th();
-    if (align == 16 && (v == kVarHelperPx4 || v == kVarHelperPx8)) return helper_strip_h(v, H, bpp, sq);
+    if (align == 16 && helper_variant(v)) return helper_strip_h(v, H, bpp, sq);
     const int64_t cap = satk::build_variant_capacity(v, bpp, sq);
     // Few strips (at most half the resident workgroups): 32-row strips, twice as many, all in one
     // round.  Measured at 4096-12000 rows: 3-11 % faster than 64-row strips; 16- and 24-row strips

@@ -30,15 +30,16 @@
 //             same code also runs in a reduce-then-scan mode (an ablation): one kernel writes the
 //             strip column totals, a second scans them down each column, and the strip kernel
 //             then reads its totals instead of looking back.
-//   Build2    four compute waves and a helper wave that stages the next tile by LDS DMA, forms
-//             its column sums and runs its lookback one block ahead, so that the lookback's
-//             memory round trip is never on the compute waves' path.
+//   Build2    four compute waves and a helper wave that stages tiles by LDS DMA and runs the
+//             lookback ahead of the compute waves, so that the lookback's memory round trip is
+//             never on their path (two pipelines, see the struct).
 //   BuildPow  Build2 for the tables of pixel^1..pixel^k (k lookback planes, one pass over the
 //             LDS tile per power).
 //
 // Per-row work: the 64 lanes of a wave scan a row of BW pixels with DPP (row_shr 1/2/4/8 within
 // rows of 16 lanes, then row_bcast 15 and 31 across them) in 32-bit integers, which cannot
-// overflow for a block (BW * 65535 < 2^32); the 64-bit carries are added once per pixel.
+// overflow for a block (BW * 65535 < 2^32; squares of 16-bit pixels are scanned as their two
+// 16-bit halves); the 64-bit carries are added once per pixel.
 #include "sat_internal.h"
 
 #include <mutex>
@@ -155,6 +156,135 @@ __device__ __forceinline__ void store16_rsrc(u32x4 data, i32x4 rsrc, uint32_t vo
                      : "memory");
 }
 
+// LDS-only workgroup barrier: orders LDS accesses between the waves of a workgroup and leaves
+// each wave's global stores in flight.  (A full __syncthreads() makes every wave wait until its
+// table stores have reached memory before the barrier: on gfx9 the vector memory counter covers
+// stores too, so each block of a strip would end in a drain of its stores.)
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// ------------------------------------------------------------------ rows of one table block
+//
+// A wave's rows of one block of one table: for every row, the lane's pixel pair of each 128-column
+// sub-block (or their squares), a DPP scan of pair sums across the wave, the row's left carry and
+// the running column sums down the wave's rows, then one 16-byte store per lane (contiguous
+// across the wave).  Rows are taken G at a time: their LDS reads go out together and their G
+// scans are independent, so one wave keeps G dependency chains in flight instead of one (with one
+// or two waves per SIMD nothing else hides the DPP and LDS latencies).  The running column sums
+// are then advanced row by row, in order.
+
+// Inclusive scan across the wave of the pair sums a0 + a1, exact in 64 bits.  WIDE (pixel values
+// up to 2^32 - 1, the squares of 16-bit pixels): both halves of each value (bits 0-15 and 16-31)
+// are scanned as separate 32-bit sums, each at most 128 * 65535 < 2^32, and recombined.
+template <bool WIDE>
+__device__ __forceinline__ void scan_pair(uint32_t a0, uint32_t a1, uint64_t &pair, uint64_t &incl) {
+    if constexpr (WIDE) {
+        const uint32_t lo = (a0 & 0xffffu) + (a1 & 0xffffu);
+        const uint32_t hi = (a0 >> 16) + (a1 >> 16);
+        const uint32_t slo = wave_scan(lo);
+        const uint32_t shi = wave_scan(hi);
+        pair = static_cast<uint64_t>(a0) + a1;
+        incl = (static_cast<uint64_t>(shi) << 16) + slo;
+    } else {
+        const uint32_t p = a0 + a1;
+        pair = p;
+        incl = wave_scan(p);
+    }
+}
+
+// G rows starting at wave row r0 (all valid).  trow: the lane's pixel pair of sub-block 0 of the
+// wave's first row in the LDS tile (rows BW pixels apart).
+template <typename T, int PX, int G, bool SQUARE, bool WIDE, bool VEC, bool NTS>
+__device__ __forceinline__ void row_group(const T *trow, int r0, int lane, const uint64_t (&u)[PX],
+                                          uint64_t (&acc)[PX], uint64_t lcarry, uint64_t &tvec, const i32x4 &rs_blk,
+                                          const char *blk0, uint32_t row_recs, uint32_t pitch_bytes) {
+    constexpr int NS = PX / 2, BW = 64 * PX;
+    uint32_t pv[G][NS];
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int sb = 0; sb < NS; ++sb) {
+            const T *src = trow + (r0 + g) * BW + 128 * sb;
+            if (sizeof(T) == 1) pv[g][sb] = *reinterpret_cast<const uint16_t *>(src);
+            else pv[g][sb] = *reinterpret_cast<const uint32_t *>(src);
+        }
+    uint64_t base[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) base[g] = readlane(lcarry, r0 + g);
+#pragma unroll
+    for (int sb = 0; sb < NS; ++sb) {
+        uint32_t a0[G], a1[G];
+        uint64_t pair[G], incl[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const uint32_t v0 = sizeof(T) == 1 ? (pv[g][sb] & 0xffu) : (pv[g][sb] & 0xffffu);
+            const uint32_t v1 = sizeof(T) == 1 ? ((pv[g][sb] >> 8) & 0xffu) : (pv[g][sb] >> 16);
+            a0[g] = SQUARE ? v0 * v0 : v0;
+            a1[g] = SQUARE ? v1 * v1 : v1;
+            scan_pair<WIDE>(a0[g], a1[g], pair[g], incl[g]);
+        }
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const uint64_t b = base[g] + (incl[g] - pair[g]);
+            acc[2 * sb] += b + a0[g];
+            acc[2 * sb + 1] += b + pair[g];
+            const uint64_t o0 = u[2 * sb] + acc[2 * sb], o1 = u[2 * sb + 1] + acc[2 * sb + 1];
+            const uint32_t roff = static_cast<uint32_t>(r0 + g) * pitch_bytes;
+            if (VEC) {
+                store16_rsrc<NTS>(u32x4{static_cast<uint32_t>(o0), static_cast<uint32_t>(o0 >> 32),
+                                        static_cast<uint32_t>(o1), static_cast<uint32_t>(o1 >> 32)},
+                                  rs_blk, static_cast<uint32_t>(lane) * 16 + sb * 1024, roff);
+            } else {
+                const __amdgpu_buffer_rsrc_t rs_row = __builtin_amdgcn_make_buffer_rsrc(
+                    const_cast<char *>(blk0 + roff), 0, static_cast<int>(row_recs), kRsrcWord3);
+                const uint32_t voff = static_cast<uint32_t>(lane) * 16 + sb * 1024;
+                __builtin_amdgcn_raw_buffer_store_b64(u32x2{static_cast<uint32_t>(o0), static_cast<uint32_t>(o0 >> 32)},
+                                                      rs_row, voff, 0, NTS ? 2 : 0);
+                __builtin_amdgcn_raw_buffer_store_b64(u32x2{static_cast<uint32_t>(o1), static_cast<uint32_t>(o1 >> 32)},
+                                                      rs_row, voff + 8, 0, NTS ? 2 : 0);
+            }
+            base[g] += readlane(incl[g], 63);
+        }
+    }
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+        if (lane == r0 + g) tvec = base[g] - readlane(lcarry, r0 + g);
+}
+
+// All rows_ok rows of the wave for one table of one block; returns the row totals of the block
+// (lane r holds row r's) to add to the left carries.  Stores go through buffer resources so that
+// the hardware range check, not a branch per row, drops what lies outside the image:
+//   VEC (block wholly inside the image width, 16-byte aligned table rows): one resource spanning
+//     the wave's rows from the block start, records ending at the last valid row's width; row r
+//     is addressed by the scalar offset r * pitch;
+//   ragged: one resource per row covering exactly [block start, W) of that row, 8-byte stores.
+template <typename T, int PX, bool SQUARE, bool WIDE, bool VEC, bool NTS>
+__device__ __forceinline__ uint64_t block_rows(const T *trow, int lane, const uint64_t (&u)[PX], uint64_t lcarry,
+                                               uint64_t *blk0, int rows_ok, uint32_t row_recs, uint32_t pitch_bytes) {
+    constexpr int G = 4;
+    uint64_t acc[PX];
+#pragma unroll
+    for (int p = 0; p < PX; ++p) acc[p] = 0;
+    uint64_t tvec = 0;
+    const int nvalid = rows_ok > 0 ? rows_ok : 0;
+    const uint32_t blk_recs = nvalid > 0 ? (nvalid - 1) * pitch_bytes + row_recs : 0;
+    const i32x4 rs_blk = make_rsrc(blk0, VEC ? blk_recs : 0);
+    const char *b0 = reinterpret_cast<const char *>(blk0);
+    int r = 0;
+#pragma unroll 1
+    for (; r + G <= nvalid; r += G)
+        row_group<T, PX, G, SQUARE, WIDE, VEC, NTS>(trow, r, lane, u, acc, lcarry, tvec, rs_blk, b0, row_recs,
+                                                    pitch_bytes);
+#pragma unroll 1
+    for (; r < nvalid; ++r)
+        row_group<T, PX, 1, SQUARE, WIDE, VEC, NTS>(trow, r, lane, u, acc, lcarry, tvec, rs_blk, b0, row_recs,
+                                                    pitch_bytes);
+    return tvec;
+}
+
 template <typename T, bool SQ, int PX, int RW, int NW, int MODE, bool NTS = false>
 struct Build {
     static constexpr int TH = RW * NW;                       // strip height
@@ -173,6 +303,8 @@ struct Build {
     static __device__ __forceinline__ int col(int lane, int p) { return (p >> 1) * 128 + 2 * lane + (p & 1); }
     // Squared partial sums: 8-bit squares fit 32 bits for a whole block, 16-bit ones do not.
     using QT = typename std::conditional<sizeof(T) == 1, uint32_t, uint64_t>::type;
+    // Squares of 16-bit pixels need the split scan of scan_pair.
+    static constexpr bool WIDE_SQ = sizeof(T) == 2;
 
     struct Smem {
         uint32_t tile[TILEB / 4];                            // image tile of the current block
@@ -500,67 +632,6 @@ struct Build {
         emit_total(d, strip, xb, lane, v, a, vq, aq);
     }
 
-    // One table's rows of the block for this wave; returns the row totals (lane r holds row r's)
-    // to add to the left carries.  Per row and sub-block: the lane's pixel pair, a DPP scan of
-    // pair sums across the wave, then one 16-byte store per lane (contiguous across the wave).
-    // Stores go through buffer resources so that the hardware range check, not a branch per
-    // row, drops what lies outside the image:
-    //   VEC (block wholly inside the image width, 16-byte aligned rows): one resource spanning
-    //     the wave's rows from the block start, records ending at the last valid row's width;
-    //     row r is addressed by the scalar offset r * pitch.
-    //   ragged: one resource per row covering exactly [block start, W) of that row, 8-byte
-    //     stores.
-    template <typename ST, bool SQUARE, bool VEC>
-    static __device__ __forceinline__ uint64_t rows_pass(const Smem &sm, int row0, int lane, const uint64_t (&u)[PX],
-                                                         uint64_t lcarry, uint64_t *blk0, int rows_ok,
-                                                         uint32_t row_recs, uint32_t pitch_bytes) {
-        uint64_t acc[PX];
-#pragma unroll
-        for (int p = 0; p < PX; ++p) acc[p] = 0;
-        uint64_t tvec = 0;
-        const uint32_t voff = static_cast<uint32_t>(lane) * 16;
-        const int nvalid = rows_ok > 0 ? rows_ok : 0;
-        const uint32_t blk_recs = nvalid > 0 ? (nvalid - 1) * pitch_bytes + row_recs : 0;
-        const i32x4 rs_blk = make_rsrc(blk0, VEC ? blk_recs : 0);
-        const char *rowp = reinterpret_cast<const char *>(blk0);
-        uint32_t roff = 0;
-#pragma unroll 1
-        for (int r = 0; r < rows_ok; ++r) {
-            uint32_t raw[NS];
-            tile_px(sm, row0 + r, lane, raw);
-            uint64_t base = readlane(lcarry, r);      // row total left of this sub-block
-            const __amdgpu_buffer_rsrc_t rs_row = __builtin_amdgcn_make_buffer_rsrc(
-                const_cast<char *>(rowp), 0, (!VEC && r < rows_ok) ? static_cast<int>(row_recs) : 0, kRsrcWord3);
-#pragma unroll
-            for (int sb = 0; sb < NS; ++sb) {
-                const ST v0 = pix(raw, 2 * sb), v1 = pix(raw, 2 * sb + 1);
-                const ST a0 = SQUARE ? v0 * v0 : v0;
-                const ST a1 = SQUARE ? v1 * v1 : v1;
-                const ST pair = add64(a0, a1);
-                const ST incl = wave_scan(pair);
-                const uint64_t b = base + (incl - pair);
-                acc[2 * sb] += b + a0;
-                acc[2 * sb + 1] += b + pair;
-                const uint64_t o0 = u[2 * sb] + acc[2 * sb], o1 = u[2 * sb + 1] + acc[2 * sb + 1];
-                if (VEC) {
-                    store16_rsrc<NTS>(u32x4{static_cast<uint32_t>(o0), static_cast<uint32_t>(o0 >> 32),
-                                       static_cast<uint32_t>(o1), static_cast<uint32_t>(o1 >> 32)},
-                                 rs_blk, voff + sb * 1024, roff);
-                } else {
-                    __builtin_amdgcn_raw_buffer_store_b64(u32x2{static_cast<uint32_t>(o0), static_cast<uint32_t>(o0 >> 32)},
-                                                          rs_row, voff + sb * 1024, 0, NTS ? 2 : 0);
-                    __builtin_amdgcn_raw_buffer_store_b64(u32x2{static_cast<uint32_t>(o1), static_cast<uint32_t>(o1 >> 32)},
-                                                          rs_row, voff + sb * 1024 + 8, 0, NTS ? 2 : 0);
-                }
-                base += readlane(incl, 63);
-            }
-            if (lane == r) tvec = base - readlane(lcarry, r);
-            rowp += pitch_bytes;
-            roff += pitch_bytes;
-        }
-        return tvec;
-    }
-
     static __device__ void strip(const BuildDesc &d, int strip_idx, uint64_t *state, unsigned int *fault, Smem &sm) {
         const int lane = threadIdx.x & 63;
         const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
@@ -585,7 +656,7 @@ struct Build {
         } else {
             load_tile_slow(d, sm, ys, 0, nvalid);
         }
-        __syncthreads();
+        lds_barrier();
 
         for (int b = 0; b < d.nblocks; ++b) {
             const int buf = b & 1;
@@ -597,7 +668,7 @@ struct Build {
                 QT csq[PX];
 #pragma unroll
                 for (int p = 0; p < PX; ++p) { cs[p] = 0; csq[p] = 0; }
-#pragma unroll 2
+#pragma unroll 8
                 for (int r = 0; r < rows_ok; ++r) {
                     uint32_t raw[NS];
                     tile_px(sm, row0 + r, lane, raw);
@@ -617,7 +688,7 @@ struct Build {
             // Prefetch the next block's tile while this block's lookback and rows run.
             const bool next_fast = b + 1 < d.nblocks && fast_tile(d, xb + BW);
             if (next_fast) fetch_any(d, ys, xb + BW, nvalid, pf);
-            __syncthreads();
+            lds_barrier();
 
             if (wave == 0) {
                 uint64_t a[PX], aq[PX], v[PX], vq[PX];
@@ -648,7 +719,7 @@ struct Build {
                     if (SQ) sm.vq[lane * PX + p] = vq[p];
                 }
             }
-            __syncthreads();
+            lds_barrier();
 
             // Table row just above this wave's rows: prefix along x of the column totals above.
             uint64_t u[PX], uq[PX];
@@ -690,20 +761,21 @@ struct Build {
             // table is a second pass over the same tile to keep live ranges short.
             const bool vec = d.sat_vec && xb + BW <= d.W;
             const uint32_t row_recs = static_cast<uint32_t>((d.W - xb) * 8);   // bytes from block start to W
+            const T *trow = reinterpret_cast<const T *>(sm.tile) + row0 * BW + 2 * lane;
             if (vec) {
-                lrow += rows_pass<uint32_t, false, true>(sm, row0, lane, u, lrow, S_w + xb, rows_ok, row_recs, pitch_bytes);
-                if (SQ) lrow_q += rows_pass<QT, true, true>(sm, row0, lane, uq, lrow_q, Q_w + xb, rows_ok, row_recs, pitch_bytes);
+                lrow += block_rows<T, PX, false, false, true, NTS>(trow, lane, u, lrow, S_w + xb, rows_ok, row_recs, pitch_bytes);
+                if (SQ) lrow_q += block_rows<T, PX, true, WIDE_SQ, true, NTS>(trow, lane, uq, lrow_q, Q_w + xb, rows_ok, row_recs, pitch_bytes);
             } else {
-                lrow += rows_pass<uint32_t, false, false>(sm, row0, lane, u, lrow, S_w + xb, rows_ok, row_recs, pitch_bytes);
-                if (SQ) lrow_q += rows_pass<QT, true, false>(sm, row0, lane, uq, lrow_q, Q_w + xb, rows_ok, row_recs, pitch_bytes);
+                lrow += block_rows<T, PX, false, false, false, NTS>(trow, lane, u, lrow, S_w + xb, rows_ok, row_recs, pitch_bytes);
+                if (SQ) lrow_q += block_rows<T, PX, true, WIDE_SQ, false, NTS>(trow, lane, uq, lrow_q, Q_w + xb, rows_ok, row_recs, pitch_bytes);
             }
 
             // Replace the tile with the next block's.
             if (b + 1 < d.nblocks) {
-                __syncthreads();
+                lds_barrier();
                 if (next_fast) commit_any(d, sm, pf);
                 else load_tile_slow(d, sm, ys, xb + BW, nvalid);
-                __syncthreads();
+                lds_barrier();
             }
         }
     }
@@ -769,16 +841,24 @@ struct TileStage {
 
 // ------------------------------------------------------------------ helper-wave strip worker
 //
-// Same arithmetic and lookback protocol as Build, organised around the single in-order vector
-// memory counter of gfx9 (loads and stores retire in issue order, so waiting for a load also waits
-// for every store issued before it).  A workgroup has NW compute waves and one helper wave:
-//   - the helper issues every global load: the next image tile goes straight into a double-
-//     buffered LDS tile (global_load_lds, no VGPRs), then it forms the strip's column sums of that
-//     tile and runs the decoupled lookback for it, one block ahead of the compute waves;
-//   - the compute waves only read LDS, scan and store, so they never wait on memory.
-// One workgroup barrier per block separates "helper prepared block b+1" from "compute waves
-// finished block b".
-template <typename T, bool SQ, int PX, int RW, int NW, int WIN, bool NTS = false>
+// Same arithmetic and lookback protocol as Build, with the global loads and the lookback kept off
+// the compute waves' path.  A workgroup has NW compute waves and one helper wave; the compute
+// waves only read LDS, scan and store.  Two pipelines:
+//   P3 = false (two tile buffers, one barrier per block): the helper stages the next tile straight
+//     into LDS (global_load_lds, no VGPRs), forms its column sums for every compute wave and runs
+//     the decoupled lookback for it, one block ahead of the compute waves.  Least LDS: two
+//     workgroups per CU for 8-bit tiles, which tall images need to reach the write ceiling.
+//   P3 = true (three tile buffers, two barriers per block): the helper stages tiles two blocks
+//     ahead; each compute wave forms the column sums of its own rows of tile b+1, and the helper
+//     runs only the lookback of block b+1 while the compute waves work on block b.  The helper's
+//     path per block is a fraction of P3 = false's, which matters where each CU holds one strip
+//     and the helper's latency sets the pace.
+//     Barriers: X_b ("column sums of b+1 are in LDS") and Y_b ("block b is done, the lookback of
+//     b+1 is in LDS, tile b+2 has landed").
+// The helper and the compute waves run separate loops with the same barriers, so the compute
+// waves' barriers wait only for their LDS accesses, never for the helper's DMA or for their own
+// table stores (gfx9 counts stores and loads on one vector memory counter).
+template <typename T, bool SQ, int PX, int RW, int NW, int WIN, bool NTS = false, bool P3 = false>
 struct Build2 {
     using B1 = Build<T, SQ, PX, RW, NW, MODE_LOOKBACK>;   // shared helpers (column map, lookback)
     static constexpr int TH = RW * NW;
@@ -788,75 +868,85 @@ struct Build2 {
     static constexpr int HELPER = NW;                     // wave index of the helper
     static constexpr int ROWB = BW * static_cast<int>(sizeof(T));
     static constexpr int TILEB = TH * ROWB;
+    static constexpr int NTILE = P3 ? 3 : 2;              // tile buffers: blocks b, b+1 (, b+2)
     static_assert(TILEB % 1024 == 0, "tile is a whole number of 1 KiB wave loads");
     using QT = typename B1::QT;
 
     struct Smem {
-        uint32_t tile[2][TILEB / 4];                      // image tiles of blocks b and b+1
-        uint32_t cs[2][NW][BW];                           // per compute wave column sums
+        uint32_t tile[NTILE][TILEB / 4];                  // image tiles of blocks b, b+1 (, b+2)
+        uint32_t cs[2][NW][BW];                           // per compute wave column sums (blocks b, b+1)
         QT csq[SQ ? 2 : 1][SQ ? NW : 1][SQ ? BW : 1];
         uint64_t v[2][BW];                                // column totals above the strip
         uint64_t vq[SQ ? 2 : 1][SQ ? BW : 1];
         long long ticket;
     };
 
-    // LDS-only workgroup barrier: orders LDS accesses, leaves this wave's global stores in flight.
-    static __device__ __forceinline__ void barrier() {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-        __builtin_amdgcn_s_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-    }
-
-    static __device__ void load_tile(const BuildDesc &d, Smem &sm, int buf, int64_t ys, int64_t xb, int nvalid,
+    static __device__ void load_tile(const BuildDesc &d, Smem &sm, int tb, int64_t ys, int64_t xb, int nvalid,
                                      int lane) {
-        TileStage<T, PX, TH>::load(d, sm.tile[buf], ys, xb, nvalid, lane);
+        TileStage<T, PX, TH>::load(d, sm.tile[tb], ys, xb, nvalid, lane);
     }
 
     // Wait for this wave's outstanding global loads (the tile DMA) and LDS traffic.
     static __device__ __forceinline__ void wait_loads() { __builtin_amdgcn_s_waitcnt(0x0070); }
 
-    // Helper wave: column sums of tile `buf` per compute wave and for the strip, the lookback for
-    // this block, and the results in LDS buffer `buf` for the compute waves.
-    static __device__ void prepare(const BuildDesc &d, Smem &sm, int buf, int64_t xb, int strip, int nvalid,
+    // Helper wave (P3 = false): column sums of tile tb for every compute wave into column-sum
+    // buffer buf, then the lookback of block xb (lookback_block).
+    static __device__ void prepare(const BuildDesc &d, Smem &sm, int tb, int buf, int64_t xb, int strip, int nvalid,
                                    int rw, int lane, uint64_t *state, unsigned int *fault) {
-        uint64_t a[PX], aq[PX];
-#pragma unroll
-        for (int p = 0; p < PX; ++p) { a[p] = 0; aq[p] = 0; }
-        const T *tile = reinterpret_cast<const T *>(sm.tile[buf]) + 2 * lane;
         for (int w = 0; w < NW; ++w) {
-            uint32_t cs[PX];
-            QT csq[PX];
+            const int left = nvalid - w * rw;
+            colsums(sm, tb, buf, w, w * rw, left < rw ? (left > 0 ? left : 0) : rw, lane);
+        }
+        lookback_block(d, sm, buf, xb, strip, lane, state, fault);
+    }
+
+    // Compute wave: column sums of its own rows (rows_ok from wave row row0) of tile tb into
+    // column-sum buffer buf.
+    static __device__ void colsums(Smem &sm, int tb, int buf, int wave, int row0, int rows_ok, int lane) {
+        uint32_t cs[PX];
+        QT csq[PX];
 #pragma unroll
-            for (int p = 0; p < PX; ++p) { cs[p] = 0; csq[p] = 0; }
-            const int r_end = nvalid - w * rw < rw ? nvalid - w * rw : rw;
-#pragma unroll 2
-            for (int r = 0; r < r_end; ++r) {
-                const T *row = tile + (w * rw + r) * BW;
+        for (int p = 0; p < PX; ++p) { cs[p] = 0; csq[p] = 0; }
+        const T *tile = reinterpret_cast<const T *>(sm.tile[tb]) + 2 * lane + row0 * BW;
+#pragma unroll 8
+        for (int r = 0; r < rows_ok; ++r) {
+            const T *row = tile + r * BW;
 #pragma unroll
-                for (int sb = 0; sb < NS; ++sb) {
-                    uint32_t pair;
-                    if (sizeof(T) == 1) pair = *reinterpret_cast<const uint16_t *>(row + 128 * sb);
-                    else pair = *reinterpret_cast<const uint32_t *>(row + 128 * sb);
-                    const uint32_t v0 = sizeof(T) == 1 ? (pair & 0xffu) : (pair & 0xffffu);
-                    const uint32_t v1 = sizeof(T) == 1 ? ((pair >> 8) & 0xffu) : (pair >> 16);
-                    cs[2 * sb] += v0;
-                    cs[2 * sb + 1] += v1;
-                    if (SQ) {
-                        csq[2 * sb] += static_cast<QT>(v0) * v0;
-                        csq[2 * sb + 1] += static_cast<QT>(v1) * v1;
-                    }
-                }
-            }
-#pragma unroll
-            for (int p = 0; p < PX; ++p) {
-                sm.cs[buf][w][lane * PX + p] = cs[p];
-                a[p] += cs[p];
+            for (int sb = 0; sb < NS; ++sb) {
+                uint32_t pair;
+                if (sizeof(T) == 1) pair = *reinterpret_cast<const uint16_t *>(row + 128 * sb);
+                else pair = *reinterpret_cast<const uint32_t *>(row + 128 * sb);
+                const uint32_t v0 = sizeof(T) == 1 ? (pair & 0xffu) : (pair & 0xffffu);
+                const uint32_t v1 = sizeof(T) == 1 ? ((pair >> 8) & 0xffu) : (pair >> 16);
+                cs[2 * sb] += v0;
+                cs[2 * sb + 1] += v1;
                 if (SQ) {
-                    sm.csq[buf][w][lane * PX + p] = csq[p];
-                    aq[p] += csq[p];
+                    csq[2 * sb] += static_cast<QT>(v0 * v0);
+                    csq[2 * sb + 1] += static_cast<QT>(v1 * v1);
                 }
             }
         }
+#pragma unroll
+        for (int p = 0; p < PX; ++p) {
+            sm.cs[buf][wave][lane * PX + p] = cs[p];
+            if (SQ) sm.csq[buf][wave][lane * PX + p] = csq[p];
+        }
+    }
+
+    // Helper wave: the strip's column sums of block xb (the compute waves' sums in buffer buf),
+    // the lookback for it, and the column totals above the strip into v[buf] / vq[buf].
+    static __device__ void lookback_block(const BuildDesc &d, Smem &sm, int buf, int64_t xb, int strip, int lane,
+                                          uint64_t *state, unsigned int *fault) {
+        uint64_t a[PX], aq[PX];
+#pragma unroll
+        for (int p = 0; p < PX; ++p) { a[p] = 0; aq[p] = 0; }
+#pragma unroll
+        for (int w = 0; w < NW; ++w)
+#pragma unroll
+            for (int p = 0; p < PX; ++p) {
+                a[p] += sm.cs[buf][w][lane * PX + p];
+                if (SQ) aq[p] += sm.csq[buf][w][lane * PX + p];
+            }
         uint64_t v[PX], vq[PX];
         if constexpr (WIN > 0) {
             B1::template lookback_win<WIN>(d, strip, xb, lane, a, aq, v, vq, state, fault);
@@ -876,9 +966,9 @@ struct Build2 {
         }
     }
 
-    // Compute wave: the rows of block (buf, xb).
-    static __device__ void compute(const BuildDesc &d, const Smem &sm, int buf, int64_t xb, int wave, int rw, int lane,
-                                   int rows_ok, uint64_t *S_w, uint64_t *Q_w, uint32_t pitch_bytes,
+    // Compute wave: the rows of block xb (tile buffer tb, column sums and totals buffer buf).
+    static __device__ void compute(const BuildDesc &d, const Smem &sm, int tb, int buf, int64_t xb, int wave, int rw,
+                                   int lane, int rows_ok, uint64_t *S_w, uint64_t *Q_w, uint32_t pitch_bytes,
                                    uint64_t &lrow, uint64_t &lrow_q, uint64_t &ucarry, uint64_t &ucarry_q) {
         uint64_t u[PX], uq[PX];
         {
@@ -914,70 +1004,14 @@ struct Build2 {
         }
         const bool vec = d.sat_vec && xb + BW <= d.W;
         const uint32_t row_recs = static_cast<uint32_t>((d.W - xb) * 8);
-        const uint32_t *tile = sm.tile[buf] + wave * rw * ROWB / 4;   // this wave's first row
+        const T *trow = reinterpret_cast<const T *>(sm.tile[tb] + wave * rw * ROWB / 4) + 2 * lane;
         if (vec) {
-            lrow += rows<uint32_t, false, true>(tile, lane, u, lrow, S_w + xb, rows_ok, row_recs, pitch_bytes);
-            if (SQ) lrow_q += rows<QT, true, true>(tile, lane, uq, lrow_q, Q_w + xb, rows_ok, row_recs, pitch_bytes);
+            lrow += block_rows<T, PX, false, false, true, NTS>(trow, lane, u, lrow, S_w + xb, rows_ok, row_recs, pitch_bytes);
+            if (SQ) lrow_q += block_rows<T, PX, true, B1::WIDE_SQ, true, NTS>(trow, lane, uq, lrow_q, Q_w + xb, rows_ok, row_recs, pitch_bytes);
         } else {
-            lrow += rows<uint32_t, false, false>(tile, lane, u, lrow, S_w + xb, rows_ok, row_recs, pitch_bytes);
-            if (SQ) lrow_q += rows<QT, true, false>(tile, lane, uq, lrow_q, Q_w + xb, rows_ok, row_recs, pitch_bytes);
+            lrow += block_rows<T, PX, false, false, false, NTS>(trow, lane, u, lrow, S_w + xb, rows_ok, row_recs, pitch_bytes);
+            if (SQ) lrow_q += block_rows<T, PX, true, B1::WIDE_SQ, false, NTS>(trow, lane, uq, lrow_q, Q_w + xb, rows_ok, row_recs, pitch_bytes);
         }
-    }
-
-    // Rows of one table (same scheme as Build::rows_pass); `tile` points at the wave's first row.
-    template <typename ST, bool SQUARE, bool VEC>
-    static __device__ __forceinline__ uint64_t rows(const uint32_t *tile, int lane, const uint64_t (&u)[PX],
-                                                    uint64_t lcarry, uint64_t *blk0, int rows_ok, uint32_t row_recs,
-                                                    uint32_t pitch_bytes) {
-        uint64_t acc[PX];
-#pragma unroll
-        for (int p = 0; p < PX; ++p) acc[p] = 0;
-        uint64_t tvec = 0;
-        const uint32_t voff = static_cast<uint32_t>(lane) * 16;
-        const int nvalid = rows_ok > 0 ? rows_ok : 0;
-        const uint32_t blk_recs = nvalid > 0 ? (nvalid - 1) * pitch_bytes + row_recs : 0;
-        const i32x4 rs_blk = make_rsrc(blk0, VEC ? blk_recs : 0);
-        const char *rowp = reinterpret_cast<const char *>(blk0);
-        uint32_t roff = 0;
-        const T *trow = reinterpret_cast<const T *>(tile) + 2 * lane;
-#pragma unroll 1
-        for (int r = 0; r < nvalid; ++r) {
-            uint64_t base = readlane(lcarry, r);
-            const __amdgpu_buffer_rsrc_t rs_row = __builtin_amdgcn_make_buffer_rsrc(
-                const_cast<char *>(rowp), 0, (!VEC && r < rows_ok) ? static_cast<int>(row_recs) : 0, kRsrcWord3);
-#pragma unroll
-            for (int sb = 0; sb < NS; ++sb) {
-                uint32_t pairv;
-                if (sizeof(T) == 1) pairv = *reinterpret_cast<const uint16_t *>(trow + 128 * sb);
-                else pairv = *reinterpret_cast<const uint32_t *>(trow + 128 * sb);
-                const ST v0 = sizeof(T) == 1 ? (pairv & 0xffu) : (pairv & 0xffffu);
-                const ST v1 = sizeof(T) == 1 ? ((pairv >> 8) & 0xffu) : (pairv >> 16);
-                const ST a0 = SQUARE ? v0 * v0 : v0;
-                const ST a1 = SQUARE ? v1 * v1 : v1;
-                const ST pair = add64(a0, a1);
-                const ST incl = wave_scan(pair);
-                const uint64_t b = base + (incl - pair);
-                acc[2 * sb] += b + a0;
-                acc[2 * sb + 1] += b + pair;
-                const uint64_t o0 = u[2 * sb] + acc[2 * sb], o1 = u[2 * sb + 1] + acc[2 * sb + 1];
-                if (VEC) {
-                    store16_rsrc<NTS>(u32x4{static_cast<uint32_t>(o0), static_cast<uint32_t>(o0 >> 32),
-                                            static_cast<uint32_t>(o1), static_cast<uint32_t>(o1 >> 32)},
-                                      rs_blk, voff + sb * 1024, roff);
-                } else {
-                    __builtin_amdgcn_raw_buffer_store_b64(u32x2{static_cast<uint32_t>(o0), static_cast<uint32_t>(o0 >> 32)},
-                                                          rs_row, voff + sb * 1024, 0, NTS ? 2 : 0);
-                    __builtin_amdgcn_raw_buffer_store_b64(u32x2{static_cast<uint32_t>(o1), static_cast<uint32_t>(o1 >> 32)},
-                                                          rs_row, voff + sb * 1024 + 8, 0, NTS ? 2 : 0);
-                }
-                base += readlane(incl, 63);
-            }
-            if (lane == r) tvec = base - readlane(lcarry, r);
-            trow += BW;
-            rowp += pitch_bytes;
-            roff += pitch_bytes;
-        }
-        return tvec;
     }
 
     static __device__ void strip(const BuildDesc &d, int strip_idx, uint64_t *state, unsigned int *fault, Smem &sm) {
@@ -995,24 +1029,70 @@ struct Build2 {
         const uint32_t pitch_bytes = static_cast<uint32_t>(d.spitch * 8);
         uint64_t lrow = 0, lrow_q = 0, ucarry = 0, ucarry_q = 0;
 
-        if (helper) {
-            load_tile(d, sm, 0, ys, 0, nvalid, lane);
-            wait_loads();
-            prepare(d, sm, 0, 0, strip_idx, nvalid, rw, lane, state, fault);
-        }
-        barrier();
-        if (helper && d.nblocks > 1) load_tile(d, sm, 1, ys, BW, nvalid, lane);
-        for (int b = 0; b < d.nblocks; ++b) {
-            const int buf = b & 1;
-            const int64_t xb = static_cast<int64_t>(b) * BW;
-            if (!helper) {
-                compute(d, sm, buf, xb, wave, rw, lane, rows_ok, S_w, Q_w, pitch_bytes, lrow, lrow_q, ucarry, ucarry_q);
-            } else if (b + 1 < d.nblocks) {
+        if constexpr (!P3) {
+            // One loop for all waves, one barrier per block.  Measured on tall 8-bit images (two
+            // workgroups per CU): the joined loop, whose barrier also drains the compute waves'
+            // table stores of the block, is 5-7 % faster than separate helper and compute loops.
+            if (helper) {
+                __builtin_amdgcn_s_setprio(3);   // see below
+                load_tile(d, sm, 0, ys, 0, nvalid, lane);
                 wait_loads();
-                prepare(d, sm, buf ^ 1, xb + BW, strip_idx, nvalid, rw, lane, state, fault);
+                prepare(d, sm, 0, 0, 0, strip_idx, nvalid, rw, lane, state, fault);
             }
-            barrier();
-            if (helper && b + 2 < d.nblocks) load_tile(d, sm, buf, ys, xb + 2 * BW, nvalid, lane);
+            lds_barrier();
+            if (helper && d.nblocks > 1) load_tile(d, sm, 1, ys, BW, nvalid, lane);
+            for (int b = 0; b < d.nblocks; ++b) {
+                const int buf = b & 1;
+                const int64_t xb = static_cast<int64_t>(b) * BW;
+                if (!helper) {
+                    compute(d, sm, buf, buf, xb, wave, rw, lane, rows_ok, S_w, Q_w, pitch_bytes, lrow, lrow_q,
+                            ucarry, ucarry_q);
+                } else if (b + 1 < d.nblocks) {
+                    wait_loads();
+                    prepare(d, sm, buf ^ 1, buf ^ 1, xb + BW, strip_idx, nvalid, rw, lane, state, fault);
+                }
+                lds_barrier();
+                if (helper && b + 2 < d.nblocks) load_tile(d, sm, buf, ys, xb + 2 * BW, nvalid, lane);
+            }
+            return;
+        }
+        // Barriers: Z (tiles 0 and 1 landed), X' / Y' (column sums, then lookback, of block 0),
+        // then X_b / Y_b per block; the same count in both loops.
+        if (helper) {
+            // The helper shares a SIMD with a compute wave that has VALU work ready nearly every
+            // cycle; at the default (age-ordered) priority the helper, the youngest wave, got only
+            // the leftover issue slots and its short lookback and DMA steps became the critical
+            // path.  Its work is a few instructions per block, so it goes first.
+            __builtin_amdgcn_s_setprio(3);
+            load_tile(d, sm, 0, ys, 0, nvalid, lane);
+            if (d.nblocks > 1) load_tile(d, sm, 1, ys, BW, nvalid, lane);
+            wait_loads();
+            lds_barrier();                                                        // Z
+            lds_barrier();                                                        // X'
+            lookback_block(d, sm, 0, 0, strip_idx, lane, state, fault);
+            lds_barrier();                                                        // Y'
+            for (int b = 0; b < d.nblocks; ++b) {
+                const int64_t xb = static_cast<int64_t>(b) * BW;
+                if (b + 2 < d.nblocks) load_tile(d, sm, (b + 2) % NTILE, ys, xb + 2 * BW, nvalid, lane);
+                lds_barrier();                                                    // X_b
+                if (b + 1 < d.nblocks) lookback_block(d, sm, (b + 1) & 1, xb + BW, strip_idx, lane, state, fault);
+                wait_loads();
+                lds_barrier();                                                    // Y_b
+            }
+        } else {
+            const int row0 = wave * rw;
+            lds_barrier();                                                        // Z
+            colsums(sm, 0, 0, wave, row0, rows_ok, lane);
+            lds_barrier();                                                        // X'
+            lds_barrier();                                                        // Y'
+            for (int b = 0; b < d.nblocks; ++b) {
+                const int64_t xb = static_cast<int64_t>(b) * BW;
+                if (b + 1 < d.nblocks) colsums(sm, (b + 1) % NTILE, (b + 1) & 1, wave, row0, rows_ok, lane);
+                lds_barrier();                                                    // X_b
+                compute(d, sm, b % NTILE, b & 1, xb, wave, rw, lane, rows_ok, S_w, Q_w, pitch_bytes, lrow, lrow_q,
+                        ucarry, ucarry_q);
+                lds_barrier();                                                    // Y_b
+            }
         }
     }
 };
@@ -1082,12 +1162,6 @@ struct BuildPow {
         uint64_t v[2][NP][BW];                            // column totals above the strip
         long long ticket;
     };
-
-    static __device__ __forceinline__ void barrier() {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-        __builtin_amdgcn_s_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-    }
 
     static __device__ __forceinline__ uint64_t *table(const BuildDesc &d, int p) {
         return p == 0 ? d.S : p == 1 ? d.Q : p == 2 ? d.T3 : d.T4;
@@ -1304,27 +1378,34 @@ struct BuildPow {
 #pragma unroll
         for (int p = 0; p < NP; ++p) { lrow[p] = 0; ucarry[p] = 0; }
 
+        // Separate helper and compute loops, as in Build2::strip.
         if (helper) {
             TileStage<T, PX, TH>::load(d, sm.tile[0], ys, 0, nvalid, lane);
             __builtin_amdgcn_s_waitcnt(0x0070);
             prepare(d, sm, 0, 0, strip_idx, nvalid, rw, lane, state, fault);
-        }
-        barrier();
-        if (helper && d.nblocks > 1) TileStage<T, PX, TH>::load(d, sm.tile[1], ys, BW, nvalid, lane);
-        for (int b = 0; b < d.nblocks; ++b) {
-            const int buf = b & 1;
-            const int64_t xb = static_cast<int64_t>(b) * BW;
-            if (!helper) {
+            lds_barrier();
+            if (d.nblocks > 1) TileStage<T, PX, TH>::load(d, sm.tile[1], ys, BW, nvalid, lane);
+            for (int b = 0; b < d.nblocks; ++b) {
+                const int buf = b & 1;
+                const int64_t xb = static_cast<int64_t>(b) * BW;
+                if (b + 1 < d.nblocks) {
+                    __builtin_amdgcn_s_waitcnt(0x0070);
+                    prepare(d, sm, buf ^ 1, xb + BW, strip_idx, nvalid, rw, lane, state, fault);
+                }
+                lds_barrier();
+                if (b + 2 < d.nblocks) TileStage<T, PX, TH>::load(d, sm.tile[buf], ys, xb + 2 * BW, nvalid, lane);
+            }
+        } else {
+            lds_barrier();
+            for (int b = 0; b < d.nblocks; ++b) {
+                const int buf = b & 1;
+                const int64_t xb = static_cast<int64_t>(b) * BW;
                 power_rows<1>(d, sm, buf, xb, wave, rw, lane, rows_ok, yw, pitch_bytes, lrow[0], ucarry[0]);
                 if constexpr (NP >= 2) power_rows<2>(d, sm, buf, xb, wave, rw, lane, rows_ok, yw, pitch_bytes, lrow[1], ucarry[1]);
                 if constexpr (NP >= 3) power_rows<3>(d, sm, buf, xb, wave, rw, lane, rows_ok, yw, pitch_bytes, lrow[2], ucarry[2]);
                 if constexpr (NP >= 4) power_rows<4>(d, sm, buf, xb, wave, rw, lane, rows_ok, yw, pitch_bytes, lrow[3], ucarry[3]);
-            } else if (b + 1 < d.nblocks) {
-                __builtin_amdgcn_s_waitcnt(0x0070);
-                prepare(d, sm, buf ^ 1, xb + BW, strip_idx, nvalid, rw, lane, state, fault);
+                lds_barrier();
             }
-            barrier();
-            if (helper && b + 2 < d.nblocks) TileStage<T, PX, TH>::load(d, sm.tile[buf], ys, xb + 2 * BW, nvalid, lane);
         }
     }
 };
@@ -1345,10 +1426,10 @@ __global__ __launch_bounds__((NW + 1) * 64) void build_pow_kernel(BuildDesc d, l
     }
 }
 
-template <typename T, bool SQ, int PX, int RW, int NW, int WIN, bool NTS>
+template <typename T, bool SQ, int PX, int RW, int NW, int WIN, bool NTS, bool P3>
 __global__ __launch_bounds__((NW + 1) * 64) void build2_kernel(const BuildDesc *__restrict__ many, int n,
                                                                long long total_items, uint64_t *state, BuildCtrl *ctrl) {
-    using B = Build2<T, SQ, PX, RW, NW, WIN, NTS>;
+    using B = Build2<T, SQ, PX, RW, NW, WIN, NTS, P3>;
     __shared__ typename B::Smem sm;
     for (;;) {
         if (threadIdx.x == 0) sm.ticket = static_cast<long long>(atomicAdd(&ctrl->ticket, 1ull));
@@ -1363,7 +1444,7 @@ __global__ __launch_bounds__((NW + 1) * 64) void build2_kernel(const BuildDesc *
             if (many[mid].first_item <= t) lo = mid;
             else hi = mid - 1;
         }
-        const BuildDesc &d = many[lo];
+        const BuildDesc d = many[lo];   // by value: kept in registers, not reloaded after every store
         B::strip(d, __builtin_amdgcn_readfirstlane(static_cast<int>(t - d.first_item)), state, &ctrl->fault, sm);
     }
 }
@@ -1392,7 +1473,7 @@ void build_kernel(const BuildDesc *__restrict__ many, int n, long long total_ite
             if (many[mid].first_item <= t) lo = mid;
             else hi = mid - 1;
         }
-        const BuildDesc &d = many[lo];
+        const BuildDesc d = many[lo];   // by value: kept in registers, not reloaded after every store
         B::strip(d, __builtin_amdgcn_readfirstlane(static_cast<int>(t - d.first_item)), state, &ctrl->fault, sm);
     }
 }
@@ -1613,7 +1694,9 @@ hipError_t launch_totals_typed(const void *img, int64_t H, int64_t W, int64_t pi
     X(8, "lookback_nt_px8_rw16_nw4", 8, 16, 4, MODE_LOOKBACK, 1, 1, true)          \
     X(9, "lookback_nt_px4_rw16_nw4", 4, 16, 4, MODE_LOOKBACK, 1, 1, true)          \
     X(10, "helper_nt_px4_rw16_nw4", 4, 16, 4, MODE_HELPER, 1, 1, true)             \
-    X(11, "helper_nt_px8_rw12_nw4", 8, 12, 4, MODE_HELPER, 1, 1, true)
+    X(11, "helper_nt_px8_rw12_nw4", 8, 12, 4, MODE_HELPER, 1, 1, true)            \
+    X(12, "helper3_nt_px4_rw16_nw4", 4, 16, 4, MODE_HELPER3, 1, 1, true)           \
+    X(13, "helper3_nt_px8_rw12_nw4", 8, 12, 4, MODE_HELPER3, 1, 1, true)
 
 const BuildVariant kVariants[] = {
 #define SAT_X(i, name, px, rw, nw, mode, win, adapt, nt) {name, px, rw, nw, mode},
@@ -1641,7 +1724,8 @@ int resident_capacity(const void *kernel, int threads) {
 constexpr size_t kLdsBytes = 160 * 1024;
 template <typename T, bool SQ, int PX, int RW, int NW, int MODE, int WIN, bool NT>
 constexpr bool lds_fits() {
-    if constexpr (MODE == MODE_HELPER) return sizeof(typename Build2<T, SQ, PX, RW, NW, WIN, NT>::Smem) <= kLdsBytes;
+    if constexpr (MODE == MODE_HELPER || MODE == MODE_HELPER3)
+        return sizeof(typename Build2<T, SQ, PX, RW, NW, WIN, NT, MODE == MODE_HELPER3>::Smem) <= kLdsBytes;
     else return sizeof(typename Build<T, SQ, PX, RW, NW, MODE, NT>::Smem) <= kLdsBytes;
 }
 
@@ -1652,9 +1736,10 @@ int capacity_typed() {
     } else {
         static int cap = 0;   // per instantiation; the library drives one device model
         if (cap == 0) {
-            if constexpr (MODE == MODE_HELPER)
-                cap = resident_capacity(reinterpret_cast<const void *>(&build2_kernel<T, SQ, PX, RW, NW, WIN, NT>),
-                                        (NW + 1) * 64);
+            if constexpr (MODE == MODE_HELPER || MODE == MODE_HELPER3)
+                cap = resident_capacity(
+                    reinterpret_cast<const void *>(&build2_kernel<T, SQ, PX, RW, NW, WIN, NT, MODE == MODE_HELPER3>),
+                    (NW + 1) * 64);
             else
                 cap = resident_capacity(reinterpret_cast<const void *>(&build_kernel<T, SQ, PX, RW, NW, MODE, NT>),
                                         NW * 64);
@@ -1674,7 +1759,7 @@ hipError_t launch_typed(const BuildDesc *descs, int n, const BuildDesc *dev_desc
         BuildDesc *slot = n == 1 ? &ctrl->one : nullptr;
         const BuildDesc *table = n == 1 ? slot : dev_descs;
         constexpr int TH = RW * NW;
-        constexpr bool kPrepass = MODE == MODE_REDUCE_SCAN || (MODE == MODE_HELPER && WIN == 0);
+        constexpr bool kPrepass = MODE == MODE_REDUCE_SCAN || ((MODE == MODE_HELPER || MODE == MODE_HELPER3) && WIN == 0);
         if (!kPrepass) {
             const long long pairs = (state_words + 1) / 2;
             const long long blocks = pairs > 0 ? (pairs + 255) / 256 : 1;
@@ -1702,8 +1787,8 @@ hipError_t launch_typed(const BuildDesc *descs, int n, const BuildDesc *dev_desc
         if (e != hipSuccess) return e;
         const int cap = capacity_typed<T, SQ, PX, RW, NW, MODE, WIN, NT>();
         const int64_t grid = total_items < cap ? total_items : cap;
-        if constexpr (MODE == MODE_HELPER)
-            hipLaunchKernelGGL((build2_kernel<T, SQ, PX, RW, NW, WIN, NT>), dim3(static_cast<unsigned>(grid)),
+        if constexpr (MODE == MODE_HELPER || MODE == MODE_HELPER3)
+            hipLaunchKernelGGL((build2_kernel<T, SQ, PX, RW, NW, WIN, NT, MODE == MODE_HELPER3>), dim3(static_cast<unsigned>(grid)),
                                dim3((NW + 1) * 64), 0, stream, table, n, static_cast<long long>(total_items), state, ctrl);
         else
             hipLaunchKernelGGL((build_kernel<T, SQ, PX, RW, NW, MODE, NT>), dim3(static_cast<unsigned>(grid)),

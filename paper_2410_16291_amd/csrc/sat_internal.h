@@ -44,7 +44,11 @@ struct BuildCtrl {
 };
 static_assert(sizeof(BuildCtrl) == 256, "control header is 256 bytes");
 
-enum BuildMode { MODE_LOOKBACK = 0, MODE_REDUCE_SCAN = 1, MODE_HELPER = 2 };
+// MODE_HELPER: helper wave stages tiles and forms column sums and lookback one block ahead (one
+// barrier per block, two tile buffers).  MODE_HELPER3: the compute waves form their own column
+// sums and the helper runs the lookback of block b+1 while they compute block b (two barriers
+// per block, three tile buffers): more LDS, shorter helper path per block.
+enum BuildMode { MODE_LOOKBACK = 0, MODE_REDUCE_SCAN = 1, MODE_HELPER = 2, MODE_HELPER3 = 3 };
 
 struct BuildVariant {
     const char *name;
