@@ -245,18 +245,26 @@ def batched_section(torch, dev, n_images):
 
     t_per = autotune.time_ms(per_image, reps=3)
     t_bat = autotune.time_ms(batched, reps=3)
+    t_fused = autotune.time_ms(lambda: batch.build_stats_batched(imgs, h, w, stride, tables=tables, outs=outs),
+                               reps=3)
     tuner = autotune.Tuner(path=None, reps=3)
     t0 = time.perf_counter()
     choice = tuner.tune_batch(imgs, squares=True, win=(h, w), stride=stride)
     tune_s = time.perf_counter() - t0
-    t_tuned = autotune.time_ms(lambda: batched(choice["build"], choice["gather"]), reps=3)
+    t_tuned = autotune.time_ms(lambda: autotune.Tuner.run_batch(choice, imgs, True, (h, w), stride, tables, outs),
+                               reps=3)
     alg = px * (2 + 16 + 1) + sum(o[1].numel() * 24 for o in outs)   # image, S+Q, rows read, outputs
     res = {"workload": "%d uint16 log-normal images (mu 6, sigma 1), sides uniform on 1000..12000 (seed 3); "
                        "tables of pixels and squares; 64x64 windows at stride 4: sum, mean, std" % n_images,
            "images": n_images, "gpix": round(px / 1e9, 4),
            "per_image_calls_ms": round(t_per, 3), "per_image_gpix_s": round(px / t_per / 1e6, 2),
            "batched_ms": round(t_bat, 3), "batched_gpix_s": round(px / t_bat / 1e6, 2),
-           "tuned": {"build": choice["build"], "gather": choice["gather"], "ms": round(t_tuned, 3),
+           "fused_ms": round(t_fused, 3), "fused_gpix_s": round(px / t_fused / 1e6, 2),
+           "fused_alg_GB_s": round(alg / (t_fused * 1e-3) / 1e9, 1),
+           "tuned": {"build": choice["build"], "gather": choice["gather"], "strip_h": choice["strip_h"],
+                     "one_launch": choice["fused"], "candidates_ms": {"strip_h": choice["strip_ms"],
+                                                                       "launches": choice["fused_ms"]},
+                     "ms": round(t_tuned, 3),
                      "gpix_s": round(px / t_tuned / 1e6, 2), "tuning_s": round(tune_s, 2)},
            "speedup_batched_vs_per_image": round(t_per / t_bat, 3),
            "speedup_tuned_vs_per_image": round(t_per / t_tuned, 3),

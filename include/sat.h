@@ -231,9 +231,30 @@ sat_status window_mean_std_batched(const sat_batch_item *items, int32_t n, int64
                                    int64_t win_w, int64_t stride, void *workspace,
                                    size_t workspace_bytes, void *stream);
 
+/* Workspace bytes for sat_build_stats_batched over these items (0 for invalid sizes). */
+size_t sat_build_stats_workspace_bytes(const sat_batch_item *items, int32_t n, sat_dtype pixel_type);
+
+/* The tables of pixels and squares of n images AND the window sum, mean and standard deviation of
+ * every image's windows in ONE persistent launch: sat_build_batched followed by
+ * window_mean_std_batched, fused.  Workgroups take work items from one queue: first every
+ * (image, strip) item of the build, then every statistics item; a statistics item of image i
+ * waits until all of image i's strips are stored (a per-image counter; bounded wait, reported by
+ * sat_workspace_check), so the statistics of early images overlap the builds of later ones.
+ * Items: as sat_build_batched (sat_sq required on every item) plus sum_out (may be NULL),
+ * mean_out, std_out and out_pitch as window_mean_std_batched; one window size and stride for all
+ * (Sec. II-A statistics of the Sec. II-B tables).  Results equal those of the two calls.  Windows
+ * whose height is not a multiple of the stride, and build variants forced outside the fused
+ * kernel's set, run as the two launches instead.
+ * workspace: device, 256-byte aligned, >= sat_build_stats_workspace_bytes(items, n, pixel_type).
+ * Errors: as sat_build_batched and window_mean_std_batched, for any item. */
+sat_status sat_build_stats_batched(const sat_batch_item *items, int32_t n, sat_dtype pixel_type, int64_t win_h,
+                                   int64_t win_w, int64_t stride, void *workspace, size_t workspace_bytes,
+                                   void *stream);
+
 /* Synchronises `stream` and reads the fault word a build left in `workspace`: SAT_OK, or
- * SAT_ERR_DEVICE if a column-lookback wait hit its spin bound or a band build's carry exceeded
- * the bound its rows_above sets (the tables of that call are then unreliable), or SAT_ERR_HIP.
+ * SAT_ERR_DEVICE if a column-lookback wait hit its spin bound, a band build's carry exceeded
+ * the bound its rows_above sets, or a fused statistics item's wait for its image's tables hit its
+ * spin bound (the results of that call are then unreliable), or SAT_ERR_HIP.
  * Meant for tests and debugging; the fast path never waits. */
 sat_status sat_workspace_check(void *workspace, void *stream);
 
@@ -281,7 +302,10 @@ sat_status window_moments(const uint64_t *const *tables, int32_t k, sat_dtype pi
 
 /* Build and tuning introspection: number of compiled kernel variants of kind 0 (table build)
  * or 1 (window gather), the name of variant i, and the variant a later call on this thread
- * will use (-1 restores the built-in choice).  Used by the tile-shape tuner. */
+ * will use (-1 restores the built-in choice).  Kind 2 sets the strip height (rows, 1..1024) of
+ * the batched builds on this thread, capped at the variant's own height and used only by
+ * variants that take shorter strips (-1 restores the variant's height; sat_batch_workspace_bytes
+ * follows it).  Used by the tile-shape tuner. */
 int32_t sat_variant_count(int32_t kind);
 const char *sat_variant_name(int32_t kind, int32_t index);
 sat_status sat_force_variant(int32_t kind, int32_t index);

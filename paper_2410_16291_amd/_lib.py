@@ -66,6 +66,8 @@ def load(path: str = LIB_PATH):
             "sat_batch_workspace_bytes": (_sz, [_p, _i32, ctypes.c_int, ctypes.c_int]),
             "sat_build_batched": (_st, [_p, _i32, ctypes.c_int, _p, _sz, _p]),
             "window_mean_std_batched": (_st, [_p, _i32, _i64, _i64, _i64, _p, _sz, _p]),
+            "sat_build_stats_workspace_bytes": (_sz, [_p, _i32, ctypes.c_int]),
+            "sat_build_stats_batched": (_st, [_p, _i32, ctypes.c_int, _i64, _i64, _i64, _p, _sz, _p]),
             "sat_workspace_check": (_st, [_p, _p]),
             "sat_last_error": (ctypes.c_char_p, []),
             "sat_variant_count": (_i32, [_i32]),

@@ -2,16 +2,19 @@
 
 The library compiles several build variants (pixels per lane, rows per wave, waves per
 workgroup, lookback / reduce-then-scan / helper-wave column scans) and several gather variants
-(chain walks with 1, 2 or 4 outputs per thread, row-pair kernels).  Which one is fastest depends
-on the image sizes, the pixel type, the squared table and the window, so the tuner times every
-candidate on the caller's own work (one warm-up and `reps` timed runs each, HIP events on the
-launch stream), keeps the fastest, and caches the choice per device and shape class in a JSON
-file.  Later calls in the same shape class reuse the cached choice without timing.
+(chain walks with 1, 2 or 4 outputs per thread, row-pair kernels over bands of 2 to 8 column
+chunks).  Which one is fastest depends on the image sizes, the pixel type, the squared table and
+the window, so the tuner times every candidate on the caller's own work (one warm-up and `reps`
+timed runs each, HIP events on the launch stream): the build variant, then the strip height of
+the chosen variant (its own, three quarters, half), the gather variant, and for statistics
+whether tables and statistics go in one launch or two.  It keeps the fastest of each and caches
+the choices per device (name, architecture, CU count) and shape class (image count, total pixels
+and rows, pixel type, squares, window, stride) in a JSON file; later calls in the same class reuse
+them without timing.
 
     tuner = Tuner()
     choice = tuner.tune_batch(images, squares=True, win=(64, 64), stride=4)
-    tables = batch.build_batched(images, squares=True, variant=choice["build"])
-    outs = batch.mean_std_batched(tables, 64, 64, 4, variant=choice["gather"])
+    Tuner.run_batch(choice, images, True, (64, 64), 4, tables, outs)
 """
 from __future__ import annotations
 
@@ -19,6 +22,7 @@ import contextlib
 import json
 import math
 import os
+import re
 from typing import Callable, Dict, Iterable, List, Optional, Sequence, Tuple
 
 import torch
@@ -46,6 +50,26 @@ def shape_class(sizes: Iterable[Tuple[int, int]], pixel_bytes: int, squares: boo
     if win is not None:
         key += "_w%dx%d_s%d" % (win[0], win[1], stride)
     return key
+
+
+@contextlib.contextmanager
+def forced_strip(rows: Optional[int]):
+    """Run the body with batched builds on this thread using strips of `rows` rows (None: the
+    variant's own height)."""
+    if rows is None:
+        yield
+        return
+    api.force_variant(2, int(rows))
+    try:
+        yield
+    finally:
+        api.force_variant(2, -1)
+
+
+def strip_height(name: str) -> Optional[int]:
+    """Full strip height (rows per wave x waves) of a build variant, from its name."""
+    m = re.search(r"rw(\d+)_nw(\d+)", name)
+    return int(m.group(1)) * int(m.group(2)) if m else None
 
 
 @contextlib.contextmanager
@@ -144,5 +168,55 @@ class Tuner:
             run = lambda: [api.window_sum(S, win[0], win[1], stride,                          # noqa: E731
                                           pixel_type="u8" if pb == 1 else "u16") for S, _ in tables]
         gather, gather_ms = self.tune(1, gkey, run, retune=retune)
+        # strip height of the chosen build variant: its own, three quarters and half of it
+        strip, strip_ms = None, {}
+        th = strip_height(build)
+        if th:
+            skey = bkey + "|" + build
+            ck = "2|" + skey
+            if not retune and ck in self.cache:
+                strip, strip_ms = self.cache[ck]["best"], self.cache[ck]["ms"]
+            else:
+                cands = [th] + sorted({h for h in (th * 3 // 4, th // 2) if 8 <= h < th}, reverse=True)
+                for h in cands:
+                    with forced(0, build), forced_strip(h):
+                        strip_ms[str(h)] = round(time_ms(lambda: batch.build_batched(images, squares, tables=tables),
+                                                         self.reps), 4)
+                best = min(strip_ms, key=strip_ms.get)
+                strip = int(best)
+                self.cache[ck] = {"best": strip, "ms": strip_ms}
+                self._save()
+            strip = None if strip == th else strip
+        # tables and statistics fused in one launch, or the two launches (statistics only)
+        fused, fused_ms = False, {}
+        if squares:
+            fkey = "3|" + gkey + "|" + build + "|" + gather + "|" + str(strip)
+            if not retune and fkey in self.cache:
+                fused, fused_ms = self.cache[fkey]["best"], self.cache[fkey]["ms"]
+            else:
+                def two():
+                    batch.build_batched(images, squares, tables=tables)
+                    batch.mean_std_batched(tables, win[0], win[1], stride, outs=outs)
+
+                def one():
+                    batch.build_stats_batched(images, win[0], win[1], stride, tables=tables, outs=outs)
+                with forced(0, build), forced(1, gather), forced_strip(strip):
+                    fused_ms = {"two_launches": round(time_ms(two, self.reps), 4),
+                                "one_launch": round(time_ms(one, self.reps), 4)}
+                fused = fused_ms["one_launch"] < fused_ms["two_launches"]
+                self.cache[fkey] = {"best": fused, "ms": fused_ms}
+                self._save()
         return {"build": build, "gather": gather, "build_ms": build_ms, "gather_ms": gather_ms,
+                "strip_h": strip, "strip_ms": strip_ms, "fused": fused, "fused_ms": fused_ms,
                 "build_key": bkey, "gather_key": gkey}
+
+    @staticmethod
+    def run_batch(choice: dict, images, squares: bool, win: Tuple[int, int], stride: int, tables, outs) -> None:
+        """The batch with a tune_batch choice: its variants, strip height and launch form."""
+        from . import batch
+        with forced(0, choice["build"]), forced(1, choice["gather"]), forced_strip(choice.get("strip_h")):
+            if choice.get("fused"):
+                batch.build_stats_batched(images, win[0], win[1], stride, tables=tables, outs=outs)
+            else:
+                batch.build_batched(images, squares, tables=tables)
+                batch.mean_std_batched(tables, win[0], win[1], stride, outs=outs)

@@ -1,9 +1,10 @@
 """Many uneven-sized images in one launch: tables for all of them, then window statistics.
 
 sat_build_batched hands the (image, strip) work items of every image to one persistent kernel;
-window_mean_std_batched covers the work items of every image's windows in one grid.  `variant`
-names a compiled kernel variant (see autotune) to use for the call; None keeps the library's
-own choice.
+window_mean_std_batched covers the work items of every image's windows in one grid;
+sat_build_stats_batched does both in one persistent launch, the statistics of each image
+starting as soon as its tables are stored.  `variant` names a compiled kernel variant (see
+autotune) to use for the call; None keeps the library's own choice.
 """
 from __future__ import annotations
 
@@ -93,3 +94,40 @@ def mean_std_batched(tables: Sequence[Tuple[torch.Tensor, torch.Tensor]], h: int
         check(lib.window_mean_std_batched(items, len(tables), h, w, stride, ws.data_ptr(), ws.numel(),
                                           _stream_handle(dev, stream)))
     return outs
+
+
+def build_stats_batched(images: Sequence[torch.Tensor], h: int, w: int, stride: int = 1, with_sum: bool = True,
+                        tables: Optional[Tables] = None, outs: Optional[Stats] = None,
+                        build_variant: Optional[str] = None, gather_variant: Optional[str] = None,
+                        stream: Optional[torch.cuda.Stream] = None) -> Tuple[Tables, Stats]:
+    """Tables (S, Q) of every image and the (sum or None, mean, std) of every image's h x w windows
+    at `stride`, in one persistent launch."""
+    if not images:
+        return [], []
+    dtype = images[0].dtype
+    if dtype not in _PIXEL or any(i.dtype != dtype for i in images):
+        raise ValueError("all images must share one dtype, uint8 or uint16")
+    for i in images:
+        _require_cuda(i, "image")
+    dev = images[0].device
+    if tables is None:
+        tables = alloc_tables(images, True)
+    if len(tables) != len(images) or any(Q is None for _, Q in tables):
+        raise ValueError("one (S, Q) pair per image, squares included")
+    for img, (S, Q) in zip(images, tables):
+        if tuple(S.shape) != tuple(img.shape) or Q.shape != S.shape:
+            raise ValueError("tables must match the images' shapes")
+    if outs is None:
+        outs = alloc_stats(tables, h, w, stride, with_sum)
+    from .api import batch_items
+    from .autotune import forced
+    items = batch_items(images, tables, outs)
+    lib = _lib.load()
+    with forced(0, build_variant), forced(1, gather_variant):
+        need = lib.sat_build_stats_workspace_bytes(items, len(images), _PIXEL[dtype])
+        if need == 0:
+            raise ValueError("invalid image sizes")
+        ws = workspace(need, dev, stream)
+        check(lib.sat_build_stats_batched(items, len(images), _PIXEL[dtype], h, w, stride, ws.data_ptr(), ws.numel(),
+                                          _stream_handle(dev, stream)))
+    return tables, outs

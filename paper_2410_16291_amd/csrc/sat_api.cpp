@@ -15,7 +15,7 @@
 namespace {
 
 thread_local std::string g_err = "no error";
-thread_local int g_force[2] = {-1, -1};
+thread_local int g_force[3] = {-1, -1, -1};   // build variant, gather variant, batch strip height
 
 sat_status fail(sat_status st, const char *fmt, ...) {
     char buf[512];
@@ -769,33 +769,23 @@ sat_status window_moments(const uint64_t *const *tables, int32_t k, sat_dtype pi
 
 static size_t round256(size_t b) { return (b + 255) & ~static_cast<size_t>(255); }
 
-size_t sat_batch_workspace_bytes(const sat_batch_item *items, int32_t n, sat_dtype pixel_type, int with_sq) {
-    if (!items || n < 1) return 0;
-    if (pixel_type != SAT_U8 && pixel_type != SAT_U16) return 0;
-    size_t words = 0;
-    int64_t rows = 0;
-    for (int i = 0; i < n; ++i) {
-        if (items[i].H < 1 || items[i].W < 1 || items[i].H > kMaxDim || items[i].W > kMaxDim) return 0;
-        rows += items[i].H;
-    }
-    for (int align : {16, 4, 1}) {   // whichever variant the rows' alignment selects
-        const int v = choose_build_variant(rows, 0, n, bytes_of(pixel_type), with_sq != 0, align);
-        if (v < 0 || v >= satk::build_variant_count()) return 0;
-        const satk::BuildVariant &var = satk::build_variant(v);
-        size_t w = 0;
-        for (int i = 0; i < n; ++i)
-            w += static_cast<size_t>(state_words_for(var, items[i].H, items[i].W, with_sq != 0, var.th()));
-        if (w > words) words = w;
-    }
-    const size_t descs = round256(static_cast<size_t>(n) *
-                                  (sizeof(satk::BuildDesc) > sizeof(satk::GatherDesc) ? sizeof(satk::BuildDesc)
-                                                                                      : sizeof(satk::GatherDesc)));
-    return sizeof(satk::BuildCtrl) + descs + 8 * words + 256;   // 256: alignment slack
+// Strip height of the images of a batch under variant v: the variant's full height, or the height
+// sat_force_variant(2, rows) set on this thread (tuning), capped at the full height for variants
+// whose waves take fewer rows (adaptive) and ignored for the others.
+static int batch_strip_h(int v) {
+    const satk::BuildVariant &var = satk::build_variant(v);
+    const int f = g_force[2];
+    if (f < 1 || !satk::build_variant_adaptive(v)) return var.th();
+    return f < var.th() ? f : var.th();
 }
 
-sat_status sat_build_batched(const sat_batch_item *items, int32_t n, sat_dtype pixel_type, void *workspace,
-                             size_t workspace_bytes, void *stream) {
-    const char *who = "sat_build_batched";
+// Validation and descriptors of a batch of builds (sat_build_batched and sat_build_stats_batched):
+// every item valid, squared tables on all items or none, the variant for the batch's rows and
+// alignment, one descriptor per item with its lookback words (state_words in all, even) and its
+// first work item (items_total in all).
+static sat_status plan_build_batch(const sat_batch_item *items, int32_t n, sat_dtype pixel_type, const char *who,
+                                   std::vector<satk::BuildDesc> &d, int *variant, int64_t *state_words,
+                                   int64_t *items_total) {
     if (!items || n < 1) return fail(SAT_ERR_ARG, "%s: need at least one item", who);
     if (pixel_type != SAT_U8 && pixel_type != SAT_U16)
         return fail(SAT_ERR_ARG, "%s: pixel_type must be SAT_U8 or SAT_U16", who);
@@ -812,14 +802,37 @@ sat_status sat_build_batched(const sat_batch_item *items, int32_t n, sat_dtype p
             return fail(SAT_ERR_ARG, "%s: item %d: every item or none must have sat_sq", who, i);
         rows += it.H;
     }
-    const bool with_sq = sq;
-    const size_t need = sat_batch_workspace_bytes(items, n, pixel_type, with_sq);
-    if (!workspace || workspace_bytes < need)
-        return fail(SAT_ERR_WORKSPACE, "%s: workspace of %zu bytes is below the %zu needed", who, workspace_bytes,
-                    need);
-    if (reinterpret_cast<uintptr_t>(workspace) % 256)
-        return fail(SAT_ERR_ARG, "%s: workspace must be 256-byte aligned", who);
-    // outputs of different items must not overlap each other or the workspace
+    const int bpp = bytes_of(pixel_type);
+    int align = 16;
+    for (int i = 0; i < n; ++i) {
+        const int a = row_align(items[i].image, items[i].image_pitch, bpp);
+        if (a < align) align = a;
+    }
+    const int v = choose_build_variant(rows, 0, n, bpp, sq, align);
+    if (sat_status st = check_build_variant(v, bpp, sq, who)) return st;
+    const satk::BuildVariant &var = satk::build_variant(v);
+    d.assign(n, satk::BuildDesc{});
+    int64_t off = 0, total = 0;
+    for (int i = 0; i < n; ++i) {
+        const sat_batch_item &it = items[i];
+        fill_desc(d[i], var, it.image, bpp, it.H, it.W, it.image_pitch, it.sat, it.sat_sq, it.sat_pitch,
+                  batch_strip_h(v));
+        const int64_t plane = static_cast<int64_t>(d[i].nstrips) * d[i].Wp;
+        d[i].state_off = off;
+        d[i].state_q_off = off + plane;
+        off += plane * (sq ? 2 : 1);
+        d[i].first_item = total;
+        total += d[i].nstrips;
+    }
+    *variant = v;
+    *state_words = (off + 1) & ~1ll;
+    *items_total = total;
+    return SAT_OK;
+}
+
+// Tables and images of a batch must not overlap the workspace, and no two items' tables overlap.
+static sat_status check_batch_workspace(const sat_batch_item *items, int32_t n, sat_dtype pixel_type, void *workspace,
+                                        size_t workspace_bytes, const char *who) {
     const Span sw{reinterpret_cast<uintptr_t>(workspace), reinterpret_cast<uintptr_t>(workspace) + workspace_bytes};
     const int bpp = bytes_of(pixel_type);
     std::vector<Span> outs;
@@ -833,59 +846,17 @@ sat_status sat_build_batched(const sat_batch_item *items, int32_t n, sat_dtype p
         outs.push_back(a);
         if (b.lo != b.hi) outs.push_back(b);
     }
-    int align = 16;
-    for (int i = 0; i < n; ++i) {
-        const int a = row_align(items[i].image, items[i].image_pitch, bpp);
-        if (a < align) align = a;
-    }
-    const int v = choose_build_variant(rows, 0, n, bpp, with_sq, align);
-    if (sat_status st = check_build_variant(v, bpp, with_sq, who)) return st;
-    const satk::BuildVariant &var = satk::build_variant(v);
-    std::vector<satk::BuildDesc> d(n);
-    int64_t off = 0, items_total = 0;
-    for (int i = 0; i < n; ++i) {
-        const sat_batch_item &it = items[i];
-        fill_desc(d[i], var, it.image, bpp, it.H, it.W, it.image_pitch, it.sat, it.sat_sq, it.sat_pitch, var.th());
-        const int64_t plane = static_cast<int64_t>(d[i].nstrips) * d[i].Wp;
-        d[i].state_off = off;
-        d[i].state_q_off = off + plane;
-        off += plane * (with_sq ? 2 : 1);
-        d[i].first_item = items_total;
-        items_total += d[i].nstrips;
-    }
-    off = (off + 1) & ~1ll;
-    // Layout: [control 256 B][descriptors][state]; the kernels see the state right after the
-    // control header, so the descriptors go at the end of the used state.
-    char *base = static_cast<char *>(workspace);
-    const size_t desc_bytes = round256(static_cast<size_t>(n) * sizeof(satk::BuildDesc));
-    char *dev_desc = base + sizeof(satk::BuildCtrl) + 8 * static_cast<size_t>(off);
-    dev_desc = reinterpret_cast<char *>((reinterpret_cast<uintptr_t>(dev_desc) + 255) & ~static_cast<uintptr_t>(255));
-    if (dev_desc + desc_bytes > base + workspace_bytes)
-        return fail(SAT_ERR_WORKSPACE, "%s: workspace too small for the descriptor table", who);
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    static_assert(sizeof(satk::BuildDesc) % 8 == 0, "descriptors move as 64-bit words");
-    hipError_t e = satk::upload_words(d.data(), static_cast<size_t>(n) * sizeof(satk::BuildDesc), dev_desc, s);
-    if (e != hipSuccess) return hip_fail(e, who);
-    e = satk::launch_build(v, bpp, with_sq, d.data(), n, reinterpret_cast<satk::BuildDesc *>(dev_desc), items_total,
-                           workspace, off, s);
-    if (e != hipSuccess) return hip_fail(e, who);
-    return ok();
+    return SAT_OK;
 }
 
-sat_status window_mean_std_batched(const sat_batch_item *items, int32_t n, int64_t win_h, int64_t win_w,
-                                   int64_t stride, void *workspace, size_t workspace_bytes, void *stream) {
-    const char *who = "window_mean_std_batched";
+// Validation and chain/row-pair plan of the window statistics of a batch (window_mean_std_batched
+// and sat_build_stats_batched): every window fits its image, sat_sq, mean_out and std_out given,
+// outputs inside their pitch and apart from each other, the workspace and every table.
+static sat_status plan_stats_batch(const sat_batch_item *items, int32_t n, int64_t win_h, int64_t win_w,
+                                   int64_t stride, void *workspace, size_t workspace_bytes, const char *who,
+                                   std::vector<satk::GatherDesc> &d, int *gvariant, int64_t *total_items) {
     if (!items || n < 1) return fail(SAT_ERR_ARG, "%s: need at least one item", who);
-    if (!workspace) return fail(SAT_ERR_WORKSPACE, "%s: workspace must be non-NULL", who);
-    if (reinterpret_cast<uintptr_t>(workspace) % 256)
-        return fail(SAT_ERR_ARG, "%s: workspace must be 256-byte aligned", who);
-    // the descriptor table goes after the control header, which keeps the fault word of a build
-    // that shared this workspace intact for sat_workspace_check
-    const size_t desc_bytes = round256(static_cast<size_t>(n) * sizeof(satk::GatherDesc));
-    if (workspace_bytes < sizeof(satk::BuildCtrl) + desc_bytes)
-        return fail(SAT_ERR_WORKSPACE, "%s: workspace of %zu bytes is below the %zu needed", who, workspace_bytes,
-                    sizeof(satk::BuildCtrl) + desc_bytes);
-    std::vector<satk::GatherDesc> d(n);
+    d.assign(n, satk::GatherDesc{});
     const Span sw{reinterpret_cast<uintptr_t>(workspace), reinterpret_cast<uintptr_t>(workspace) + workspace_bytes};
     std::vector<Span> outs;
     for (int i = 0; i < n; ++i) {
@@ -919,12 +890,151 @@ sat_status window_mean_std_batched(const sat_batch_item *items, int32_t n, int64
             if (overlap(o, a) || overlap(o, b)) return fail(SAT_ERR_ARG, "%s: an output overlaps a table", who);
     }
     if (total > 0xffffffffll) return fail(SAT_ERR_ARG, "%s: too many work items", who);
+    *gvariant = v;
+    *total_items = total;
+    return SAT_OK;
+}
+
+size_t sat_batch_workspace_bytes(const sat_batch_item *items, int32_t n, sat_dtype pixel_type, int with_sq) {
+    if (!items || n < 1) return 0;
+    if (pixel_type != SAT_U8 && pixel_type != SAT_U16) return 0;
+    size_t words = 0;
+    int64_t rows = 0;
+    for (int i = 0; i < n; ++i) {
+        if (items[i].H < 1 || items[i].W < 1 || items[i].H > kMaxDim || items[i].W > kMaxDim) return 0;
+        rows += items[i].H;
+    }
+    for (int align : {16, 4, 1}) {   // whichever variant the rows' alignment selects
+        const int v = choose_build_variant(rows, 0, n, bytes_of(pixel_type), with_sq != 0, align);
+        if (v < 0 || v >= satk::build_variant_count()) return 0;
+        const satk::BuildVariant &var = satk::build_variant(v);
+        size_t w = 0;
+        for (int i = 0; i < n; ++i)
+            w += static_cast<size_t>(state_words_for(var, items[i].H, items[i].W, with_sq != 0, batch_strip_h(v)));
+        if (w > words) words = w;
+    }
+    const size_t descs = round256(static_cast<size_t>(n) *
+                                  (sizeof(satk::BuildDesc) > sizeof(satk::GatherDesc) ? sizeof(satk::BuildDesc)
+                                                                                      : sizeof(satk::GatherDesc)));
+    return sizeof(satk::BuildCtrl) + descs + 8 * words + 256;   // 256: alignment slack
+}
+
+sat_status sat_build_batched(const sat_batch_item *items, int32_t n, sat_dtype pixel_type, void *workspace,
+                             size_t workspace_bytes, void *stream) {
+    const char *who = "sat_build_batched";
+    std::vector<satk::BuildDesc> d;
+    int v = 0;
+    int64_t off = 0, items_total = 0;
+    sat_status st = plan_build_batch(items, n, pixel_type, who, d, &v, &off, &items_total);
+    if (st) return st;
+    const bool with_sq = items[0].sat_sq != nullptr;
+    const size_t need = sat_batch_workspace_bytes(items, n, pixel_type, with_sq);
+    if (!workspace || workspace_bytes < need)
+        return fail(SAT_ERR_WORKSPACE, "%s: workspace of %zu bytes is below the %zu needed", who, workspace_bytes,
+                    need);
+    if (reinterpret_cast<uintptr_t>(workspace) % 256)
+        return fail(SAT_ERR_ARG, "%s: workspace must be 256-byte aligned", who);
+    if ((st = check_batch_workspace(items, n, pixel_type, workspace, workspace_bytes, who))) return st;
+    // Layout: [control 256 B][state][descriptors]; the kernels see the state right after the
+    // control header, so the descriptors go at the end of the used state.
+    char *base = static_cast<char *>(workspace);
+    const size_t desc_bytes = round256(static_cast<size_t>(n) * sizeof(satk::BuildDesc));
+    char *dev_desc = base + sizeof(satk::BuildCtrl) + 8 * static_cast<size_t>(off);
+    dev_desc = reinterpret_cast<char *>((reinterpret_cast<uintptr_t>(dev_desc) + 255) & ~static_cast<uintptr_t>(255));
+    if (dev_desc + desc_bytes > base + workspace_bytes)
+        return fail(SAT_ERR_WORKSPACE, "%s: workspace too small for the descriptor table", who);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    static_assert(sizeof(satk::BuildDesc) % 8 == 0, "descriptors move as 64-bit words");
+    hipError_t e = satk::upload_words(d.data(), static_cast<size_t>(n) * sizeof(satk::BuildDesc), dev_desc, s);
+    if (e != hipSuccess) return hip_fail(e, who);
+    e = satk::launch_build(v, bytes_of(pixel_type), with_sq, d.data(), n, reinterpret_cast<satk::BuildDesc *>(dev_desc),
+                           items_total, workspace, off, s);
+    if (e != hipSuccess) return hip_fail(e, who);
+    return ok();
+}
+
+sat_status window_mean_std_batched(const sat_batch_item *items, int32_t n, int64_t win_h, int64_t win_w,
+                                   int64_t stride, void *workspace, size_t workspace_bytes, void *stream) {
+    const char *who = "window_mean_std_batched";
+    if (!items || n < 1) return fail(SAT_ERR_ARG, "%s: need at least one item", who);
+    if (!workspace) return fail(SAT_ERR_WORKSPACE, "%s: workspace must be non-NULL", who);
+    if (reinterpret_cast<uintptr_t>(workspace) % 256)
+        return fail(SAT_ERR_ARG, "%s: workspace must be 256-byte aligned", who);
+    // the descriptor table goes after the control header, which keeps the fault word of a build
+    // that shared this workspace intact for sat_workspace_check
+    const size_t desc_bytes = round256(static_cast<size_t>(n) * sizeof(satk::GatherDesc));
+    if (workspace_bytes < sizeof(satk::BuildCtrl) + desc_bytes)
+        return fail(SAT_ERR_WORKSPACE, "%s: workspace of %zu bytes is below the %zu needed", who, workspace_bytes,
+                    sizeof(satk::BuildCtrl) + desc_bytes);
+    std::vector<satk::GatherDesc> d;
+    int v = 0;
+    int64_t total = 0;
+    sat_status st = plan_stats_batch(items, n, win_h, win_w, stride, workspace, workspace_bytes, who, d, &v, &total);
+    if (st) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
     static_assert(sizeof(satk::GatherDesc) % 8 == 0, "descriptors move as 64-bit words");
     auto *dev_desc = reinterpret_cast<satk::GatherDesc *>(static_cast<char *>(workspace) + sizeof(satk::BuildCtrl));
     hipError_t e = satk::upload_words(d.data(), static_cast<size_t>(n) * sizeof(satk::GatherDesc), dev_desc, s);
     if (e != hipSuccess) return hip_fail(e, who);
     e = satk::launch_mean_std(v, d.data(), n, dev_desc, total, s);
+    if (e != hipSuccess) return hip_fail(e, who);
+    return ok();
+}
+
+size_t sat_build_stats_workspace_bytes(const sat_batch_item *items, int32_t n, sat_dtype pixel_type) {
+    const size_t b = sat_batch_workspace_bytes(items, n, pixel_type, 1);
+    if (b == 0) return 0;
+    // the build's workspace, then the per-image ready counters and the statistics descriptors
+    return b + round256(4 * static_cast<size_t>(n) + 8) + round256(static_cast<size_t>(n) * sizeof(satk::GatherDesc));
+}
+
+sat_status sat_build_stats_batched(const sat_batch_item *items, int32_t n, sat_dtype pixel_type, int64_t win_h,
+                                   int64_t win_w, int64_t stride, void *workspace, size_t workspace_bytes,
+                                   void *stream) {
+    const char *who = "sat_build_stats_batched";
+    std::vector<satk::BuildDesc> bd;
+    int bv = 0;
+    int64_t state_words = 0, build_items = 0;
+    sat_status st = plan_build_batch(items, n, pixel_type, who, bd, &bv, &state_words, &build_items);
+    if (st) return st;
+    if (!items[0].sat_sq) return fail(SAT_ERR_ARG, "%s: every item needs sat_sq", who);
+    const size_t need = sat_build_stats_workspace_bytes(items, n, pixel_type);
+    if (!workspace || workspace_bytes < need)
+        return fail(SAT_ERR_WORKSPACE, "%s: workspace of %zu bytes is below the %zu needed", who, workspace_bytes,
+                    need);
+    if (reinterpret_cast<uintptr_t>(workspace) % 256)
+        return fail(SAT_ERR_ARG, "%s: workspace must be 256-byte aligned", who);
+    if ((st = check_batch_workspace(items, n, pixel_type, workspace, workspace_bytes, who))) return st;
+    std::vector<satk::GatherDesc> gd;
+    int gv = 0;
+    int64_t gather_items = 0;
+    if ((st = plan_stats_batch(items, n, win_h, win_w, stride, workspace, workspace_bytes, who, gd, &gv,
+                               &gather_items)))
+        return st;
+    if (!satk::fused_build_variant(bv) || gd[0].q == 0) {
+        // no fused kernel for this build variant or window (row-pair statistics): two launches
+        if ((st = sat_build_batched(items, n, pixel_type, workspace, workspace_bytes, stream))) return st;
+        return window_mean_std_batched(items, n, win_h, win_w, stride, workspace, workspace_bytes, stream);
+    }
+    // Layout: [control 256 B][lookback words][ready counters][build descriptors][statistics
+    // descriptors]; the launch clears the lookback words and the counters together.
+    const int64_t ready_words = (n + 1) / 2;
+    const int64_t cleared = (state_words + ready_words + 1) & ~1ll;
+    char *base = static_cast<char *>(workspace);
+    auto *ready = reinterpret_cast<unsigned int *>(base + sizeof(satk::BuildCtrl) + 8 * static_cast<size_t>(state_words));
+    char *dev_b = base + sizeof(satk::BuildCtrl) + 8 * static_cast<size_t>(cleared);
+    dev_b = reinterpret_cast<char *>((reinterpret_cast<uintptr_t>(dev_b) + 255) & ~static_cast<uintptr_t>(255));
+    char *dev_g = dev_b + round256(static_cast<size_t>(n) * sizeof(satk::BuildDesc));
+    if (dev_g + static_cast<size_t>(n) * sizeof(satk::GatherDesc) > base + workspace_bytes)
+        return fail(SAT_ERR_WORKSPACE, "%s: workspace too small for the descriptor tables", who);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = satk::upload_words(bd.data(), static_cast<size_t>(n) * sizeof(satk::BuildDesc), dev_b, s);
+    if (e == hipSuccess)
+        e = satk::upload_words(gd.data(), static_cast<size_t>(n) * sizeof(satk::GatherDesc), dev_g, s);
+    if (e == hipSuccess)
+        e = satk::launch_fused(bv, bytes_of(pixel_type), satk::mean_std_chain_v(gv, stride), bd.data(), n,
+                               reinterpret_cast<satk::BuildDesc *>(dev_b), build_items,
+                               reinterpret_cast<satk::GatherDesc *>(dev_g), gather_items, workspace, cleared, ready, s);
     if (e != hipSuccess) return hip_fail(e, who);
     return ok();
 }
@@ -941,6 +1051,9 @@ sat_status sat_workspace_check(void *workspace, void *stream) {
     if (ctrl.fault & 2u)
         return fail(SAT_ERR_DEVICE, "sat_workspace_check: a carried column total leaves no room below 2^62 for "
                     "the band (a carry above its rows_above bound)");
+    if (ctrl.fault & 4u)
+        return fail(SAT_ERR_DEVICE, "sat_workspace_check: a statistics item's wait for its image's tables exceeded "
+                    "its spin bound");
     return ok();
 }
 
@@ -964,7 +1077,13 @@ int32_t sat_variant_supported(int32_t kind, int32_t index, sat_dtype pixel_type,
 }
 
 sat_status sat_force_variant(int32_t kind, int32_t index) {
-    if (kind != 0 && kind != 1) return fail(SAT_ERR_ARG, "sat_force_variant: kind must be 0 or 1");
+    if (kind == 2) {
+        if (index != -1 && (index < 1 || index > 1024))
+            return fail(SAT_ERR_ARG, "sat_force_variant: strip height out of range");
+        g_force[2] = index;
+        return ok();
+    }
+    if (kind != 0 && kind != 1) return fail(SAT_ERR_ARG, "sat_force_variant: kind must be 0, 1 or 2");
     if (index < -1 || index >= sat_variant_count(kind))
         return fail(SAT_ERR_ARG, "sat_force_variant: index out of range");
     g_force[kind] = index;

@@ -41,6 +41,7 @@
 // overflow for a block (BW * 65535 < 2^32; squares of 16-bit pixels are scanned as their two
 // 16-bit halves); the 64-bit carries are added once per pixel.
 #include "sat_internal.h"
+#include "sat_chain_stats.h"
 
 #include <mutex>
 #include <type_traits>
@@ -142,9 +143,27 @@ __device__ __forceinline__ i32x4 make_rsrc(const void *base, uint32_t num_record
 // The compiler does not insert them for gfx950: an overwrite in the next cycle was seen to
 // corrupt lanes 12-15 of every 16-lane group.  Keeping the s_nop inside the same asm block
 // makes the gap independent of scheduling and register allocation.  The asm has no outputs.
-template <bool NT = false>
+// Store policies of table rows: bit 0 non-temporal (the table is read back only after it has
+// left the caches); bit 1 device-coherent (written through this XCD's L2, so that a reader on
+// another XCD sees it once the store has completed, with no write-back of the whole L2).
+constexpr int kStNT = 1;
+constexpr int kStCoherent = 2;
+// Cache-policy bits of the buffer-store builtins: slc (nt) = 2, scc (sc1) = 16.
+constexpr int store_aux(int pol) { return ((pol & kStNT) ? 2 : 0) | ((pol & kStCoherent) ? 16 : 0); }
+
+template <int POL = 0>
 __device__ __forceinline__ void store16_rsrc(u32x4 data, i32x4 rsrc, uint32_t voff, uint32_t soff) {
-    if constexpr (NT)
+    if constexpr (POL == (kStNT | kStCoherent))
+        asm volatile("buffer_store_dwordx4 %0, %1, %2, %3 offen sc1 nt\n\ts_nop 1"
+                     :
+                     : "v"(data), "v"(voff), "s"(rsrc), "s"(soff)
+                     : "memory");
+    else if constexpr (POL == kStCoherent)
+        asm volatile("buffer_store_dwordx4 %0, %1, %2, %3 offen sc1\n\ts_nop 1"
+                     :
+                     : "v"(data), "v"(voff), "s"(rsrc), "s"(soff)
+                     : "memory");
+    else if constexpr (POL == kStNT)
         asm volatile("buffer_store_dwordx4 %0, %1, %2, %3 offen nt\n\ts_nop 1"
                      :
                      : "v"(data), "v"(voff), "s"(rsrc), "s"(soff)
@@ -197,7 +216,7 @@ __device__ __forceinline__ void scan_pair(uint32_t a0, uint32_t a1, uint64_t &pa
 
 // G rows starting at wave row r0 (all valid).  trow: the lane's pixel pair of sub-block 0 of the
 // wave's first row in the LDS tile (rows BW pixels apart).
-template <typename T, int PX, int G, bool SQUARE, bool WIDE, bool VEC, bool NTS>
+template <typename T, int PX, int G, bool SQUARE, bool WIDE, bool VEC, int POL>
 __device__ __forceinline__ void row_group(const T *trow, int r0, int lane, const uint64_t (&u)[PX],
                                           uint64_t (&acc)[PX], uint64_t lcarry, uint64_t &tvec, const i32x4 &rs_blk,
                                           const char *blk0, uint32_t row_recs, uint32_t pitch_bytes) {
@@ -234,7 +253,7 @@ __device__ __forceinline__ void row_group(const T *trow, int r0, int lane, const
             const uint64_t o0 = u[2 * sb] + acc[2 * sb], o1 = u[2 * sb + 1] + acc[2 * sb + 1];
             const uint32_t roff = static_cast<uint32_t>(r0 + g) * pitch_bytes;
             if (VEC) {
-                store16_rsrc<NTS>(u32x4{static_cast<uint32_t>(o0), static_cast<uint32_t>(o0 >> 32),
+                store16_rsrc<POL>(u32x4{static_cast<uint32_t>(o0), static_cast<uint32_t>(o0 >> 32),
                                         static_cast<uint32_t>(o1), static_cast<uint32_t>(o1 >> 32)},
                                   rs_blk, static_cast<uint32_t>(lane) * 16 + sb * 1024, roff);
             } else {
@@ -242,9 +261,9 @@ __device__ __forceinline__ void row_group(const T *trow, int r0, int lane, const
                     const_cast<char *>(blk0 + roff), 0, static_cast<int>(row_recs), kRsrcWord3);
                 const uint32_t voff = static_cast<uint32_t>(lane) * 16 + sb * 1024;
                 __builtin_amdgcn_raw_buffer_store_b64(u32x2{static_cast<uint32_t>(o0), static_cast<uint32_t>(o0 >> 32)},
-                                                      rs_row, voff, 0, NTS ? 2 : 0);
+                                                      rs_row, voff, 0, store_aux(POL));
                 __builtin_amdgcn_raw_buffer_store_b64(u32x2{static_cast<uint32_t>(o1), static_cast<uint32_t>(o1 >> 32)},
-                                                      rs_row, voff + 8, 0, NTS ? 2 : 0);
+                                                      rs_row, voff + 8, 0, store_aux(POL));
             }
             base[g] += readlane(incl[g], 63);
         }
@@ -261,7 +280,7 @@ __device__ __forceinline__ void row_group(const T *trow, int r0, int lane, const
 //     the wave's rows from the block start, records ending at the last valid row's width; row r
 //     is addressed by the scalar offset r * pitch;
 //   ragged: one resource per row covering exactly [block start, W) of that row, 8-byte stores.
-template <typename T, int PX, bool SQUARE, bool WIDE, bool VEC, bool NTS>
+template <typename T, int PX, bool SQUARE, bool WIDE, bool VEC, int POL>
 __device__ __forceinline__ uint64_t block_rows(const T *trow, int lane, const uint64_t (&u)[PX], uint64_t lcarry,
                                                uint64_t *blk0, int rows_ok, uint32_t row_recs, uint32_t pitch_bytes) {
     constexpr int G = 4;
@@ -276,17 +295,18 @@ __device__ __forceinline__ uint64_t block_rows(const T *trow, int lane, const ui
     int r = 0;
 #pragma unroll 1
     for (; r + G <= nvalid; r += G)
-        row_group<T, PX, G, SQUARE, WIDE, VEC, NTS>(trow, r, lane, u, acc, lcarry, tvec, rs_blk, b0, row_recs,
+        row_group<T, PX, G, SQUARE, WIDE, VEC, POL>(trow, r, lane, u, acc, lcarry, tvec, rs_blk, b0, row_recs,
                                                     pitch_bytes);
 #pragma unroll 1
     for (; r < nvalid; ++r)
-        row_group<T, PX, 1, SQUARE, WIDE, VEC, NTS>(trow, r, lane, u, acc, lcarry, tvec, rs_blk, b0, row_recs,
+        row_group<T, PX, 1, SQUARE, WIDE, VEC, POL>(trow, r, lane, u, acc, lcarry, tvec, rs_blk, b0, row_recs,
                                                     pitch_bytes);
     return tvec;
 }
 
-template <typename T, bool SQ, int PX, int RW, int NW, int MODE, bool NTS = false>
+template <typename T, bool SQ, int PX, int RW, int NW, int MODE, bool NTS = false, bool COH = false>
 struct Build {
+    static constexpr int POL = (NTS ? kStNT : 0) | (COH ? kStCoherent : 0);   // table store policy
     static constexpr int TH = RW * NW;                       // strip height
     static constexpr int BW = 64 * PX;                       // block width
     static constexpr int NT = NW * 64;                       // threads per workgroup
@@ -763,11 +783,11 @@ struct Build {
             const uint32_t row_recs = static_cast<uint32_t>((d.W - xb) * 8);   // bytes from block start to W
             const T *trow = reinterpret_cast<const T *>(sm.tile) + row0 * BW + 2 * lane;
             if (vec) {
-                lrow += block_rows<T, PX, false, false, true, NTS>(trow, lane, u, lrow, S_w + xb, rows_ok, row_recs, pitch_bytes);
-                if (SQ) lrow_q += block_rows<T, PX, true, WIDE_SQ, true, NTS>(trow, lane, uq, lrow_q, Q_w + xb, rows_ok, row_recs, pitch_bytes);
+                lrow += block_rows<T, PX, false, false, true, POL>(trow, lane, u, lrow, S_w + xb, rows_ok, row_recs, pitch_bytes);
+                if (SQ) lrow_q += block_rows<T, PX, true, WIDE_SQ, true, POL>(trow, lane, uq, lrow_q, Q_w + xb, rows_ok, row_recs, pitch_bytes);
             } else {
-                lrow += block_rows<T, PX, false, false, false, NTS>(trow, lane, u, lrow, S_w + xb, rows_ok, row_recs, pitch_bytes);
-                if (SQ) lrow_q += block_rows<T, PX, true, WIDE_SQ, false, NTS>(trow, lane, uq, lrow_q, Q_w + xb, rows_ok, row_recs, pitch_bytes);
+                lrow += block_rows<T, PX, false, false, false, POL>(trow, lane, u, lrow, S_w + xb, rows_ok, row_recs, pitch_bytes);
+                if (SQ) lrow_q += block_rows<T, PX, true, WIDE_SQ, false, POL>(trow, lane, uq, lrow_q, Q_w + xb, rows_ok, row_recs, pitch_bytes);
             }
 
             // Replace the tile with the next block's.
@@ -1006,11 +1026,11 @@ struct Build2 {
         const uint32_t row_recs = static_cast<uint32_t>((d.W - xb) * 8);
         const T *trow = reinterpret_cast<const T *>(sm.tile[tb] + wave * rw * ROWB / 4) + 2 * lane;
         if (vec) {
-            lrow += block_rows<T, PX, false, false, true, NTS>(trow, lane, u, lrow, S_w + xb, rows_ok, row_recs, pitch_bytes);
-            if (SQ) lrow_q += block_rows<T, PX, true, B1::WIDE_SQ, true, NTS>(trow, lane, uq, lrow_q, Q_w + xb, rows_ok, row_recs, pitch_bytes);
+            lrow += block_rows<T, PX, false, false, true, NTS ? kStNT : 0>(trow, lane, u, lrow, S_w + xb, rows_ok, row_recs, pitch_bytes);
+            if (SQ) lrow_q += block_rows<T, PX, true, B1::WIDE_SQ, true, NTS ? kStNT : 0>(trow, lane, uq, lrow_q, Q_w + xb, rows_ok, row_recs, pitch_bytes);
         } else {
-            lrow += block_rows<T, PX, false, false, false, NTS>(trow, lane, u, lrow, S_w + xb, rows_ok, row_recs, pitch_bytes);
-            if (SQ) lrow_q += block_rows<T, PX, true, B1::WIDE_SQ, false, NTS>(trow, lane, uq, lrow_q, Q_w + xb, rows_ok, row_recs, pitch_bytes);
+            lrow += block_rows<T, PX, false, false, false, NTS ? kStNT : 0>(trow, lane, u, lrow, S_w + xb, rows_ok, row_recs, pitch_bytes);
+            if (SQ) lrow_q += block_rows<T, PX, true, B1::WIDE_SQ, false, NTS ? kStNT : 0>(trow, lane, uq, lrow_q, Q_w + xb, rows_ok, row_recs, pitch_bytes);
         }
     }
 
@@ -1344,14 +1364,14 @@ struct BuildPow {
                 acc[2 * sb + 1] += b + pair;
                 const uint64_t o0 = u[2 * sb] + acc[2 * sb], o1 = u[2 * sb + 1] + acc[2 * sb + 1];
                 if (vec) {
-                    store16_rsrc<NTS>(u32x4{static_cast<uint32_t>(o0), static_cast<uint32_t>(o0 >> 32),
+                    store16_rsrc<NTS ? kStNT : 0>(u32x4{static_cast<uint32_t>(o0), static_cast<uint32_t>(o0 >> 32),
                                             static_cast<uint32_t>(o1), static_cast<uint32_t>(o1 >> 32)},
                                       rs_blk, voff + sb * 1024, roff);
                 } else {
                     __builtin_amdgcn_raw_buffer_store_b64(u32x2{static_cast<uint32_t>(o0), static_cast<uint32_t>(o0 >> 32)},
-                                                          rs_row, voff + sb * 1024, 0, NTS ? 2 : 0);
+                                                          rs_row, voff + sb * 1024, 0, store_aux(NTS ? kStNT : 0));
                     __builtin_amdgcn_raw_buffer_store_b64(u32x2{static_cast<uint32_t>(o1), static_cast<uint32_t>(o1 >> 32)},
-                                                          rs_row, voff + sb * 1024 + 8, 0, NTS ? 2 : 0);
+                                                          rs_row, voff + sb * 1024 + 8, 0, store_aux(NTS ? kStNT : 0));
                 }
                 base += readlane(incl, 63);
             }
@@ -1475,6 +1495,77 @@ void build_kernel(const BuildDesc *__restrict__ many, int n, long long total_ite
         }
         const BuildDesc d = many[lo];   // by value: kept in registers, not reloaded after every store
         B::strip(d, __builtin_amdgcn_readfirstlane(static_cast<int>(t - d.first_item)), state, &ctrl->fault, sm);
+    }
+}
+
+// Batched tables and window statistics in one persistent launch.  Tickets 0 .. build_items-1 are
+// the (image, strip) items of the table build, image by image; the tickets after them are the
+// chain-walk mean/std items of the images' windows, image by image.  A build item, once its
+// strip's table rows are stored, releases them at agent scope and counts the strip in its image's
+// ready counter.  A statistics item of image i first waits (bounded; bit 2 of the fault word on
+// timeout) until every strip of image i is counted, then acquires; a workgroup acquires each image
+// once, as its items come in ticket order.  Every wait is on items with smaller tickets, handed out
+// before it, so progress never depends on dispatch order, and the statistics of early images run
+// while the last strips of later ones are still being built.
+template <typename T, int PX, int RW, int NW, bool NTS, int V>
+__global__ __launch_bounds__(NW * 64) void fused_kernel(const BuildDesc *__restrict__ bd,
+                                                        const GatherDesc *__restrict__ gd, int n,
+                                                        long long build_items, long long total_items, uint64_t *state,
+                                                        BuildCtrl *ctrl, unsigned int *ready) {
+    static_assert(NW * 64 == 256, "statistics items run on 256 threads");
+    using B = Build<T, true, PX, RW, NW, MODE_LOOKBACK, NTS, true>;   // device-coherent table stores
+    __shared__ typename B::Smem sm;
+    int acquired = -1;
+    for (;;) {
+        if (threadIdx.x == 0) sm.ticket = static_cast<long long>(atomicAdd(&ctrl->ticket, 1ull));
+        __syncthreads();
+        const long long t = static_cast<long long>(__builtin_amdgcn_readfirstlane(static_cast<int>(sm.ticket))) |
+                            (static_cast<long long>(__builtin_amdgcn_readfirstlane(static_cast<int>(sm.ticket >> 32))) << 32);
+        __syncthreads();
+        if (t >= total_items) return;
+        if (t < build_items) {
+            int lo = 0, hi = n - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (bd[mid].first_item <= t) lo = mid;
+                else hi = mid - 1;
+            }
+            const BuildDesc d = bd[lo];
+            B::strip(d, __builtin_amdgcn_readfirstlane(static_cast<int>(t - d.first_item)), state, &ctrl->fault, sm);
+            // Release: the strip's table stores are device-coherent (written through the L2), so
+            // once each wave has seen its stores complete they are visible on every XCD; no
+            // write-back of the whole L2 (an agent-scope release fence) is needed, which per strip
+            // cost a quarter of the launch.
+            __builtin_amdgcn_s_waitcnt(0x0070);                  // vmcnt(0), lgkmcnt(0)
+            __syncthreads();
+            if (threadIdx.x == 0) __hip_atomic_fetch_add(ready + lo, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            const long long item = t - build_items;
+            int lo = 0, hi = n - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (gd[mid].first_item <= item) lo = mid;
+                else hi = mid - 1;
+            }
+            if (lo != acquired) {
+                if (threadIdx.x == 0) {
+                    const unsigned int need = static_cast<unsigned int>(bd[lo].nstrips);
+                    uint32_t spins = 0;
+                    while (__hip_atomic_load(ready + lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+                        if (++spins > kSpinLimit) {
+                            atomicOr(&ctrl->fault, 4u);
+                            break;
+                        }
+                        __builtin_amdgcn_s_sleep(2);
+                    }
+                }
+                __syncthreads();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                acquired = lo;
+            }
+            const GatherDesc d = gd[lo];
+            chain_stats_item<V>(d, item - d.first_item);
+        }
     }
 }
 
@@ -1967,6 +2058,71 @@ int build_variant_adaptive(int v) { return (v >= 0 && v < kNumVariants) ? kAdapt
 int build_variant_capacity(int v, int bpp, bool sq) {
     if (bpp == 1) return sq ? capacity_variant<uint8_t, true>(v) : capacity_variant<uint8_t, false>(v);
     return sq ? capacity_variant<uint16_t, true>(v) : capacity_variant<uint16_t, false>(v);
+}
+
+bool fused_build_variant(int variant) { return variant == 9 || variant == 1 || variant == 2; }
+
+namespace {
+
+template <typename T, int PX, int RW, int NW, bool NTS>
+hipError_t launch_fused_typed(int v, const BuildDesc *bdescs, const BuildDesc *dev_bdescs, int n, int64_t build_items,
+                              const GatherDesc *dev_gdescs, int64_t gather_items, void *workspace, int64_t state_words,
+                              unsigned int *ready, hipStream_t stream) {
+    BuildCtrl *ctrl = static_cast<BuildCtrl *>(workspace);
+    uint64_t *state = reinterpret_cast<uint64_t *>(static_cast<char *>(workspace) + sizeof(BuildCtrl));
+    const long long pairs = (state_words + 1) / 2;
+    const long long blocks = pairs > 0 ? (pairs + 255) / 256 : 1;
+    const unsigned cgrid = static_cast<unsigned>(blocks < 8192 ? blocks : 8192);
+    hipLaunchKernelGGL(clear_kernel, dim3(cgrid), dim3(256), 0, stream, state, static_cast<long long>(state_words),
+                       ctrl, bdescs[0], static_cast<BuildDesc *>(nullptr));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const void *k1 = reinterpret_cast<const void *>(&fused_kernel<T, PX, RW, NW, NTS, 1>);
+    const void *k2 = reinterpret_cast<const void *>(&fused_kernel<T, PX, RW, NW, NTS, 2>);
+    const void *k4 = reinterpret_cast<const void *>(&fused_kernel<T, PX, RW, NW, NTS, 4>);
+    const void *k = v == 1 ? k1 : v == 4 ? k4 : k2;
+    static int cap[3] = {0, 0, 0};
+    const int ci = v == 1 ? 0 : v == 4 ? 2 : 1;
+    if (cap[ci] == 0) cap[ci] = resident_capacity(k, NW * 64);
+    const long long total = static_cast<long long>(build_items + gather_items);
+    const unsigned grid = static_cast<unsigned>(total < cap[ci] ? total : cap[ci]);
+    if (v == 1)
+        hipLaunchKernelGGL((fused_kernel<T, PX, RW, NW, NTS, 1>), dim3(grid), dim3(NW * 64), 0, stream, dev_bdescs,
+                           dev_gdescs, n, static_cast<long long>(build_items), total, state, ctrl, ready);
+    else if (v == 4)
+        hipLaunchKernelGGL((fused_kernel<T, PX, RW, NW, NTS, 4>), dim3(grid), dim3(NW * 64), 0, stream, dev_bdescs,
+                           dev_gdescs, n, static_cast<long long>(build_items), total, state, ctrl, ready);
+    else
+        hipLaunchKernelGGL((fused_kernel<T, PX, RW, NW, NTS, 2>), dim3(grid), dim3(NW * 64), 0, stream, dev_bdescs,
+                           dev_gdescs, n, static_cast<long long>(build_items), total, state, ctrl, ready);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fused_t(int variant, int v, const BuildDesc *bdescs, const BuildDesc *dev_bdescs, int n,
+                          int64_t build_items, const GatherDesc *dev_gdescs, int64_t gather_items, void *workspace,
+                          int64_t state_words, unsigned int *ready, hipStream_t stream) {
+    switch (variant) {
+        case 9: return launch_fused_typed<T, 4, 16, 4, true>(v, bdescs, dev_bdescs, n, build_items, dev_gdescs,
+                                                             gather_items, workspace, state_words, ready, stream);
+        case 1: return launch_fused_typed<T, 4, 16, 4, false>(v, bdescs, dev_bdescs, n, build_items, dev_gdescs,
+                                                              gather_items, workspace, state_words, ready, stream);
+        case 2: return launch_fused_typed<T, 4, 8, 4, false>(v, bdescs, dev_bdescs, n, build_items, dev_gdescs,
+                                                             gather_items, workspace, state_words, ready, stream);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_fused(int variant, int bpp, int v, const BuildDesc *bdescs, int n, const BuildDesc *dev_bdescs,
+                        int64_t build_items, const GatherDesc *dev_gdescs, int64_t gather_items, void *workspace,
+                        int64_t state_words, unsigned int *ready, hipStream_t stream) {
+    if (bpp == 1)
+        return launch_fused_t<uint8_t>(variant, v, bdescs, dev_bdescs, n, build_items, dev_gdescs, gather_items,
+                                       workspace, state_words, ready, stream);
+    return launch_fused_t<uint16_t>(variant, v, bdescs, dev_bdescs, n, build_items, dev_gdescs, gather_items,
+                                    workspace, state_words, ready, stream);
 }
 
 hipError_t launch_build(int variant, int bpp, bool sq, const BuildDesc *descs, int n,

@@ -37,7 +37,8 @@ struct BuildDesc {
 struct BuildCtrl {
     unsigned long long ticket;   // next work item
     unsigned int fault;          // bit 0: a lookback wait hit its spin bound; bit 1: a carried
-                                 // column total reached 2^62 (band builds)
+                                 // column total reached 2^62 (band builds); bit 2: a statistics
+                                 // item's wait for its image's tables hit its spin bound (fused)
     unsigned int pad0;
     BuildDesc one;               // descriptor of a single-image build (written by the clear kernel)
     unsigned char pad[256 - 16 - sizeof(BuildDesc)];
@@ -147,5 +148,18 @@ hipError_t launch_window_sum_multi(int variant, const GatherDesc *d, int n, bool
 int64_t plan_mean_std(int variant, GatherDesc *descs, int n);
 hipError_t launch_mean_std(int variant, const GatherDesc *descs, int n, const GatherDesc *dev_descs,
                            int64_t total_items, hipStream_t stream);
+// Outputs per thread (1, 2 or 4) of the chain-walk mean/std items of gather variant `variant`.
+int mean_std_chain_v(int variant, int64_t stride);
+
+// Batched tables of pixels and squares and the window mean/std of every image in ONE persistent
+// launch (build variant `variant`, one of those fused_build_variant accepts; `v` the chain
+// outputs per thread).  bdescs / dev_bdescs: one build descriptor per image (host / device copy),
+// build_items strips in all; gdescs: the images' chain mean/std descriptors (planned by
+// plan_mean_std, q > 0), gather_items items in all, device copy dev_gdescs.  ready: n counters
+// inside the cleared state words (the launch zeroes them with the lookback state).
+bool fused_build_variant(int variant);
+hipError_t launch_fused(int variant, int bpp, int v, const BuildDesc *bdescs, int n, const BuildDesc *dev_bdescs,
+                        int64_t build_items, const GatherDesc *dev_gdescs, int64_t gather_items, void *workspace,
+                        int64_t state_words, unsigned int *ready, hipStream_t stream);
 
 }  // namespace satk

@@ -173,6 +173,43 @@ def test_multi_and_batch_validation(lib):
     assert b"item 1" in lib.sat_last_error()
 
 
+def test_fused_build_stats_validation(lib):
+    """sat_build_stats_batched: every build and statistics argument error, before any HIP call."""
+    items = (BatchItem * 2)()
+    for i in range(2):
+        o = i * 0x1000000
+        items[i].image, items[i].H, items[i].W, items[i].image_pitch = IMG + o, 50, 60, 64
+        items[i].sat, items[i].sat_sq, items[i].sat_pitch = SAT + o, SQ + o, 64
+        items[i].sum_out, items[i].mean_out, items[i].std_out, items[i].out_pitch = OUT + o, OUT2 + o, OUT3 + o, 64
+    need = lib.sat_build_stats_workspace_bytes(items, 2, SAT_U16)
+    assert need > lib.sat_batch_workspace_bytes(items, 2, SAT_U16, 1)
+    assert lib.sat_build_stats_workspace_bytes(items, 0, SAT_U16) == 0
+
+    def call(n=2, ptype=SAT_U16, h=8, w=8, s=2, ws=WS, wsb=None):
+        return lib.sat_build_stats_batched(items, n, ptype, h, w, s, ws, need if wsb is None else wsb, None)
+    assert call(n=0) == SAT_ERR_ARG
+    assert call(ptype=SAT_U32) == SAT_ERR_ARG
+    assert call(wsb=need - 1) == SAT_ERR_WORKSPACE
+    assert call(ws=None) == SAT_ERR_WORKSPACE
+    assert call(ws=WS + 16) == SAT_ERR_ARG                           # not 256-byte aligned
+    assert call(h=51) == SAT_ERR_WINDOW
+    assert call(s=0) == SAT_ERR_ARG
+    items[1].mean_out = 0
+    assert call() == SAT_ERR_ARG
+    items[1].mean_out = OUT2 + 0x1000000
+    items[1].std_out = items[0].std_out                              # outputs of two items overlap
+    assert call() == SAT_ERR_ARG
+    items[1].std_out = OUT3 + 0x1000000
+    items[0].sum_out = SQ + 0x1000000 + 8                            # an output overlaps a table
+    assert call() == SAT_ERR_ARG
+    items[0].sum_out = OUT
+    items[1].sat_sq = 0                                              # squares needed on every item
+    assert call() == SAT_ERR_ARG
+    items[0].sat_sq = 0
+    assert call() == SAT_ERR_ARG
+    assert b"sat_sq" in lib.sat_last_error()
+
+
 def test_batched_mean_std_workspace_keeps_the_control_header(lib):
     """window_mean_std_batched puts its descriptor table after the 256-byte control header (whose
     fault word sat_workspace_check reads), so it needs 256 bytes more than the table itself; the

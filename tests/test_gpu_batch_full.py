@@ -2,7 +2,8 @@
 log-normal images with sides uniform on 1000..12000 (about 2.5 Gpx), tables of pixels and squares
 in one persistent build launch, then the sum, mean and std of every 64 x 64 window at stride 4 in
 one launch -- with the library's built-in kernel choice, the autotuner's choice, and the fastest
-build and gather variants the tuner timed after its choice.  Every
+build and gather variants the tuner timed after its choice -- and tables and statistics fused in
+one launch (sat_build_stats_batched).  Every
 table entry and every output of every image is compared; images are checked in parallel, one
 image per worker at a time, to bound host memory."""
 import os
@@ -66,6 +67,10 @@ def test_batched_64_images_every_output_default_and_tuned(capsys):
         t = batch.build_batched(imgs, True, variant=bv)
         runs[name] = (t, batch.mean_std_batched(t, H_WIN, W_WIN, STRIDE, variant=gv))
         torch.cuda.synchronize()
+    say("fused: tables and statistics in one launch")
+    runs["fused"] = batch.build_stats_batched(imgs, H_WIN, W_WIN, STRIDE)
+    torch.cuda.synchronize()
+    api.workspace_check(api.workspace(0, dev))
     for name, (tables, _) in runs.items():
         for i, (S, Q) in enumerate(tables):
             assert tuple(S.shape) == sizes[i] and tuple(Q.shape) == sizes[i], (name, i)

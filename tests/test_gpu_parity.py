@@ -410,8 +410,11 @@ def test_autotuned_batch_matches_oracle(tmp_path):
     assert set(choice["build_ms"]) == set(api.variants(0, "u16", True))
     again = autotune.Tuner(path=str(tmp_path / "tune.json")).tune_batch(imgs, squares=True, win=(32, 48), stride=2)
     assert again["build"] == choice["build"] and again["gather_ms"] == choice["gather_ms"]    # from the cache
-    tables = batch.build_batched(imgs, True, variant=choice["build"])
-    outs = batch.mean_std_batched(tables, 32, 48, 2, variant=choice["gather"])
+    assert choice["strip_h"] is None or 8 <= choice["strip_h"] < autotune.strip_height(choice["build"])
+    assert set(choice["fused_ms"]) == {"one_launch", "two_launches"}
+    tables = batch.alloc_tables(imgs, True)
+    outs = batch.alloc_stats(tables, 32, 48, 2)
+    autotune.Tuner.run_batch(choice, imgs, True, (32, 48), 2, tables, outs)
     torch.cuda.synchronize()
     for i, img_np in enumerate(imgs_np):
         ref_S, ref_Q = oracle.sat(img_np, squares=True)
@@ -422,6 +425,69 @@ def test_autotuned_batch_matches_oracle(tmp_path):
         assert np.array_equal(to_host(outs[i][0]), sums), i
         assert np.array_equal(to_host(outs[i][1]), ref_mean), i
         check_std(to_host(outs[i][2]), ref_std)
+
+
+def fused_check(imgs_np, tables, outs, h, w, s, what):
+    for i, img_np in enumerate(imgs_np):
+        ref_S, ref_Q = oracle.sat(img_np, squares=True)
+        assert np.array_equal(to_host(tables[i][0]), ref_S), (what, i, "S")
+        assert np.array_equal(to_host(tables[i][1]), ref_Q), (what, i, "Q")
+        sums = oracle.window_sum_sat(ref_S, h, w, s)
+        ref_mean, ref_std = oracle.mean_std(sums, oracle.window_sum_sat(ref_Q, h, w, s), h * w)
+        if outs[i][0] is not None:
+            assert np.array_equal(to_host(outs[i][0]), sums), (what, i, "sum")
+        assert np.array_equal(to_host(outs[i][1]), ref_mean), (what, i, "mean")
+        check_std(to_host(outs[i][2]), ref_std)
+
+
+@pytest.mark.parametrize("dtype", ["u16", "u8"])
+def test_fused_build_and_stats_every_variant(dtype):
+    """sat_build_stats_batched (tables and window statistics in one launch) against the oracle, for
+    every build variant of the fused kernel and every chain gather variant, then a window whose
+    height is not a multiple of the stride (the two-launch path), then a second call on the same
+    tables with other images (no result may come from the first call)."""
+    from paper_2410_16291_amd import batch
+    imgs_np = synth.uneven_batch(7, lo=70, hi=700, seed=31)
+    if dtype == "u8":
+        imgs_np = [(i % 256).astype(np.uint8) for i in imgs_np]
+    imgs = [to_device(i) for i in imgs_np]
+    fused = ["lookback_nt_px4_rw16_nw4", "lookback_px4_rw16_nw4", "lookback_px4_rw8_nw4"]
+    chains = [g for g in api.variants(1) if g.startswith("chain_v")]
+    assert chains
+    for bv in fused:
+        for gv in chains:
+            print("case: fused", dtype, bv, gv, flush=True)
+            tables, outs = batch.build_stats_batched(imgs, 32, 48, 4, build_variant=bv, gather_variant=gv)
+            torch.cuda.synchronize()
+            fused_check(imgs_np, tables, outs, 32, 48, 4, (bv, gv))
+    print("case: fused, row-pair window 30x20 stride 4", flush=True)
+    tables, outs = batch.build_stats_batched(imgs, 30, 20, 4)
+    torch.cuda.synchronize()
+    fused_check(imgs_np, tables, outs, 30, 20, 4, "row-pair")
+    print("case: fused, second call on the same tables", flush=True)
+    other_np = [np.ascontiguousarray(np.flipud(i)) for i in imgs_np]
+    tables2, outs2 = batch.build_stats_batched([to_device(i) for i in other_np], 32, 48, 4, tables=tables,
+                                               with_sum=False)
+    torch.cuda.synchronize()
+    fused_check(other_np, tables2, outs2, 32, 48, 4, "second call")
+
+
+def test_batched_build_forced_strip_heights():
+    """Batched builds at strip heights the tuner may set (sat_force_variant kind 2), including
+    heights that leave waves with partial or no rows."""
+    from paper_2410_16291_amd import autotune, batch
+    imgs_np = synth.uneven_batch(5, lo=60, hi=500, seed=33)
+    imgs = [to_device(i) for i in imgs_np]
+    refs = [oracle.sat(i, squares=True) for i in imgs_np]
+    for name in ("lookback_nt_px4_rw16_nw4", "lookback_px4_rw8_nw4"):
+        for rows in (48, 32, 13, 5, 1):
+            print("case: strip height", name, rows, flush=True)
+            with autotune.forced(0, name), autotune.forced_strip(rows):
+                tables = batch.build_batched(imgs, True)
+            torch.cuda.synchronize()
+            for i, (ref_S, ref_Q) in enumerate(refs):
+                assert np.array_equal(to_host(tables[i][0]), ref_S), (name, rows, i)
+                assert np.array_equal(to_host(tables[i][1]), ref_Q), (name, rows, i)
 
 
 def test_device_generator_through_the_path():
