@@ -305,7 +305,10 @@ sat_status window_moments(const uint64_t *const *tables, int32_t k, sat_dtype pi
  * will use (-1 restores the built-in choice).  Kind 2 sets the strip height (rows, 1..1024) of
  * the batched builds on this thread, capped at the variant's own height and used only by
  * variants that take shorter strips (-1 restores the variant's height; sat_batch_workspace_bytes
- * follows it).  Used by the tile-shape tuner. */
+ * follows it).  Kind 3 (tests only) sets a nonzero seed on this thread that makes later builds
+ * sleep a pseudo-random time before every lookback publication, to perturb the order in which
+ * strips finish; 0 turns it off.  Results are unchanged.  Used by the tile-shape tuner and the
+ * tests. */
 int32_t sat_variant_count(int32_t kind);
 const char *sat_variant_name(int32_t kind, int32_t index);
 sat_status sat_force_variant(int32_t kind, int32_t index);

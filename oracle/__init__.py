@@ -23,9 +23,10 @@ _p = ctypes.c_void_p
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(_build.LIB):
+        path = os.environ.get("SAT_ORACLE_LIBRARY") or _build.LIB   # another build of sat_oracle.c (sanitizers)
+        if path == _build.LIB and not os.path.exists(path):
             _build.build()
-        lib = ctypes.CDLL(_build.LIB)
+        lib = ctypes.CDLL(path)
         lib.oracle_window_shape.argtypes = [_i64] * 5 + [_p, _p]
         lib.oracle_sat.argtypes = [_p, ctypes.c_int, _i64, _i64, _i64, _p, _p]
         lib.oracle_window_sum_sat.argtypes = [_p] + [_i64] * 5 + [_p]

@@ -7,7 +7,8 @@ import ctypes
 import os
 import threading
 
-LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsat.so")
+# SAT_LIBRARY names another build of the same library (the tests' sanitizer build of the host code).
+LIB_PATH = os.environ.get("SAT_LIBRARY") or os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsat.so")
 
 SAT_OK, SAT_ERR_ARG, SAT_ERR_WINDOW, SAT_ERR_OVERFLOW, SAT_ERR_WORKSPACE, SAT_ERR_HIP, SAT_ERR_DEVICE = range(7)
 STATUS_NAMES = {0: "SAT_OK", 1: "SAT_ERR_ARG", 2: "SAT_ERR_WINDOW", 3: "SAT_ERR_OVERFLOW",

@@ -15,7 +15,8 @@
 namespace {
 
 thread_local std::string g_err = "no error";
-thread_local int g_force[3] = {-1, -1, -1};   // build variant, gather variant, batch strip height
+// build variant, gather variant, batch strip height, lookback stress seed (0: off)
+thread_local int g_force[4] = {-1, -1, -1, 0};
 
 sat_status fail(sat_status st, const char *fmt, ...) {
     char buf[512];
@@ -301,6 +302,7 @@ void fill_desc(satk::BuildDesc &d, const satk::BuildVariant &v, const void *imag
     const bool sa = reinterpret_cast<uintptr_t>(sat) % 16 == 0 &&
                     (!sat_sq || reinterpret_cast<uintptr_t>(sat_sq) % 16 == 0);
     d.sat_vec = (sa && spitch % 2 == 0) ? 1 : 0;
+    d.stress = static_cast<uint32_t>(g_force[3]);
 }
 
 sat_status validate_build_item(const void *image, sat_dtype pixel_type, int64_t H, int64_t W, int64_t ipitch,
@@ -1077,13 +1079,18 @@ int32_t sat_variant_supported(int32_t kind, int32_t index, sat_dtype pixel_type,
 }
 
 sat_status sat_force_variant(int32_t kind, int32_t index) {
+    if (kind == 3) {
+        if (index < 0) return fail(SAT_ERR_ARG, "sat_force_variant: stress seed must be >= 0");
+        g_force[3] = index;
+        return ok();
+    }
     if (kind == 2) {
         if (index != -1 && (index < 1 || index > 1024))
             return fail(SAT_ERR_ARG, "sat_force_variant: strip height out of range");
         g_force[2] = index;
         return ok();
     }
-    if (kind != 0 && kind != 1) return fail(SAT_ERR_ARG, "sat_force_variant: kind must be 0, 1 or 2");
+    if (kind != 0 && kind != 1) return fail(SAT_ERR_ARG, "sat_force_variant: kind must be 0, 1, 2 or 3");
     if (index < -1 || index >= sat_variant_count(kind))
         return fail(SAT_ERR_ARG, "sat_force_variant: index out of range");
     g_force[kind] = index;

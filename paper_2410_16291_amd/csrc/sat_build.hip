@@ -118,6 +118,23 @@ __device__ __forceinline__ uint64_t readlane(uint64_t v, int l) {
            readlane(static_cast<uint32_t>(v), l);
 }
 
+// Test-only perturbation of the lookback: with a nonzero seed (BuildDesc::stress) a wave sleeps a
+// pseudo-random number of steps (0..31 x 512 cycles, hashed from the seed, strip, block and phase)
+// before it publishes a lookback word or a fused ready count.  Publication order then varies
+// from run to run while every wait stays bounded and ticket order keeps progress guaranteed.
+__device__ __forceinline__ void stress_delay(uint32_t seed, int strip, int64_t xb, uint32_t phase) {
+    if (seed == 0) return;
+    uint32_t h = seed ^ (static_cast<uint32_t>(strip) * 0x9E3779B1u) ^ (static_cast<uint32_t>(xb) * 0x85EBCA77u) ^
+                 (phase * 0xC2B2AE3Du);
+    h ^= h >> 15;
+    h *= 0x2C1B3C6Du;
+    h ^= h >> 12;
+    h *= 0x297A2D39u;
+    h ^= h >> 15;
+    const uint32_t n = h & 31u;
+    for (uint32_t i = 0; i < n; ++i) __builtin_amdgcn_s_sleep(8);
+}
+
 __device__ __forceinline__ void store_state(uint64_t *p, uint64_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -491,6 +508,7 @@ struct Build {
         for (int p = 0; p < PX; ++p) { v[p] = 0; vq[p] = 0; }
         if (strip == 0) {
             seed(d, xb, lane, v, vq, fault);
+            stress_delay(d.stress, strip, xb, 0);
 #pragma unroll
             for (int p = 0; p < PX; ++p) {
                 store_state(mine + lslot(p), kStPrefix | (v[p] + a[p]));
@@ -499,6 +517,7 @@ struct Build {
             emit_total(d, strip, xb, lane, v, a, vq, aq);
             return;
         }
+        stress_delay(d.stress, strip, xb, 1);
 #pragma unroll
         for (int p = 0; p < PX; ++p) {
             store_state(mine + lslot(p), kStAggregate | a[p]);
@@ -548,6 +567,7 @@ struct Build {
             if (__all(done == kAll)) break;
             --j;
         }
+        stress_delay(d.stress, strip, xb, 2);
 #pragma unroll
         for (int p = 0; p < PX; ++p) {
             store_state(mine + lslot(p), kStPrefix | (v[p] + a[p]));
@@ -573,6 +593,7 @@ struct Build {
         for (int p = 0; p < PX; ++p) { v[p] = 0; vq[p] = 0; }
         if (strip == 0) {
             seed(d, xb, lane, v, vq, fault);
+            stress_delay(d.stress, strip, xb, 0);
 #pragma unroll
             for (int p = 0; p < PX; ++p) {
                 store_state(mine + lslot(p), kStPrefix | (v[p] + a[p]));
@@ -581,6 +602,7 @@ struct Build {
             emit_total(d, strip, xb, lane, v, a, vq, aq);
             return;
         }
+        stress_delay(d.stress, strip, xb, 1);
 #pragma unroll
         for (int p = 0; p < PX; ++p) {
             store_state(mine + lslot(p), kStAggregate | a[p]);
@@ -644,6 +666,7 @@ struct Build {
                 __builtin_amdgcn_s_sleep(2);
             }
         }
+        stress_delay(d.stress, strip, xb, 2);
 #pragma unroll
         for (int p = 0; p < PX; ++p) {
             store_state(mine + lslot(p), kStPrefix | (v[p] + a[p]));
@@ -1198,6 +1221,7 @@ struct BuildPow {
 #pragma unroll
             for (int i = 0; i < PX; ++i) v[p][i] = 0;
         const uint64_t first = strip == 0 ? kStPrefix : kStAggregate;
+        stress_delay(d.stress, strip, xb, 1);
 #pragma unroll
         for (int p = 0; p < NP; ++p)
 #pragma unroll
@@ -1244,7 +1268,10 @@ struct BuildPow {
 #pragma unroll
         for (int p = 0; p < NP; ++p)
 #pragma unroll
-            for (int i = 0; i < PX; ++i) store_state(mine + p * plane + B1::lslot(i), kStPrefix | (v[p][i] + a[p][i]));
+            for (int i = 0; i < PX; ++i) {
+                if (p == 0 && i == 0) stress_delay(d.stress, strip, xb, 2);
+                store_state(mine + p * plane + B1::lslot(i), kStPrefix | (v[p][i] + a[p][i]));
+            }
     }
 
     // Helper wave: per-wave column sums of every power of tile `buf`, the lookback, and the
@@ -1538,7 +1565,10 @@ __global__ __launch_bounds__(NW * 64) void fused_kernel(const BuildDesc *__restr
             // cost a quarter of the launch.
             __builtin_amdgcn_s_waitcnt(0x0070);                  // vmcnt(0), lgkmcnt(0)
             __syncthreads();
-            if (threadIdx.x == 0) __hip_atomic_fetch_add(ready + lo, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (threadIdx.x == 0) {
+                stress_delay(d.stress, static_cast<int>(t), 0, 3);
+                __hip_atomic_fetch_add(ready + lo, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
         } else {
             const long long item = t - build_items;
             int lo = 0, hi = n - 1;

@@ -31,6 +31,9 @@ struct BuildDesc {
     int32_t img_vb;       // widest aligned load (16, 8 or 4 bytes) every image row start allows;
                           // -4: rows not 4-byte aligned (unaligned 4-byte loads, no LDS DMA)
     int32_t sat_vec;      // 1: table rows allow 16-byte vector stores
+    uint32_t stress;      // nonzero (tests only): seed of pseudo-random delays before every lookback
+                          // publish and fused ready count, to perturb the order strips finish in
+    uint32_t pad_;
 };
 
 // Workspace layout: 256-byte control header, then the lookback state.

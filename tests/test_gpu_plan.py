@@ -4,9 +4,10 @@ oracle's tables (needs an MI355X with 256 compute units, the device the plan is 
 The plan picks the helper-wave variant and its strip height from the image shape: eight pixels
 per lane at 48-row strips (24-row strips for very few strips, balanced heights for tall images),
 four pixels per lane at one 64-row strip per CU, and four pixels per lane at 32, 48 or 64 rows (or
-balanced heights) for narrow images and 16-bit images with squares.  Each case below lands in one
-branch; widths that are not a multiple of the block width end in a ragged block.  Tables must be
-bit-exact.
+balanced heights) for narrow images and 16-bit images with squares; images up to 32768 pixels
+wide take the three-stage helper pipeline, wider ones the two-stage one.  Each case below lands in
+one branch; widths that are not a multiple of the block width end in a ragged block.  Tables must
+be bit-exact.
 """
 import numpy as np
 import pytest
@@ -34,6 +35,8 @@ CASES = [
     (5, 8200, np.uint16, True, "five rows, 16-bit with squares, ragged"),
     (1, 1, np.uint8, False, "one pixel: narrow, 4 px/lane"),
     (47, 4096, np.uint16, False, "one strip just short of 48 rows"),
+    (300, 40000, np.uint8, False, "wider than 32768: two-stage helper, 8 px/lane"),
+    (100, 33000, np.uint16, True, "wider than 32768, 16-bit with squares: two-stage helper, 4 px/lane, ragged"),
 ]
 
 
