@@ -19,6 +19,13 @@ Scheduling is continuous batching, not a queue alone:
   * a query whose table was evicted rebuilds it first (the image is regenerated from its seed)
     and counts as a miss.
 
+Images arrive as host data: a producer thread (ImageSource) draws each build request's image into
+a buffer of a pinned host pool ahead of its arrival, as a client upload would have it ready; the
+scheduler admits a build only once its image is ready and copies it to the device asynchronously
+on the request's stream (the H2D copy is timed separately from the build).  No request does host
+work on the scheduler thread beyond launching; the longest scheduler-side executor call is
+reported.
+
 Latency runs from a request's arrival to the moment the host observes its completion event.
 Results stay on the device; copying them to the host is not part of the latency.
 
@@ -30,6 +37,7 @@ from __future__ import annotations
 import collections
 import dataclasses
 import math
+import threading
 import time
 from typing import Callable, Dict, List, Optional
 
@@ -90,10 +98,13 @@ class Report:
     evictions: int
     peak_bytes: int
     max_in_flight: int
+    host_call_ms: Dict[str, float] = dataclasses.field(default_factory=dict)   # longest executor call, by kind
+    device_ms: Dict[str, Dict[str, float]] = dataclasses.field(default_factory=dict)   # H2D / build split
 
     def as_dict(self) -> dict:
         w = max(self.wall_s, 1e-9)
         return {"requests": self.n, "wall_s": round(self.wall_s, 3), "latency_ms": self.latency_ms,
+                "max_host_call_ms": self.host_call_ms, "build_device_ms": self.device_ms,
                 "build_gpix_s": round(self.build_gpix / w, 3),
                 "served_gpix_s": round((self.build_gpix + self.query_gpix) / w, 3),
                 "window_outputs_g_s": round(self.outputs_g / w, 3),
@@ -120,6 +131,17 @@ class Server:
         self.max_flight = 0
         self.done: List[Job] = []
         self.protect = True                       # keep tables that queued queries are about to read
+        self.host_max: Dict[str, float] = collections.defaultdict(float)
+        self.image_wait = False
+
+    def _call(self, kind: str, fn, *args):
+        """An executor call from the scheduler, its duration kept per kind (the longest)."""
+        t = time.perf_counter()
+        out = fn(*args)
+        dt = (time.perf_counter() - t) * 1e3
+        if dt > self.host_max[kind]:
+            self.host_max[kind] = dt
+        return out
 
     # -------------------------------------------------------------- memory
     def _make_room(self, need: int) -> bool:
@@ -153,6 +175,9 @@ class Server:
         trans = self.ex.build_transient_bytes(req.H, req.W)
         if nbytes + trans > self.budget:
             raise ValueError("image %d (%dx%d) cannot fit the %d-byte budget" % (iid, req.H, req.W, self.budget))
+        if not self._call("image_ready", self.ex.image_ready, req):
+            self.image_wait = True
+            return False
         if not self._make_room(nbytes + trans):
             return False
         r = Resident(iid, req.H, req.W, nbytes, last_used=now)
@@ -160,7 +185,7 @@ class Server:
         self.used += nbytes
         self._start(job, now, trans)
         r.build_job = job
-        job.handle = self.ex.start_build(req, r, job.slot)
+        job.handle = self._call("start_build", self.ex.start_build, req, r, job.slot)
         return True
 
     def _admit_query(self, job: Job, r: Resident, now: float) -> bool:
@@ -172,11 +197,12 @@ class Server:
         r.pins += 1
         r.last_used = now
         self.res.move_to_end(r.image_id)
-        job.handle = self.ex.start_query(job.req, r, job.slot, after)
+        job.handle = self._call("start_query", self.ex.start_query, job.req, r, job.slot, after)
         return True
 
     def _schedule(self, now: float) -> None:
         build_blocked = False
+        self.image_wait = False                   # a build waits for its image (not for memory)
         i = 0
         while i < len(self.queue) and self.free_slots:
             job = self.queue[i]
@@ -196,6 +222,7 @@ class Server:
                     self.queued_build[iid] = rb
                     job.miss = True
                     self.queue.insert(i, rb)
+                    self._call("prefetch", self.ex.prefetch, [rb.req])
                     continue
                 i += 1                                    # its build has not been admitted yet
                 continue
@@ -209,7 +236,7 @@ class Server:
     def _retire(self, now: float) -> int:
         still, n = [], 0
         for job in self.flight:
-            if not self.ex.is_done(job.handle):
+            if not self._call("is_done", self.ex.is_done, job.handle):
                 still.append(job)
                 continue
             n += 1
@@ -221,12 +248,12 @@ class Server:
                 if r is not None and r.build_job is job:
                     r.state = "resident"
                     r.build_job = None
-                self.ex.finish_build(job.handle)
+                self._call("finish_build", self.ex.finish_build, job.handle)
             else:
                 if r is not None:
                     r.pins -= 1
                     r.last_used = now
-                job.result = self.ex.finish_query(job.handle, self.keep)
+                job.result = self._call("finish_query", self.ex.finish_query, job.handle, self.keep)
             job.handle = None if not self.keep else job.handle
             if job.idx >= 0:
                 self.done.append(job)
@@ -241,6 +268,8 @@ class Server:
             if req.kind == "build":
                 self.builds[image_id(req)] = req
         order = sorted(range(len(requests)), key=lambda k: requests[k].t_arrival)
+        # the images the stream will upload, in arrival order, prepared ahead by the executor
+        self.ex.prefetch([requests[k] for k in order if requests[k].kind == "build"])
         t0 = clock()
         nxt = 0
         while nxt < len(order) or self.queue or self.flight:
@@ -255,12 +284,12 @@ class Server:
             retired = self._retire(now)
             n_before = len(self.flight)
             self._schedule(now)
-            if not self.flight and self.queue:
+            if not self.flight and self.queue and not self.image_wait:
                 # nothing in flight will free memory: let eviction take protected tables too
                 self.protect = False
                 self._schedule(now)
                 self.protect = True
-                if not self.flight:
+                if not self.flight and not self.image_wait:
                     raise RuntimeError("no queued request fits the memory budget")
             if not retired and len(self.flight) == n_before:
                 idle()
@@ -279,18 +308,124 @@ class Server:
                 qpx += b.H * b.W / 1e9
                 h, w = min(j.req.win_h, b.H), min(j.req.win_w, b.W)
                 opx += ((b.H - h) // j.req.stride + 1) * ((b.W - w) // j.req.stride + 1) / 1e9
+        dev = {}
+        split = getattr(self.ex, "build_split_ms", None)
+        if split:
+            for part in ("h2d", "build"):
+                xs = [x[part] for x in split]
+                dev[part] = {"n": len(xs), "p50": round(percentile(xs, 0.5), 3), "p99": round(percentile(xs, 0.99), 3),
+                             "max": round(max(xs), 3)}
         return Report(len(self.done), wall, lat, bpx, qpx, opx, sum(1 for j in self.done if j.miss),
-                      self.evictions, self.peak, self.max_flight)
+                      self.evictions, self.peak, self.max_flight,
+                      {k: round(v, 3) for k, v in sorted(self.host_max.items())}, dev)
+
+
+class ImageSource:
+    """Producer threads that prepare the images of build requests as host data ahead of their
+    arrival, the way a client's upload would be waiting in host memory: the 8-bit cluster mask of
+    each request (synth.thomas_points, seeded by the request) drawn into a pinned buffer of a
+    fixed pool, on rows of image_pitch(W) bytes.  Requests are taken in the order given; an
+    image asked for again (a rebuild after eviction) draws from one buffer kept apart for that, so
+    that buffers held by images waiting for admission can never block it.  The drawing (numpy's
+    generator, torch's fill and scatter on CPU tensors) runs outside the GIL for all but the
+    bookkeeping."""
+
+    def __init__(self, torch, pool: int = 4, max_pixels: int = 16000 * 16064, workers: int = 2):
+        self.torch = torch
+        self.cv = threading.Condition()
+        self.free = [torch.empty(max_pixels, dtype=torch.uint8, pin_memory=True) for _ in range(pool)]
+        self.spare = [torch.empty(max_pixels, dtype=torch.uint8, pin_memory=True)]
+        self.max_pixels = max_pixels
+        self.todo: "collections.deque" = collections.deque()
+        self.seen = set()
+        self.ready: Dict[int, tuple] = {}
+        self.closed = False
+        self.threads = [threading.Thread(target=self._work, name="image-source-%d" % i, daemon=True)
+                        for i in range(workers)]
+        for t in self.threads:
+            t.start()
+
+    def request(self, reqs) -> None:
+        with self.cv:
+            for r in reqs:
+                iid = image_id(r)
+                again = iid in self.seen
+                self.seen.add(iid)
+                self.todo.append((r, again))
+            self.cv.notify_all()
+
+    def is_ready(self, iid: int) -> bool:
+        with self.cv:
+            return iid in self.ready
+
+    def take(self, iid: int):
+        """(buffer, H, W, pitch, spare) of a ready image, now owned by the caller."""
+        with self.cv:
+            return self.ready.pop(iid)
+
+    def give_back(self, buf, spare: bool) -> None:
+        with self.cv:
+            (self.spare if spare else self.free).append(buf)
+            self.cv.notify_all()
+
+    def close(self) -> None:
+        with self.cv:
+            self.closed = True
+            self.cv.notify_all()
+        for t in self.threads:
+            t.join()
+
+    def _work(self) -> None:
+        from .api import image_pitch
+        from .synth import thomas_points
+        torch = self.torch
+        while True:
+            with self.cv:
+                while True:
+                    if self.closed:
+                        return
+                    # the first request a buffer is free for (a rebuild waits only for the spare)
+                    k = next((i for i, (_, again) in enumerate(self.todo) if (self.spare if again else self.free)),
+                             None)
+                    if k is not None:
+                        break
+                    self.cv.wait()
+                req, again = self.todo[k]
+                del self.todo[k]
+                buf = (self.spare if again else self.free).pop()
+            H, W = req.H, req.W
+            pitch = image_pitch(W, torch.uint8)
+            if H * pitch > self.max_pixels:
+                raise ValueError("image %dx%d exceeds the source's buffers" % (H, W))
+            ys, xs = thomas_points(H, W, seed=req.image_seed)
+            view = buf[:H * pitch]
+            view.zero_()
+            view[torch.from_numpy(ys * pitch + xs)] = 1
+            with self.cv:
+                self.ready[image_id(req)] = (buf, H, W, pitch, again)
 
 
 class GpuExecutor:
-    """Runs the requests on one GPU through the library, one stream per slot."""
+    """Runs the requests on one GPU through the library, one stream per slot.  Build requests
+    copy their image from the ImageSource's pinned buffer to the device on their stream, then
+    build; the H2D copy and the build are timed apart with events (build_split_ms)."""
 
-    def __init__(self, device, slots: int):
+    def __init__(self, device, slots: int, pool: int = 4):
         import torch
         self.torch = torch
         self.dev = torch.device(device)
         self.streams = [torch.cuda.Stream(self.dev) for _ in range(slots)]
+        self.src = ImageSource(torch, pool)
+        self.build_split_ms: List[dict] = []
+
+    def close(self) -> None:
+        self.src.close()
+
+    def prefetch(self, reqs) -> None:
+        self.src.request(reqs)
+
+    def image_ready(self, req: Request) -> bool:
+        return self.src.is_ready(image_id(req))
 
     def table_bytes(self, H: int, W: int) -> int:
         from .api import table_pitch
@@ -311,20 +446,29 @@ class GpuExecutor:
         return 3 * oh * out_pitch(ow, torch.float64) * 8
 
     def start_build(self, req: Request, r: Resident, slot: int):
-        from . import api, synth
+        from . import api
         torch = self.torch
         s = self.streams[slot]
+        buf, H, W, pitch, spare = self.src.take(image_id(req))
         with torch.cuda.stream(s):
-            # the image lands on 128-byte row lines, the layout the build stages fastest
-            img = synth.thomas_mask_device(req.H, req.W, req.image_seed, self.dev,
-                                           out=api.empty_image(req.H, req.W, torch.uint8, self.dev))
+            base = torch.empty((H, pitch), dtype=torch.uint8, device=self.dev)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            ev = torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            base.copy_(buf[:H * pitch].view(H, pitch), non_blocking=True)
+            e1.record(s)
+            img = base[:, :W]                    # rows on 128-byte lines: the helper-wave plans
             r.tables = api.sat_build(img, stream=s)
-            ev = torch.cuda.Event()
             ev.record(s)
-        return {"ev": ev, "img": img}
+        return {"ev": ev, "e0": e0, "e1": e1, "img": img, "buf": buf, "spare": spare}
 
     def finish_build(self, handle) -> None:
+        self.build_split_ms.append({"h2d": handle["e0"].elapsed_time(handle["e1"]),
+                                    "build": handle["e1"].elapsed_time(handle["ev"])})
+        self.src.give_back(handle["buf"], handle["spare"])
         handle["img"] = None
+        handle["buf"] = None
 
     def start_query(self, req: Request, r: Resident, slot: int, after):
         from . import api

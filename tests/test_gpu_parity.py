@@ -557,6 +557,7 @@ def test_serving_results_same_alone_and_in_mix():
     srv = serve.Server(ex, budget_bytes=40e6, slots=4, keep_results=True)
     rep = srv.run(reqs, idle=lambda: time.sleep(2e-5))
     torch.cuda.synchronize()
+    ex.close()
     print("case: serving", rep.as_dict(), flush=True)
     assert rep.n == len(reqs) and rep.max_in_flight > 1 and rep.peak_bytes <= 40e6
     n_sum, n_stats = check_served_against_oracle(srv, "small")
@@ -578,7 +579,9 @@ def test_serving_full_size_images_every_query():
     srv = serve.Server(ex, budget_bytes=3e9, slots=4, keep_results=True)
     rep = srv.run(reqs, idle=lambda: time.sleep(2e-5))
     torch.cuda.synchronize()
+    ex.close()
     print("case: serving full size", rep.as_dict(), flush=True)
+    assert rep.device_ms["h2d"]["n"] == rep.device_ms["build"]["n"] >= len(builds)
     assert rep.n == len(reqs) and rep.max_in_flight > 1 and rep.peak_bytes <= 3e9
     assert rep.evictions > 0
     n_sum, n_stats = check_served_against_oracle(srv, "full size")

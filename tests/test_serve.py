@@ -31,6 +31,12 @@ class FakeExecutor:
     def table_bytes(self, H, W):
         return H * W * 8
 
+    def prefetch(self, reqs):
+        self.prefetched = getattr(self, "prefetched", []) + [image_id(r) for r in reqs]
+
+    def image_ready(self, req):
+        return image_id(req) in getattr(self, "prefetched", [])
+
     def build_transient_bytes(self, H, W):
         return H * W
 
@@ -155,3 +161,34 @@ def test_oversized_image_is_refused():
     reqs = [synth.Request(0.0, "build", image_seed=1000, H=2000, W=2000)]
     with pytest.raises(ValueError):
         serve(reqs, budget=1e6)
+
+
+def test_builds_wait_for_their_images_and_prefetch_covers_the_stream():
+    """A build is admitted only once its image is ready (host data prepared ahead), in arrival
+    order; rebuilds after eviction ask for their image again; executor calls are timed."""
+    clock = Clock()
+    ex = FakeExecutor(clock)
+    reqs = synth.request_stream(rate=200.0, duration=0.5, seed=9, side_lo=100, side_hi=400)
+    srv = Server(ex, budget_bytes=4e6, slots=2)
+    rep = srv.run(reqs, clock=clock, idle=clock.idle)
+    builds = [image_id(r) for r in reqs if r.kind == "build"]
+    assert ex.prefetched[:len(builds)] == builds                 # the whole stream, in arrival order
+    assert len(ex.prefetched) == len(builds) + rep.misses        # one more per rebuild
+    assert set(rep.host_call_ms) >= {"image_ready", "start_build", "is_done"}
+
+
+def test_builds_wait_for_late_images_without_a_budget_error():
+    """Images that become ready only after several scheduler passes (a slow producer) delay their
+    builds; the loop keeps idling instead of reporting a memory deadlock."""
+    clock = Clock()
+
+    class SlowImages(FakeExecutor):
+        def image_ready(self, req):
+            self.asked = getattr(self, "asked", {})
+            self.asked[image_id(req)] = self.asked.get(image_id(req), 0) + 1
+            return super().image_ready(req) and self.asked[image_id(req)] > 5
+
+    ex = SlowImages(clock)
+    reqs = synth.request_stream(rate=100.0, duration=0.3, seed=10, side_lo=100, side_hi=300)
+    rep = Server(ex, budget_bytes=50e6, slots=2).run(reqs, clock=clock, idle=clock.idle)
+    assert rep.n == len(reqs)
