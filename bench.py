@@ -375,9 +375,10 @@ def serving_section(torch, dev, seconds, burst_seconds):
 
     # No warm-up run: the first requests of the stream pay the first launch of each kernel.
     out = {"workload": "Poisson arrivals; 20% builds of uint8 Thomas-cluster masks with sides uniform on "
-                       "2000..16000, uploaded from pinned host buffers a producer thread fills ahead of "
-                       "arrival (H2D timed apart from the build), 80% window queries (sides 16..512, "
-                       "strides 1..8, 25% mean/std) on resident tables; 200 GB admission budget; seed 4",
+                       "2000..16000, uploaded by a copy kernel from pinned host buffers a producer thread "
+                       "fills ahead of arrival (H2D timed apart from the build), 80% window queries (sides "
+                       "16..512, strides 1..8, 25% mean/std) on resident tables; tables, images and outputs "
+                       "placed in one 200 GB device arena allocated before the stream; seed 4",
            "nominal_50_per_s": dict(run(50.0, seconds, 4), rate=50.0, slots=4)}
     if burst_seconds > 0:
         out["burst_500_per_s_4_slots"] = dict(run(500.0, burst_seconds, 4), rate=500.0, slots=4)

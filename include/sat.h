@@ -258,6 +258,17 @@ sat_status sat_build_stats_batched(const sat_batch_item *items, int32_t n, sat_d
  * Meant for tests and debugging; the fast path never waits. */
 sat_status sat_workspace_check(void *workspace, void *stream);
 
+/* Copy nbytes from pinned host memory to device memory with a kernel on `stream`, for callers
+ * that feed images from host buffers while other streams compute (the serving loop's uploads).
+ * The enqueue is a kernel launch: it returns without waiting for copies in flight elsewhere, where
+ * a DMA copy enqueue (hipMemcpyAsync) can hold the calling thread for milliseconds.  The kernel
+ * reads the host pages over the bus and writes dst with 16-byte stores.
+ * host: memory from hipHostMalloc (torch's pin_memory), valid until the copy has run on the
+ * stream; dst: device, nbytes bytes; both 16-byte aligned; they must not overlap.
+ * Errors: SAT_ERR_ARG (NULL, nbytes 0, misaligned, or host memory the device cannot address:
+ * checked with hipHostGetDevicePointer, which leaves no error pending); SAT_ERR_HIP. */
+sat_status sat_upload(const void *host, void *dst, size_t nbytes, void *stream);
+
 /* Message for the last error returned on the calling thread (static storage, never NULL). */
 const char *sat_last_error(void);
 

@@ -70,6 +70,7 @@ def load(path: str = LIB_PATH):
             "sat_build_stats_workspace_bytes": (_sz, [_p, _i32, ctypes.c_int]),
             "sat_build_stats_batched": (_st, [_p, _i32, ctypes.c_int, _i64, _i64, _i64, _p, _sz, _p]),
             "sat_workspace_check": (_st, [_p, _p]),
+            "sat_upload": (_st, [_p, _p, _sz, _p]),
             "sat_last_error": (ctypes.c_char_p, []),
             "sat_variant_count": (_i32, [_i32]),
             "sat_variant_name": (ctypes.c_char_p, [_i32, _i32]),

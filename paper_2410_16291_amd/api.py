@@ -362,6 +362,23 @@ def window_moments(tables: List[torch.Tensor], h: int, w: int, stride: int = 1, 
     return {n: outs[n] for n in stats}
 
 
+def upload(host: torch.Tensor, dst: torch.Tensor, stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:
+    """Copy the pinned host tensor `host` into the device tensor `dst` (both contiguous, the same
+    number of bytes) with a kernel on `stream`: the call returns once the kernel is enqueued,
+    whatever other copies are in flight.  `host` must stay alive until the copy has run."""
+    if host.device.type != "cpu" or not host.is_pinned():
+        raise ValueError("host must be a pinned CPU tensor")
+    if not dst.is_cuda:
+        raise ValueError("dst must be a device (cuda) tensor")
+    if not host.is_contiguous() or not dst.is_contiguous():
+        raise ValueError("host and dst must be contiguous")
+    n = host.numel() * host.element_size()
+    if n != dst.numel() * dst.element_size():
+        raise ValueError("host and dst must hold the same number of bytes")
+    check(_lib.load().sat_upload(host.data_ptr(), dst.data_ptr(), n, _stream_handle(dst.device, stream)))
+    return dst
+
+
 def workspace_check(ws: torch.Tensor, stream: Optional[torch.cuda.Stream] = None) -> None:
     """Synchronise and raise if a build that used `ws` reported a lookback fault."""
     check(_lib.load().sat_workspace_check(ws.data_ptr(), _stream_handle(ws.device, stream)))

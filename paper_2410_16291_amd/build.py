@@ -13,7 +13,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libsat.so")
-SOURCES = ["sat_api.cpp", "sat_build.hip", "sat_gather.hip"]
+SOURCES = ["sat_api.cpp", "sat_build.hip", "sat_gather.hip", "sat_upload.hip"]
 ARCH = os.environ.get("SAT_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

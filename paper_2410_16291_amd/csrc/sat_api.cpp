@@ -1059,6 +1059,24 @@ sat_status sat_workspace_check(void *workspace, void *stream) {
     return ok();
 }
 
+sat_status sat_upload(const void *host, void *dst, size_t nbytes, void *stream) {
+    const char *who = "sat_upload";
+    if (!host || !dst) return fail(SAT_ERR_ARG, "%s: host and dst must be non-NULL", who);
+    if (nbytes == 0) return fail(SAT_ERR_ARG, "%s: nbytes must be at least 1", who);
+    if ((reinterpret_cast<uintptr_t>(host) | reinterpret_cast<uintptr_t>(dst)) & 15u)
+        return fail(SAT_ERR_ARG, "%s: host and dst must be 16-byte aligned", who);
+    // the device's address of the pinned pages (the same address on a unified address space)
+    void *src = nullptr;
+    hipError_t e = hipHostGetDevicePointer(&src, const_cast<void *>(host), 0);
+    if (e != hipSuccess || !src) {
+        (void)hipGetLastError();     // leave no sticky error behind for the caller's next check
+        return fail(SAT_ERR_ARG, "%s: host is not pinned, device-accessible host memory (hipHostMalloc)", who);
+    }
+    e = satk::launch_upload(src, dst, nbytes, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, who);
+    return ok();
+}
+
 int32_t sat_variant_count(int32_t kind) {
     if (kind == 0) return satk::build_variant_count();
     if (kind == 1) return satk::gather_variant_count();

@@ -161,6 +161,9 @@ int mean_std_chain_v(int variant, int64_t stride);
 // plan_mean_std, q > 0), gather_items items in all, device copy dev_gdescs.  ready: n counters
 // inside the cleared state words (the launch zeroes them with the lookback state).
 bool fused_build_variant(int variant);
+// Host-to-device copy by a kernel reading pinned host memory at its device address src_dev.
+hipError_t launch_upload(const void *src_dev, void *dst, size_t nbytes, hipStream_t stream);
+
 hipError_t launch_fused(int variant, int bpp, int v, const BuildDesc *bdescs, int n, const BuildDesc *dev_bdescs,
                         int64_t build_items, const GatherDesc *dev_gdescs, int64_t gather_items, void *workspace,
                         int64_t state_words, unsigned int *ready, hipStream_t stream);

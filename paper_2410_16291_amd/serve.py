@@ -11,9 +11,13 @@ Scheduling is continuous batching, not a queue alone:
   * whenever a slot or memory frees up, waiting requests are admitted in arrival order.  A build
     that cannot be admitted yet (its table does not fit) does not block the queries behind it,
     but no later build overtakes it;
-  * admission is by memory footprint under `budget_bytes`: resident tables plus the transient
-    image, workspace and output bytes of the requests in flight.  To make room, the least
-    recently used resident tables that no in-flight or imminent query reads are evicted;
+  * admission is by placement in an arena of `budget_bytes`, one device allocation made before
+    the stream starts: every resident table, and the transient image, workspace and output bytes
+    of each request in flight, is a block of it (Arena).  A request is admitted once its blocks
+    can be placed; to make room, the least recently used resident tables that no in-flight or
+    imminent query reads are evicted.  No request allocates or frees device memory, so no
+    allocator call (and none of the device synchronisation a caching allocator falls back on
+    near the memory's end) lands on the scheduler thread;
   * a query may be admitted while its image is still being built: its stream waits for the
     build's completion event on the device, not on the host;
   * a query whose table was evicted rebuilds it first (the image is regenerated from its seed)
@@ -22,9 +26,13 @@ Scheduling is continuous batching, not a queue alone:
 Images arrive as host data: a producer thread (ImageSource) draws each build request's image into
 a buffer of a pinned host pool ahead of its arrival, as a client upload would have it ready; the
 scheduler admits a build only once its image is ready and copies it to the device asynchronously
-on the request's stream (the H2D copy is timed separately from the build).  No request does host
+on the request's stream, by a kernel that reads the pinned pages (the H2D copy is timed
+separately from the build).  No request does host
 work on the scheduler thread beyond launching; the longest scheduler-side executor call is
-reported.
+reported.  Python's cyclic garbage collector is paused while the loop runs (after one collection
+and a freeze of everything allocated before the stream): a full collection walks every object the
+process holds, torch's included, and stopped all threads for tens of milliseconds; the loop's own
+objects form no reference cycles and are freed by reference counting.
 
 Latency runs from a request's arrival to the moment the host observes its completion event.
 Results stay on the device; copying them to the host is not part of the latency.
@@ -34,8 +42,10 @@ the CPU tests drive a simulated one).
 """
 from __future__ import annotations
 
+import bisect
 import collections
 import dataclasses
+import gc
 import math
 import threading
 import time
@@ -55,6 +65,7 @@ class Resident:
     H: int
     W: int
     nbytes: int
+    offset: int = -1                   # the table's block in the arena
     state: str = "building"            # "building" or "resident"
     tables: object = None              # executor-owned (device tensors)
     build_job: Optional["Job"] = None
@@ -72,6 +83,7 @@ class Job:
     slot: int = -1
     handle: object = None
     transient: int = 0                 # bytes held while in flight
+    block: int = -1                    # their block in the arena
     result: object = None
     miss: bool = False
     waiting_on: Optional["Job"] = None  # a query behind the (re)build of its image
@@ -112,12 +124,94 @@ class Report:
                 "peak_GB": round(self.peak_bytes / 1e9, 3), "max_in_flight": self.max_in_flight}
 
 
+class Arena:
+    """Placement of blocks in one fixed device region of `size` bytes, by offset: best fit (the
+    smallest free run that holds the block, lowest offset among equals), a released block merged
+    with free neighbours.  The server places every table and every in-flight request's transient
+    block here, so the device memory of the stream is one allocation made before it starts and
+    no request allocates or frees device memory.  Long-lived blocks (tables) are cut from the top
+    of their run and short-lived ones (transients) from the bottom, so that tables pack towards
+    the region's end and the space the transients come and go in stays in one piece."""
+
+    ALIGN = 256
+
+    def __init__(self, size: int):
+        self.size = int(size) // self.ALIGN * self.ALIGN
+        self.starts: List[int] = [0] if self.size else []      # free runs, sorted by offset
+        self.lens: List[int] = [self.size] if self.size else []
+        self.live: Dict[int, int] = {}                          # placed block offset -> rounded length
+
+    @classmethod
+    def rounded(cls, n: int) -> int:
+        return (max(int(n), 1) + cls.ALIGN - 1) // cls.ALIGN * cls.ALIGN
+
+    @staticmethod
+    def _best(lens: List[int], n: int) -> int:
+        best = -1
+        for i, ln in enumerate(lens):
+            if ln >= n and (best < 0 or ln < lens[best]):
+                best = i
+        return best
+
+    def fits(self, sizes) -> bool:
+        """Whether blocks of `sizes` bytes can all be placed now (in that order, as alloc would)."""
+        lens = list(self.lens)
+        for n in sizes:
+            n = self.rounded(n)
+            i = self._best(lens, n)
+            if i < 0:
+                return False
+            lens[i] -= n
+        return True
+
+    def alloc(self, n: int, top: bool = False) -> Optional[int]:
+        """Offset of a new block of n bytes (cut from the top of its run with `top`), or None if
+        no free run holds it."""
+        n = self.rounded(n)
+        i = self._best(self.lens, n)
+        if i < 0:
+            return None
+        off = self.starts[i] + (self.lens[i] - n if top else 0)
+        if self.lens[i] == n:
+            del self.starts[i]
+            del self.lens[i]
+        else:
+            if not top:
+                self.starts[i] += n
+            self.lens[i] -= n
+        self.live[off] = n
+        return off
+
+    def release(self, off: int) -> None:
+        n = self.live.pop(off)
+        i = bisect.bisect_left(self.starts, off)
+        # merge with the free run that ends at `off` and with the one that starts where it ends
+        if i > 0 and self.starts[i - 1] + self.lens[i - 1] == off:
+            i -= 1
+            self.lens[i] += n
+        else:
+            self.starts.insert(i, off)
+            self.lens.insert(i, n)
+        if i + 1 < len(self.starts) and self.starts[i] + self.lens[i] == self.starts[i + 1]:
+            self.lens[i] += self.lens.pop(i + 1)
+            del self.starts[i + 1]
+
+    @property
+    def free_bytes(self) -> int:
+        return sum(self.lens)
+
+    @property
+    def largest_free(self) -> int:
+        return max(self.lens, default=0)
+
+
 class Server:
     def __init__(self, executor, budget_bytes: float = 200e9, slots: int = 4, keep_results: bool = False):
         if slots < 1:
             raise ValueError("need at least one slot")
         self.ex = executor
         self.budget = int(budget_bytes)
+        self.arena = Arena(self.budget)
         self.keep = keep_results
         self.res: "collections.OrderedDict[int, Resident]" = collections.OrderedDict()   # LRU first
         self.builds: Dict[int, Request] = {}      # image id -> its build request (for rebuilds)
@@ -144,60 +238,73 @@ class Server:
         return out
 
     # -------------------------------------------------------------- memory
-    def _make_room(self, need: int) -> bool:
-        if self.used + need <= self.budget:
+    def _make_room(self, sizes: List[int], reads: Optional[int] = None) -> bool:
+        """Evict least recently used tables until blocks of `sizes` can be placed in the arena
+        (never the table `reads`, which the request being admitted reads)."""
+        if self.arena.fits(sizes):
             return True
         soon = {image_id(j.req) for j in self.queue[:64] if j.req.kind == "query"} if self.protect else set()
         for iid in list(self.res.keys()):
             r = self.res[iid]
-            if r.state != "resident" or r.pins > 0 or iid in soon:
+            if r.state != "resident" or r.pins > 0 or iid in soon or iid == reads:
                 continue
-            self.ex.free(r)
-            del self.res[iid]
-            self.used -= r.nbytes
-            self.evictions += 1
-            if self.used + need <= self.budget:
+            self._evict(r)
+            if self.arena.fits(sizes):
                 return True
         return False
+
+    def _evict(self, r: Resident) -> None:
+        self.ex.free(r)
+        del self.res[r.image_id]
+        self.arena.release(r.offset)
+        self.used -= r.nbytes
+        self.evictions += 1
 
     # -------------------------------------------------------------- admission
     def _start(self, job: Job, now: float, transient: int) -> None:
         job.slot = self.free_slots.pop()
         job.t_admit = now
-        job.transient = transient
-        self.used += transient
+        job.transient = Arena.rounded(transient)
+        job.block = self.arena.alloc(transient)
+        self.used += job.transient
         self.flight.append(job)
 
     def _admit_build(self, job: Job, now: float) -> bool:
         req = job.req
         iid = image_id(req)
-        nbytes = self.ex.table_bytes(req.H, req.W)
+        nbytes = Arena.rounded(self.ex.table_bytes(req.H, req.W))
         trans = self.ex.build_transient_bytes(req.H, req.W)
-        if nbytes + trans > self.budget:
+        if nbytes + Arena.rounded(trans) > self.arena.size:
             raise ValueError("image %d (%dx%d) cannot fit the %d-byte budget" % (iid, req.H, req.W, self.budget))
         if not self._call("image_ready", self.ex.image_ready, req):
             self.image_wait = True
             return False
-        if not self._make_room(nbytes + trans):
+        if not self._make_room([nbytes, trans]):
             return False
-        r = Resident(iid, req.H, req.W, nbytes, last_used=now)
+        r = Resident(iid, req.H, req.W, nbytes, offset=self.arena.alloc(nbytes, top=True), last_used=now)
         self.res[iid] = r
         self.used += nbytes
         self._start(job, now, trans)
         r.build_job = job
-        job.handle = self._call("start_build", self.ex.start_build, req, r, job.slot)
+        job.handle = self._call("start_build", self.ex.start_build, req, r, job.slot, job.block)
         return True
 
     def _admit_query(self, job: Job, r: Resident, now: float) -> bool:
         trans = self.ex.query_transient_bytes(job.req, r)
-        if not self._make_room(trans):
+        if r.nbytes + Arena.rounded(trans) > self.arena.size:
+            raise ValueError("the outputs of query %d do not fit the %d-byte budget beside their table"
+                             % (job.idx, self.budget))
+        if not self._make_room([trans], reads=r.image_id):
+            if not self.protect and not self.flight and r.state == "resident" and r.pins == 0:
+                # the table itself splits the free space: give it up too and rebuild it (a miss)
+                self._evict(r)
             return False
         self._start(job, now, trans)
         after = r.build_job.handle if r.state == "building" else None
         r.pins += 1
         r.last_used = now
         self.res.move_to_end(r.image_id)
-        job.handle = self._call("start_query", self.ex.start_query, job.req, r, job.slot, after)
+        job.handle = self._call("start_query", self.ex.start_query, job.req, r, job.slot, after, job.block)
         return True
 
     def _schedule(self, now: float) -> None:
@@ -242,6 +349,8 @@ class Server:
             n += 1
             job.t_done = now
             self.used -= job.transient
+            self.arena.release(job.block)
+            job.block = -1
             self.free_slots.append(job.slot)
             r = self.res.get(image_id(job.req))
             if job.req.kind == "build":
@@ -268,8 +377,22 @@ class Server:
             if req.kind == "build":
                 self.builds[image_id(req)] = req
         order = sorted(range(len(requests)), key=lambda k: requests[k].t_arrival)
+        self.ex.reserve(self.arena.size)        # the arena's device memory, before the clock starts
         # the images the stream will upload, in arrival order, prepared ahead by the executor
         self.ex.prefetch([requests[k] for k in order if requests[k].kind == "build"])
+        gc_was_on = gc.isenabled()
+        gc.collect()
+        gc.freeze()
+        gc.disable()
+        try:
+            return self._loop(requests, order, clock, idle)
+        finally:
+            gc.unfreeze()
+            if gc_was_on:
+                gc.enable()
+
+    def _loop(self, requests: List[Request], order: List[int], clock: Callable[[], float],
+              idle: Callable[[], None]) -> Report:
         t0 = clock()
         nxt = 0
         while nxt < len(order) or self.queue or self.flight:
@@ -286,10 +409,11 @@ class Server:
             self._schedule(now)
             if not self.flight and self.queue and not self.image_wait:
                 # nothing in flight will free memory: let eviction take protected tables too
+                ev = self.evictions
                 self.protect = False
                 self._schedule(now)
                 self.protect = True
-                if not self.flight and not self.image_wait:
+                if not self.flight and not self.image_wait and self.evictions == ev:
                     raise RuntimeError("no queued request fits the memory budget")
             if not retired and len(self.flight) == n_before:
                 idle()
@@ -406,9 +530,14 @@ class ImageSource:
 
 
 class GpuExecutor:
-    """Runs the requests on one GPU through the library, one stream per slot.  Build requests
-    copy their image from the ImageSource's pinned buffer to the device on their stream, then
-    build; the H2D copy and the build are timed apart with events (build_split_ms)."""
+    """Runs the requests on one GPU through the library, one stream per slot, in the device memory
+    of one arena allocation (reserve) carved by the server's block offsets.  Build requests copy
+    their image from the ImageSource's pinned buffer into their transient block on their stream
+    (api.upload: a kernel reading the pinned pages, whose enqueue never waits for other copies
+    in flight as a DMA copy's can), then build into their table's block with the workspace that
+    follows the image; the upload and the build are timed apart with events (build_split_ms).
+    Query outputs are views of their transient block, given back when the query retires; with
+    keep=True a result is copied out before that."""
 
     def __init__(self, device, slots: int, pool: int = 4):
         import torch
@@ -417,9 +546,58 @@ class GpuExecutor:
         self.streams = [torch.cuda.Stream(self.dev) for _ in range(slots)]
         self.src = ImageSource(torch, pool)
         self.build_split_ms: List[dict] = []
+        self.mem = None
+
+    def reserve(self, nbytes: int) -> None:
+        """The arena's device memory (kept across runs of the same size), then the executor's
+        start-up: one upload from pinned host memory, one table build and one gather of each kind on
+        every slot's stream, with timing events, on a small image in the still empty arena.  The
+        HIP runtime sets up its copy path, events and code objects on first use (tens of
+        milliseconds of host time); start-up takes that before the server accepts requests."""
+        torch = self.torch
+        if self.mem is not None and self.mem.numel() == nbytes:
+            return
+        self.mem = None
+        self.mem = torch.empty(nbytes, dtype=torch.uint8, device=self.dev)
+        from . import api
+        H, W = 96, 200
+        pitch = api.image_pitch(W, torch.uint8)
+        need = H * pitch + api.build_workspace_bytes(H, W, 1, False) + 2 * H * api.table_pitch(W) * 8 + 4 * 65536
+        if need > nbytes:
+            torch.cuda.synchronize(self.dev)
+            return
+        host = torch.ones(H * pitch, dtype=torch.uint8, pin_memory=True)
+        img = self.mem[:H * pitch].view(H, pitch)
+        ws_off = (H * pitch + 255) // 256 * 256
+        ws_n = api.build_workspace_bytes(H, W, 1, False)
+        t_off = (ws_off + ws_n + 255) // 256 * 256
+        tp = api.table_pitch(W)
+        S = self._view(t_off, H, tp, W, torch.uint64)
+        o_off = (t_off + H * tp * 8 + 255) // 256 * 256
+        for s in self.streams:
+            with torch.cuda.stream(s):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(s)
+                api.upload(host, self.mem[:H * pitch], stream=s)
+                api.sat_build(img[:, :W], sat=S, ws=self.mem[ws_off:ws_off + ws_n], stream=s)
+                for h, w, dt in ((8, 8, torch.uint32), (90, 190, torch.uint64)):
+                    oh, ow = api.out_shape(H, W, h, w, 1)
+                    op = api.out_pitch(ow, dt)
+                    api.window_sum(S, h, w, 1, pixel_type="u8", stream=s, out=self._view(o_off, oh, op, ow, dt))
+                oh, ow = api.out_shape(H, W, 16, 16, 2)
+                op = api.out_pitch(ow, torch.float64)
+                part = oh * op * 8
+                outs = (self._view(o_off, oh, op, ow, torch.uint64), self._view(o_off + part, oh, op, ow, torch.float64),
+                        self._view(o_off + 2 * part, oh, op, ow, torch.float64))
+                api.window_mean_std(S, S, 16, 16, 2, outs=outs, stream=s)
+                e1.record(s)
+            e1.synchronize()
+            e0.elapsed_time(e1)
+        torch.cuda.synchronize(self.dev)
 
     def close(self) -> None:
         self.src.close()
+        self.mem = None
 
     def prefetch(self, reqs) -> None:
         self.src.request(reqs)
@@ -427,72 +605,100 @@ class GpuExecutor:
     def image_ready(self, req: Request) -> bool:
         return self.src.is_ready(image_id(req))
 
+    def _view(self, off: int, rows: int, pitch: int, cols: int, dtype):
+        n = rows * pitch * dtype.itemsize
+        return self.mem[off:off + n].view(dtype).view(rows, pitch)[:, :cols]
+
+    @staticmethod
+    def _image_bytes(H: int, W: int) -> int:
+        from .api import image_pitch
+        import torch
+        return (H * image_pitch(W, torch.uint8) + 255) // 256 * 256
+
     def table_bytes(self, H: int, W: int) -> int:
         from .api import table_pitch
         return H * table_pitch(W) * 8
 
     def build_transient_bytes(self, H: int, W: int) -> int:
-        from .api import build_workspace_bytes, image_pitch
-        return H * image_pitch(W, self.torch.uint8) + build_workspace_bytes(H, W, 1, False)
+        from .api import build_workspace_bytes
+        return self._image_bytes(H, W) + build_workspace_bytes(H, W, 1, False)
 
-    def query_transient_bytes(self, req: Request, r: Resident) -> int:
+    def _out_layout(self, req: Request, r: Resident):
         import torch
         from .api import out_pitch
         h, w = min(req.win_h, r.H), min(req.win_w, r.W)
         oh, ow = (r.H - h) // req.stride + 1, (r.W - w) // req.stride + 1
         if req.op == "sum":
             dt = torch.uint32 if h * w * 255 <= 0xFFFFFFFF else torch.uint64
-            return oh * out_pitch(ow, dt) * dt.itemsize
-        return 3 * oh * out_pitch(ow, torch.float64) * 8
+            return h, w, oh, ow, dt, out_pitch(ow, dt), 1
+        return h, w, oh, ow, torch.float64, out_pitch(ow, torch.float64), 3
 
-    def start_build(self, req: Request, r: Resident, slot: int):
+    def query_transient_bytes(self, req: Request, r: Resident) -> int:
+        _, _, oh, _, dt, pitch, n = self._out_layout(req, r)
+        return n * oh * pitch * dt.itemsize
+
+    def start_build(self, req: Request, r: Resident, slot: int, block: int):
         from . import api
         torch = self.torch
         s = self.streams[slot]
         buf, H, W, pitch, spare = self.src.take(image_id(req))
+        tp = api.table_pitch(W)
+        S = self._view(r.offset, H, tp, W, torch.uint64)
+        base = self._view(block, H, pitch, pitch, torch.uint8)
+        ws_off = block + self._image_bytes(H, W)
+        ws = self.mem[ws_off:ws_off + api.build_workspace_bytes(H, W, 1, False)]
         with torch.cuda.stream(s):
-            base = torch.empty((H, pitch), dtype=torch.uint8, device=self.dev)
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
             ev = torch.cuda.Event(enable_timing=True)
             e0.record(s)
-            base.copy_(buf[:H * pitch].view(H, pitch), non_blocking=True)
+            api.upload(buf[:H * pitch], self.mem[block:block + H * pitch], stream=s)
             e1.record(s)
             img = base[:, :W]                    # rows on 128-byte lines: the helper-wave plans
-            r.tables = api.sat_build(img, stream=s)
+            r.tables = api.sat_build(img, sat=S, ws=ws, stream=s)
             ev.record(s)
-        return {"ev": ev, "e0": e0, "e1": e1, "img": img, "buf": buf, "spare": spare}
+        return {"ev": ev, "e0": e0, "e1": e1, "buf": buf, "spare": spare}
 
     def finish_build(self, handle) -> None:
         self.build_split_ms.append({"h2d": handle["e0"].elapsed_time(handle["e1"]),
                                     "build": handle["e1"].elapsed_time(handle["ev"])})
         self.src.give_back(handle["buf"], handle["spare"])
-        handle["img"] = None
         handle["buf"] = None
 
-    def start_query(self, req: Request, r: Resident, slot: int, after):
+    def start_query(self, req: Request, r: Resident, slot: int, after, block: int):
         from . import api
         torch = self.torch
         s = self.streams[slot]
         if after is not None:
             s.wait_event(after["ev"])
-        h, w = min(req.win_h, r.H), min(req.win_w, r.W)
+        h, w, oh, ow, dt, pitch, n = self._out_layout(req, r)
         S = r.tables
+        part = oh * pitch * dt.itemsize
         with torch.cuda.stream(s):
             if req.op == "sum":
-                out = api.window_sum(S, h, w, req.stride, pixel_type="u8", stream=s)
+                out = api.window_sum(S, h, w, req.stride, pixel_type="u8", stream=s,
+                                     out=self._view(block, oh, pitch, ow, dt))
             else:
-                out = api.window_mean_std(S, S, h, w, req.stride, stream=s)
+                outs = (self._view(block, oh, pitch, ow, torch.uint64),
+                        self._view(block + part, oh, pitch, ow, dt), self._view(block + 2 * part, oh, pitch, ow, dt))
+                out = api.window_mean_std(S, S, h, w, req.stride, outs=outs, stream=s)
             ev = torch.cuda.Event()
             ev.record(s)
-        S.record_stream(s)
-        return {"ev": ev, "out": out}
+        return {"ev": ev, "out": out, "stream": s}
 
     def is_done(self, handle) -> bool:
         return handle["ev"].query()
 
     def finish_query(self, handle, keep: bool):
-        return handle["out"] if keep else None
+        """The result (copied out of the arena block, which is given back next) with keep=True."""
+        if not keep:
+            return None
+        torch = self.torch
+        out = handle["out"]
+        with torch.cuda.stream(handle["stream"]):
+            res = out.clone() if isinstance(out, torch.Tensor) else tuple(o.clone() for o in out)
+        handle["stream"].synchronize()
+        return res
 
     def free(self, r: Resident) -> None:
         r.tables = None

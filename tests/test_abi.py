@@ -358,3 +358,13 @@ def test_column_totals_validation(lib):
     assert tot(out_sq=TOT + 8) == SAT_ERR_ARG                        # outputs overlap
     assert tot(carry=TOT + 8) == SAT_ERR_ARG                         # partial overlap of a carry
     assert tot(out=TOT + 4) == SAT_ERR_ARG                           # misaligned
+
+
+def test_sat_upload_validation(lib):
+    """Argument checks that need no device: NULL pointers, an empty copy, misalignment."""
+    assert lib.sat_upload(None, OUT, 64, None) == SAT_ERR_ARG
+    assert lib.sat_upload(IMG, None, 64, None) == SAT_ERR_ARG
+    assert lib.sat_upload(IMG, OUT, 0, None) == SAT_ERR_ARG
+    assert lib.sat_upload(IMG + 8, OUT, 64, None) == SAT_ERR_ARG
+    assert lib.sat_upload(IMG, OUT + 4, 64, None) == SAT_ERR_ARG
+    assert "aligned" in lib.sat_last_error().decode()

@@ -18,7 +18,7 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_2410_16291_amd", "csrc")
-SOURCES = ["sat_build.hip", "sat_gather.hip"]
+SOURCES = ["sat_build.hip", "sat_gather.hip", "sat_upload.hip"]
 
 
 def compile_asm(src, out):

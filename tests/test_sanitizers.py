@@ -21,7 +21,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 OUT = os.path.join(ROOT, "_build", "sanitize")
 CSRC = os.path.join(ROOT, "paper_2410_16291_amd", "csrc")
-LIB_SOURCES = ["sat_api.cpp", "sat_build.hip", "sat_gather.hip"]
+LIB_SOURCES = ["sat_api.cpp", "sat_build.hip", "sat_gather.hip", "sat_upload.hip"]
 CLANG = "/opt/rocm/llvm/bin/clang"
 SAN = ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined", "-shared-libsan", "-fno-omit-frame-pointer"]
 CHILD_TESTS = ["tests/test_abi.py", "tests/test_oracle.py", "tests/test_oracle_stream.py", "tests/test_oracle_bands.py",

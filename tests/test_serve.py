@@ -4,7 +4,7 @@ import math
 import pytest
 
 from paper_2410_16291_amd import synth
-from paper_2410_16291_amd.serve import Server, image_id, percentile
+from paper_2410_16291_amd.serve import Arena, Server, image_id, percentile
 
 
 class Clock:
@@ -19,7 +19,9 @@ class Clock:
 
 
 class FakeExecutor:
-    """Builds take 4 ms per Mpx, queries 1 ms per Mpx of table; slots run concurrently."""
+    """Builds take 4 ms per Mpx, queries 1 ms per Mpx of table; slots run concurrently.  Checks
+    that the arena blocks the server hands out lie inside the reserved region and that no two
+    blocks in use overlap."""
 
     def __init__(self, clock):
         self.clock = clock
@@ -27,6 +29,21 @@ class FakeExecutor:
         self.log = []            # (event, image id, request index or None)
         self.waited = 0
         self.freed = []
+        self.size = None
+        self.blocks = {}         # offset -> (end, owner) of the blocks in use
+
+    def reserve(self, nbytes):
+        self.size = nbytes
+
+    def _take(self, off, n, owner):
+        assert self.size is not None and 0 <= off and off + n <= self.size and off % Arena.ALIGN == 0
+        for o, (e, _) in self.blocks.items():
+            assert off + n <= o or e <= off, "blocks overlap"
+        self.blocks[off] = (off + n, owner)
+
+    def _give(self, owner):
+        for o in [o for o, (_, w) in self.blocks.items() if w == owner]:
+            del self.blocks[o]
 
     def table_bytes(self, H, W):
         return H * W * 8
@@ -44,16 +61,19 @@ class FakeExecutor:
         h, w = min(req.win_h, r.H), min(req.win_w, r.W)
         return ((r.H - h) // req.stride + 1) * ((r.W - w) // req.stride + 1) * 4
 
-    def start_build(self, req, r, slot):
+    def start_build(self, req, r, slot, block):
         end = self.clock() + 4e-3 * req.H * req.W / 1e6
         r.tables = ("table", image_id(req))
+        self._take(r.offset, self.table_bytes(req.H, req.W), ("table", image_id(req)))
+        h = {"end": end, "req": req}
+        self._take(block, self.build_transient_bytes(req.H, req.W), id(h))
         self.log.append(("build", image_id(req), self.clock()))
-        return {"end": end, "req": req}
+        return h
 
     def finish_build(self, h):
-        pass
+        self._give(id(h))
 
-    def start_query(self, req, r, slot, after):
+    def start_query(self, req, r, slot, after, block):
         assert r.tables == ("table", image_id(req)), "query started on a table that is not there"
         start = self.clock()
         if after is not None:
@@ -61,17 +81,21 @@ class FakeExecutor:
             start = max(start, after["end"])
         end = start + 1e-3 * r.H * r.W / 1e6
         self.log.append(("query", image_id(req), self.clock()))
-        return {"end": end, "req": req, "after": after}
+        h = {"end": end, "req": req, "after": after}
+        self._take(block, self.query_transient_bytes(req, r), id(h))
+        return h
 
     def is_done(self, h):
         return self.clock() >= h["end"] - 1e-12
 
     def finish_query(self, h, keep):
+        self._give(id(h))
         req = h["req"]
         return (image_id(req), req.win_h, req.win_w, req.stride, req.op) if keep else None
 
     def free(self, r):
         self.freed.append(r.image_id)
+        self._give(("table", r.image_id))
         r.tables = None
 
 
@@ -192,3 +216,121 @@ def test_builds_wait_for_late_images_without_a_budget_error():
     reqs = synth.request_stream(rate=100.0, duration=0.3, seed=10, side_lo=100, side_hi=300)
     rep = Server(ex, budget_bytes=50e6, slots=2).run(reqs, clock=clock, idle=clock.idle)
     assert rep.n == len(reqs)
+
+
+def test_arena_placement_against_a_byte_map():
+    """Random placements and releases: every block lies inside the region, no two live blocks
+    overlap, free runs are merged (their count never exceeds live blocks + 1) and the free bytes
+    add up; fits() agrees with what alloc() then does."""
+    import random
+    rnd = random.Random(7)
+    size = 1 << 20
+    a = Arena(size)
+    used = bytearray(size // Arena.ALIGN)
+    live = {}
+    for step in range(4000):
+        if live and (rnd.random() < 0.45 or a.largest_free < Arena.ALIGN):
+            off = rnd.choice(sorted(live))
+            n = live.pop(off)
+            a.release(off)
+            for k in range(off // Arena.ALIGN, (off + n) // Arena.ALIGN):
+                assert used[k] == 1
+                used[k] = 0
+        else:
+            want = rnd.choice([1, 255, 256, 257, 3000, 20000, 65536, 200000])
+            ok = a.fits([want])
+            off = a.alloc(want)
+            assert ok == (off is not None)
+            if off is None:
+                assert a.largest_free < Arena.rounded(want)
+                continue
+            n = Arena.rounded(want)
+            assert off % Arena.ALIGN == 0 and off + n <= size
+            for k in range(off // Arena.ALIGN, (off + n) // Arena.ALIGN):
+                assert used[k] == 0, "blocks overlap"
+                used[k] = 1
+            live[off] = n
+        assert a.free_bytes == (len(used) - sum(used)) * Arena.ALIGN
+        assert len(a.starts) <= len(live) + 1
+        for i in range(len(a.starts) - 1):
+            assert a.starts[i] + a.lens[i] < a.starts[i + 1]     # sorted, disjoint, never adjacent
+    for off in list(live):
+        a.release(off)
+    assert a.starts == [0] and a.lens == [size]
+
+
+def test_arena_fits_places_several_blocks_in_order():
+    a = Arena(10 * 256)
+    x = a.alloc(3 * 256)
+    a.alloc(256)
+    a.release(x)                                   # free runs: 3 blocks at 0, 6 blocks at 4
+    assert a.fits([3 * 256, 6 * 256])
+    assert not a.fits([4 * 256, 4 * 256])
+    assert a.alloc(2 * 256) == 0                   # best fit: the smaller run
+    assert a.alloc(5 * 256) == 4 * 256
+
+
+def test_no_allocation_when_served_through_the_arena():
+    """Under a budget that forces evictions, every table and transient block the executor is handed
+    lies in the reserved region and none overlaps another in use (FakeExecutor checks both)."""
+    reqs = stream(rate=800.0, duration=1.0, seed=11)
+    srv, ex, rep = serve(reqs, budget=50e6, slots=4)
+    assert rep.n == len(reqs) and rep.evictions > 0
+    assert ex.size == srv.arena.size
+    assert rep.peak_bytes <= srv.arena.size
+
+
+def test_a_query_never_evicts_its_own_table():
+    """A query whose outputs cannot be placed beside its own table makes room from other tables
+    only (the table it reads stays); one whose outputs could never fit beside it is refused."""
+    build = synth.Request(0.0, "build", image_seed=1000, H=1000, W=1000)
+    other = synth.Request(0.0, "build", image_seed=1001, H=300, W=300)
+    small = synth.Request(0.05, "query", image_seed=0, win_h=990, win_w=990, stride=1)
+    big = synth.Request(0.06, "query", image_seed=0, win_h=2, win_w=2, stride=1)
+    budget = 1000 * 1000 * 8 + 1000 * 1000 + 300 * 300 * 8 + 4096
+    srv, ex, rep = serve([build, other, small], budget=budget, slots=2)
+    assert rep.n == 3 and rep.misses == 0
+    with pytest.raises(ValueError, match="do not fit"):
+        serve([build, other, small, big], budget=budget, slots=2)
+
+
+def test_a_table_that_splits_the_free_space_is_rebuilt_for_its_query():
+    """The only resident table sits between two free runs, neither of which holds the query's
+    outputs: with nothing in flight the table is given up and rebuilt (a miss), and the query is
+    then served from the rebuilt table."""
+    clock = Clock()
+    ex = FakeExecutor(clock)
+    a = synth.Request(0.0, "build", image_seed=1000, H=1000, W=1000)
+    q = synth.Request(0.5, "query", image_seed=0, win_h=2, win_w=2, stride=1)
+    budget = 8_000_000 + 3_000_000 + 3_500_000
+    srv = Server(ex, budget_bytes=budget, slots=1)
+    srv.builds[0] = a
+    from paper_2410_16291_amd.serve import Resident
+    # place the table in the middle by hand: 3 MB free below it, 3.5 MB above
+    off = srv.arena.alloc(3_000_000)
+    r = Resident(0, 1000, 1000, Arena.rounded(8_000_000), offset=srv.arena.alloc(8_000_000), state="resident")
+    srv.arena.release(off)
+    ex.reserve(srv.arena.size)
+    ex._take(r.offset, 8_000_000, ("table", 0))
+    r.tables = ("table", 0)
+    srv.res[0] = r
+    srv.used = r.nbytes
+    assert not srv.arena.fits([ex.query_transient_bytes(q, r)])
+    rep = srv.run([q], clock=clock, idle=clock.idle)
+    assert rep.n == 1 and rep.misses == 1 and rep.evictions == 1
+
+
+def test_cyclic_gc_is_paused_during_the_loop_and_restored():
+    import gc
+    seen = []
+
+    class Watch(FakeExecutor):
+        def is_done(self, h):
+            seen.append(gc.isenabled())
+            return super().is_done(h)
+
+    clock = Clock()
+    assert gc.isenabled()
+    Server(Watch(clock), budget_bytes=200e9, slots=2).run(stream(duration=0.2), clock=clock, idle=clock.idle)
+    assert seen and not any(seen)
+    assert gc.isenabled()
