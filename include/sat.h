@@ -149,7 +149,9 @@ sat_status sat_column_totals(const void *image, sat_dtype pixel_type, int64_t H,
  * rows_above bounds the carry: every carry[x] must be at most rows_above * max_pixel (and
  * carry_sq[x] at most rows_above * max_pixel^2), as column totals of rows_above rows are.  The
  * host refuses (rows_above + H) * max_pixel(^2) >= 2^62 with SAT_ERR_OVERFLOW; a carry beyond
- * 2^62 - 1 - H * max_pixel(^2) makes sat_workspace_check report SAT_ERR_DEVICE.
+ * 2^62 - 1 - H * max_pixel(^2) makes sat_workspace_check report SAT_ERR_DEVICE.  A build without
+ * sat_sq whose (rows_above + H) * max_pixel is below 2^30 keeps its lookback words in 32 bits,
+ * and there the bound is 2^30 - 1 - H * max_pixel.
  * Other arguments, workspace (sat_build_workspace_bytes(H, W, ...)) and errors as sat_build;
  * a carry with sat_sq needs carry_sq; carries and totals 8-byte aligned. */
 sat_status sat_build_band(const void *image, sat_dtype pixel_type, int64_t H, int64_t W,

@@ -305,6 +305,14 @@ void fill_desc(satk::BuildDesc &d, const satk::BuildVariant &v, const void *imag
     d.stress = static_cast<uint32_t>(g_force[3]);
 }
 
+// Whether a build of `rows` rows in all (rows above included) may keep 32-bit lookback state
+// words: a variant whose strips run the lookback, no squared table, and every column total below
+// 2^30.
+bool narrow_state(const satk::BuildVariant &v, bool sq, int64_t rows, int bpp) {
+    const uint64_t maxpix = bpp == 1 ? 255u : 65535u;
+    return v.lookback() && !sq && rows >= 0 && static_cast<uint64_t>(rows) * maxpix < (uint64_t(1) << 30);
+}
+
 sat_status validate_build_item(const void *image, sat_dtype pixel_type, int64_t H, int64_t W, int64_t ipitch,
                                const uint64_t *sat, const uint64_t *sat_sq, int64_t spitch, const char *who) {
     if (!image || !sat) return fail(SAT_ERR_ARG, "%s: image and sat must be non-NULL", who);
@@ -431,6 +439,7 @@ sat_status build_one(const void *image, sat_dtype pixel_type, int64_t H, int64_t
     d.carry_q = carry_sq;
     d.total = total;
     d.total_q = total_sq;
+    d.narrow = narrow_state(var, sq, rows_above + H, bpp) ? 1u : 0u;
     const int64_t words = state_words_for(var, H, W, sq, strip_h);
     hipError_t e = satk::launch_build(v, bpp, sq, &d, 1, nullptr, d.nstrips, workspace, words,
                                       static_cast<hipStream_t>(stream));
@@ -632,7 +641,7 @@ namespace {
 
 // Geometry of the power build (for strip heights and state sizes): 4 pixels per lane, 16 rows per
 // wave, 4 compute waves.
-const satk::BuildVariant kPowVariant{"power_px4_rw16_nw4", 4, 16, 4, satk::MODE_HELPER};
+const satk::BuildVariant kPowVariant{"power_px4_rw16_nw4", 4, 16, 4, satk::MODE_HELPER, 1};
 static_assert(4 * 64 == satk::kPowBlockW && 16 * 4 == satk::kPowStripH, "power build geometry");
 
 int64_t power_state_words(int64_t H, int64_t W, int k, int strip_h) {
@@ -826,6 +835,9 @@ static sat_status plan_build_batch(const sat_batch_item *items, int32_t n, sat_d
         d[i].first_item = total;
         total += d[i].nstrips;
     }
+    bool narrow = true;
+    for (int i = 0; i < n; ++i) narrow = narrow && narrow_state(var, sq, items[i].H, bpp);
+    for (int i = 0; i < n; ++i) d[i].narrow = narrow ? 1u : 0u;
     *variant = v;
     *state_words = (off + 1) & ~1ll;
     *items_total = total;

@@ -135,6 +135,32 @@ __device__ __forceinline__ void stress_delay(uint32_t seed, int strip, int64_t x
     for (uint32_t i = 0; i < n; ++i) __builtin_amdgcn_s_sleep(8);
 }
 
+// Lookback state words: the value in the low bits, the status in the top two (0: not yet
+// published, kAggregate: the strip's own column total, kPrefix: the inclusive column total of
+// every strip through this one).  64-bit words hold any total a build can reach; 32-bit words
+// serve builds whose column totals stay below 2^30 (no squared table and (rows above + H) *
+// max_pixel < 2^30, decided by the host per launch): half the lookback's traffic and half the
+// state to clear.
+constexpr uint32_t kAggregate = 1u;
+constexpr uint32_t kPrefix = 2u;
+
+template <typename SW>
+struct StateWord {
+    static constexpr int kShift = 8 * static_cast<int>(sizeof(SW)) - 2;
+    static constexpr SW kMask = (static_cast<SW>(1) << kShift) - 1;
+    static __device__ __forceinline__ SW make(uint32_t status, uint64_t value) {
+        return (static_cast<SW>(status) << kShift) | static_cast<SW>(value);
+    }
+    static __device__ __forceinline__ uint32_t status(SW w) { return static_cast<uint32_t>(w >> kShift); }
+    static __device__ __forceinline__ uint64_t value(SW w) { return static_cast<uint64_t>(w & kMask); }
+    static __device__ __forceinline__ void store(SW *p, SW v) {
+        __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    static __device__ __forceinline__ SW load(const SW *p) {
+        return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+};
+
 __device__ __forceinline__ void store_state(uint64_t *p, uint64_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -460,14 +486,17 @@ struct Build {
 
     // Strip 0 of a band build: the column totals above the strip are the carried totals of the
     // rows above the image (zero without a carry).  Every lookback value of the band is then a
-    // carry plus at most H maximal pixels, which must stay below 2^62: a carry above
-    // 2^62 - 1 - H * max_pixel (the host has checked that H * max_pixel < 2^62) sets fault bit 1.
+    // carry plus at most H maximal pixels, which must stay below the state word's value range
+    // (2^62, or 2^30 for 32-bit words; the host has checked that H * max_pixel fits): a carry
+    // above that range less H * max_pixel sets fault bit 1.
+    template <typename SW>
     static __device__ __forceinline__ void seed(const BuildDesc &d, int64_t xb, int lane, uint64_t (&v)[PX],
                                                 uint64_t (&vq)[PX], unsigned int *fault) {
         if (!d.carry) return;
         constexpr uint64_t kMaxPix = sizeof(T) == 1 ? 255u : 65535u;
-        const uint64_t room = kValueMask - static_cast<uint64_t>(d.H) * kMaxPix;
-        const uint64_t room_q = kValueMask - static_cast<uint64_t>(d.H) * kMaxPix * kMaxPix;
+        constexpr uint64_t kRange = static_cast<uint64_t>(StateWord<SW>::kMask);
+        const uint64_t room = kRange - static_cast<uint64_t>(d.H) * kMaxPix;
+        const uint64_t room_q = kRange - static_cast<uint64_t>(d.H) * kMaxPix * kMaxPix;
         bool big = false;
 #pragma unroll
         for (int p = 0; p < PX; ++p) {
@@ -498,82 +527,34 @@ struct Build {
         }
     }
 
-    static __device__ void lookback(const BuildDesc &d, int strip, int64_t xb, int lane,
-                                    const uint64_t (&a)[PX], const uint64_t (&aq)[PX],
-                                    uint64_t (&v)[PX], uint64_t (&vq)[PX], uint64_t *state,
-                                    unsigned int *fault) {
-        uint64_t *mine = state + d.state_off + static_cast<int64_t>(strip) * d.Wp + xb + lane;
-        uint64_t *mine_q = state + d.state_q_off + static_cast<int64_t>(strip) * d.Wp + xb + lane;
-#pragma unroll
-        for (int p = 0; p < PX; ++p) { v[p] = 0; vq[p] = 0; }
-        if (strip == 0) {
-            seed(d, xb, lane, v, vq, fault);
-            stress_delay(d.stress, strip, xb, 0);
-#pragma unroll
-            for (int p = 0; p < PX; ++p) {
-                store_state(mine + lslot(p), kStPrefix | (v[p] + a[p]));
-                if (SQ) store_state(mine_q + lslot(p), kStPrefix | (vq[p] + aq[p]));
+    // Column totals of all strips above `strip` for this lane's PX columns by decoupled lookback
+    // over the state words of the strips above (32-bit words when the build's descriptor says its
+    // totals fit them).  Run by one full wave.
+    static __device__ __forceinline__ void lookback(const BuildDesc &d, int strip, int64_t xb, int lane,
+                                                    const uint64_t (&a)[PX], const uint64_t (&aq)[PX],
+                                                    uint64_t (&v)[PX], uint64_t (&vq)[PX], uint64_t *state,
+                                                    unsigned int *fault) {
+        if constexpr (!SQ) {
+            if (d.narrow) {
+                lookback_win_t<1, uint32_t>(d, strip, xb, lane, a, aq, v, vq, state, fault);
+                return;
             }
-            emit_total(d, strip, xb, lane, v, a, vq, aq);
-            return;
         }
-        stress_delay(d.stress, strip, xb, 1);
-#pragma unroll
-        for (int p = 0; p < PX; ++p) {
-            store_state(mine + lslot(p), kStAggregate | a[p]);
-            if (SQ) store_state(mine_q + lslot(p), kStAggregate | aq[p]);
-        }
-        constexpr uint32_t kAll = SQ ? ((1u << (2 * PX)) - 1u) : ((1u << PX) - 1u);
-        uint32_t done = 0;
-        uint32_t spins = 0;
-        int j = strip - 1;
-        for (;;) {
-            const uint64_t *up = state + d.state_off + static_cast<int64_t>(j) * d.Wp + xb + lane;
-            const uint64_t *up_q = state + d.state_q_off + static_cast<int64_t>(j) * d.Wp + xb + lane;
-            uint64_t w[PX], wq[PX];
-            bool ready = true;
-#pragma unroll
-            for (int p = 0; p < PX; ++p) {
-                w[p] = 0;
-                wq[p] = 0;
-                if (!(done & (1u << p))) {
-                    w[p] = load_state(up + lslot(p));
-                    ready = ready && (w[p] >> 62) != 0;
-                }
-                if (SQ && !(done & (1u << (PX + p)))) {
-                    wq[p] = load_state(up_q + lslot(p));
-                    ready = ready && (wq[p] >> 62) != 0;
-                }
+        lookback_win_t<1, uint64_t>(d, strip, xb, lane, a, aq, v, vq, state, fault);
+    }
+
+    template <int WIN>
+    static __device__ __forceinline__ void lookback_win(const BuildDesc &d, int strip, int64_t xb, int lane,
+                                                        const uint64_t (&a)[PX], const uint64_t (&aq)[PX],
+                                                        uint64_t (&v)[PX], uint64_t (&vq)[PX], uint64_t *state,
+                                                        unsigned int *fault) {
+        if constexpr (!SQ) {
+            if (d.narrow) {
+                lookback_win_t<WIN, uint32_t>(d, strip, xb, lane, a, aq, v, vq, state, fault);
+                return;
             }
-            if (!__all(ready)) {
-                if (++spins > kSpinLimit) {
-                    atomicOr(fault, 1u);
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(2);
-                continue;
-            }
-#pragma unroll
-            for (int p = 0; p < PX; ++p) {
-                if (!(done & (1u << p))) {
-                    v[p] += w[p] & kValueMask;
-                    if ((w[p] >> 62) == 2 || j == 0) done |= 1u << p;
-                }
-                if (SQ && !(done & (1u << (PX + p)))) {
-                    vq[p] += wq[p] & kValueMask;
-                    if ((wq[p] >> 62) == 2 || j == 0) done |= 1u << (PX + p);
-                }
-            }
-            if (__all(done == kAll)) break;
-            --j;
         }
-        stress_delay(d.stress, strip, xb, 2);
-#pragma unroll
-        for (int p = 0; p < PX; ++p) {
-            store_state(mine + lslot(p), kStPrefix | (v[p] + a[p]));
-            if (SQ) store_state(mine_q + lslot(p), kStPrefix | (vq[p] + aq[p]));
-        }
-        emit_total(d, strip, xb, lane, v, a, vq, aq);
+        lookback_win_t<WIN, uint64_t>(d, strip, xb, lane, a, aq, v, vq, state, fault);
     }
 
     // Decoupled lookback that reads the states of WIN strips per round trip (j, j-1, ...,
@@ -581,23 +562,29 @@ struct Build {
     // aggregates are added and the walk goes on, an inclusive prefix (or strip 0) closes the
     // column.  When all strips are in flight together, prefixes propagate one strip per memory
     // round trip; the window lets a walk cover WIN strips per round trip instead.
-    template <int WIN>
-    static __device__ void lookback_win(const BuildDesc &d, int strip, int64_t xb, int lane,
-                                        const uint64_t (&a)[PX], const uint64_t (&aq)[PX],
-                                        uint64_t (&v)[PX], uint64_t (&vq)[PX], uint64_t *state,
-                                        unsigned int *fault) {
+    // A strip publishes its aggregates before it reads anything.  (Publishing them only for the
+    // columns that the strip above had not yet closed saves a store per column where it had, but
+    // holding them back for one round trip slowed the whole build by a third: strips below wait
+    // on them.)
+    template <int WIN, typename SW>
+    static __device__ __forceinline__ void lookback_win_t(const BuildDesc &d, int strip, int64_t xb, int lane,
+                                          const uint64_t (&a)[PX], const uint64_t (&aq)[PX],
+                                          uint64_t (&v)[PX], uint64_t (&vq)[PX], uint64_t *state_words,
+                                          unsigned int *fault) {
+        using SWd = StateWord<SW>;
+        SW *state = reinterpret_cast<SW *>(state_words);
         const int64_t col0 = xb + lane;
-        uint64_t *mine = state + d.state_off + static_cast<int64_t>(strip) * d.Wp + col0;
-        uint64_t *mine_q = state + d.state_q_off + static_cast<int64_t>(strip) * d.Wp + col0;
+        SW *mine = state + d.state_off + static_cast<int64_t>(strip) * d.Wp + col0;
+        SW *mine_q = state + d.state_q_off + static_cast<int64_t>(strip) * d.Wp + col0;
 #pragma unroll
         for (int p = 0; p < PX; ++p) { v[p] = 0; vq[p] = 0; }
         if (strip == 0) {
-            seed(d, xb, lane, v, vq, fault);
+            seed<SW>(d, xb, lane, v, vq, fault);
             stress_delay(d.stress, strip, xb, 0);
 #pragma unroll
             for (int p = 0; p < PX; ++p) {
-                store_state(mine + lslot(p), kStPrefix | (v[p] + a[p]));
-                if (SQ) store_state(mine_q + lslot(p), kStPrefix | (vq[p] + aq[p]));
+                SWd::store(mine + lslot(p), SWd::make(kPrefix, v[p] + a[p]));
+                if (SQ) SWd::store(mine_q + lslot(p), SWd::make(kPrefix, vq[p] + aq[p]));
             }
             emit_total(d, strip, xb, lane, v, a, vq, aq);
             return;
@@ -605,26 +592,26 @@ struct Build {
         stress_delay(d.stress, strip, xb, 1);
 #pragma unroll
         for (int p = 0; p < PX; ++p) {
-            store_state(mine + lslot(p), kStAggregate | a[p]);
-            if (SQ) store_state(mine_q + lslot(p), kStAggregate | aq[p]);
+            SWd::store(mine + lslot(p), SWd::make(kAggregate, a[p]));
+            if (SQ) SWd::store(mine_q + lslot(p), SWd::make(kAggregate, aq[p]));
         }
         constexpr uint32_t kAll = SQ ? ((1u << (2 * PX)) - 1u) : ((1u << PX) - 1u);
         uint32_t done = 0;
         uint32_t spins = 0;
         int j = strip - 1;
         for (;;) {
-            uint64_t w[WIN][PX], wq[WIN][PX];
+            SW w[WIN][PX], wq[WIN][PX];
 #pragma unroll
             for (int k = 0; k < WIN; ++k) {
                 const int jj = j - k;
-                const uint64_t *up = state + d.state_off + static_cast<int64_t>(jj) * d.Wp + col0;
-                const uint64_t *up_q = state + d.state_q_off + static_cast<int64_t>(jj) * d.Wp + col0;
+                const SW *up = state + d.state_off + static_cast<int64_t>(jj) * d.Wp + col0;
+                const SW *up_q = state + d.state_q_off + static_cast<int64_t>(jj) * d.Wp + col0;
 #pragma unroll
                 for (int p = 0; p < PX; ++p) {
                     w[k][p] = 0;
                     wq[k][p] = 0;
-                    if (jj >= 0 && !(done & (1u << p))) w[k][p] = load_state(up + lslot(p));
-                    if (SQ && jj >= 0 && !(done & (1u << (PX + p)))) wq[k][p] = load_state(up_q + lslot(p));
+                    if (jj >= 0 && !(done & (1u << p))) w[k][p] = SWd::load(up + lslot(p));
+                    if (SQ && jj >= 0 && !(done & (1u << (PX + p)))) wq[k][p] = SWd::load(up_q + lslot(p));
                 }
             }
             int consumed = 0;
@@ -636,8 +623,8 @@ struct Build {
                 bool ready = true;
 #pragma unroll
                 for (int p = 0; p < PX; ++p) {
-                    if (!(done & (1u << p))) ready = ready && (w[k][p] >> 62) != 0;
-                    if (SQ && !(done & (1u << (PX + p)))) ready = ready && (wq[k][p] >> 62) != 0;
+                    if (!(done & (1u << p))) ready = ready && SWd::status(w[k][p]) != 0;
+                    if (SQ && !(done & (1u << (PX + p)))) ready = ready && SWd::status(wq[k][p]) != 0;
                 }
                 if (!__all(ready)) {
                     stalled = true;
@@ -646,12 +633,12 @@ struct Build {
 #pragma unroll
                 for (int p = 0; p < PX; ++p) {
                     if (!(done & (1u << p))) {
-                        v[p] += w[k][p] & kValueMask;
-                        if ((w[k][p] >> 62) == 2 || jj == 0) done |= 1u << p;
+                        v[p] += SWd::value(w[k][p]);
+                        if (SWd::status(w[k][p]) == kPrefix || jj == 0) done |= 1u << p;
                     }
                     if (SQ && !(done & (1u << (PX + p)))) {
-                        vq[p] += wq[k][p] & kValueMask;
-                        if ((wq[k][p] >> 62) == 2 || jj == 0) done |= 1u << (PX + p);
+                        vq[p] += SWd::value(wq[k][p]);
+                        if (SWd::status(wq[k][p]) == kPrefix || jj == 0) done |= 1u << (PX + p);
                     }
                 }
                 ++consumed;
@@ -669,8 +656,8 @@ struct Build {
         stress_delay(d.stress, strip, xb, 2);
 #pragma unroll
         for (int p = 0; p < PX; ++p) {
-            store_state(mine + lslot(p), kStPrefix | (v[p] + a[p]));
-            if (SQ) store_state(mine_q + lslot(p), kStPrefix | (vq[p] + aq[p]));
+            SWd::store(mine + lslot(p), SWd::make(kPrefix, v[p] + a[p]));
+            if (SQ) SWd::store(mine_q + lslot(p), SWd::make(kPrefix, vq[p] + aq[p]));
         }
         emit_total(d, strip, xb, lane, v, a, vq, aq);
     }
@@ -1820,7 +1807,7 @@ hipError_t launch_totals_typed(const void *img, int64_t H, int64_t W, int64_t pi
     X(13, "helper3_nt_px8_rw12_nw4", 8, 12, 4, MODE_HELPER3, 1, 1, true)
 
 const BuildVariant kVariants[] = {
-#define SAT_X(i, name, px, rw, nw, mode, win, adapt, nt) {name, px, rw, nw, mode},
+#define SAT_X(i, name, px, rw, nw, mode, win, adapt, nt) {name, px, rw, nw, mode, win},
     SAT_BUILD_VARIANTS(SAT_X)
 #undef SAT_X
 };
@@ -1882,11 +1869,12 @@ hipError_t launch_typed(const BuildDesc *descs, int n, const BuildDesc *dev_desc
         constexpr int TH = RW * NW;
         constexpr bool kPrepass = MODE == MODE_REDUCE_SCAN || ((MODE == MODE_HELPER || MODE == MODE_HELPER3) && WIN == 0);
         if (!kPrepass) {
-            const long long pairs = (state_words + 1) / 2;
+            // 32-bit state words fill the first half of the state (the offsets count words)
+            const long long words = descs[0].narrow ? (state_words + 1) / 2 : state_words;
+            const long long pairs = (words + 1) / 2;
             const long long blocks = pairs > 0 ? (pairs + 255) / 256 : 1;
             const unsigned grid = static_cast<unsigned>(blocks < 8192 ? blocks : 8192);
-            hipLaunchKernelGGL(clear_kernel, dim3(grid), dim3(256), 0, stream, state,
-                               static_cast<long long>(state_words), ctrl, descs[0], slot);
+            hipLaunchKernelGGL(clear_kernel, dim3(grid), dim3(256), 0, stream, state, words, ctrl, descs[0], slot);
         } else {
             hipLaunchKernelGGL(clear_kernel, dim3(1), dim3(256), 0, stream, state, 0ll, ctrl, descs[0], slot);
             for (int i = 0; i < n; ++i) {

@@ -33,7 +33,9 @@ struct BuildDesc {
     int32_t sat_vec;      // 1: table rows allow 16-byte vector stores
     uint32_t stress;      // nonzero (tests only): seed of pseudo-random delays before every lookback
                           // publish and fused ready count, to perturb the order strips finish in
-    uint32_t pad_;
+    uint32_t narrow;      // 1: the lookback keeps 32-bit state words (no squared table and every
+                          // column total, carry included, below 2^30); the same for every image
+                          // of a launch, and only for variants whose strips run the lookback
 };
 
 // Workspace layout: 256-byte control header, then the lookback state.
@@ -60,8 +62,11 @@ struct BuildVariant {
     int rw;       // rows per wave
     int nw;       // waves per workgroup
     int mode;     // BuildMode
+    int win;      // strips read this many lookback words per round trip (0: totals from a pre-pass)
     int th() const { return rw * nw; }       // strip height
     int bw() const { return 64 * px; }        // block width
+    // The strips run the decoupled lookback (and may keep 32-bit state words, BuildDesc::narrow).
+    bool lookback() const { return mode != MODE_REDUCE_SCAN && win > 0; }
 };
 
 int build_variant_count();
