@@ -397,12 +397,16 @@ def banded_section(torch, dev, H, W, band_rows):
     host.numpy()[...] = mask
     del mask
     wins = [(h, h) for h in WINDOWS]
-    res = {"workload": "the %dx%d mask above in bands of %d rows (plus the 499 overlap rows each band "
-                       "rebuilds); windows 100/250/500 at stride 1; outputs left on the device" % (H, W, band_rows),
+    res = {"workload": "the %dx%d mask above in bands of %d rows, each band's table rows built from the "
+                       "column totals of the rows above, the last 500 table rows carried to the next band "
+                       "on the device; windows 100/250/500 at stride 1; outputs left on the device; "
+                       "from_device: the image resident in HBM on 128-byte row lines, built in place"
+                       % (H, W, band_rows),
            "band_rows": band_rows}
     for name, src in (("from_pinned_host", host), ("from_device", None)):
         if src is None:
-            src = host.to(dev)
+            src = api.empty_image(H, W, torch.uint8, dev)
+            src.copy_(host)
         job = banded.BandedWindowSums(H, W, wins, 1, "u8", band_rows, dev)
         job.run(lambda r0, r1: src[r0:r1], lambda i, k0, rows: None)        # warm-up
         torch.cuda.synchronize()
@@ -411,7 +415,8 @@ def banded_section(torch, dev, H, W, band_rows):
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         res[name] = {"ms": round(dt * 1e3, 2), "gpix_s": round(H * W / dt / 1e9, 2), "bands": len(job.plan),
-                     "device_GB": round((sum(t.numel() for t in job.dimg) + job.table.numel() * 8) / 1e9, 2)}
+                     "device_GB": round((sum(t.storage().nbytes() for t in (job.up.dimg if job.up else []))
+                                         + sum(t.storage().nbytes() for t in job.tables)) / 1e9, 2)}
         del job, src
         torch.cuda.empty_cache()
     # the whole table in HBM, built band by band as the image streams in (no overlap rows: each

@@ -1,26 +1,31 @@
 """Window sums of images whose integral image does not fit in HBM, or that stream from the host.
 
-The image is processed in bands of rows.  For the band of rows [b0, b1) the device builds the
-integral image of rows [r0, b1) only, r0 = b0 - (h_max - 1) rounded down to the stride grid: a
-local table.  A window sum is a difference of table values along both axes, so the sum of any
-window lying inside rows [r0, b1) is the same from the local table as from the table of the
-whole image.  The band emits exactly the output rows whose windows end inside it (their last row
-in [b0, b1)); every such window starts at or after r0.  The full table is never materialised: the
-device holds one band's image rows, its local table and its output rows at a time.
+The image is processed in bands of rows.  Each band's rows of the image's table are built from
+the band's image rows and the column totals of every row above it (sat_build_band), which the
+build advances for the next band: the table values are those of the whole image's table, and no
+image row is built twice.  A window that ends inside the band [b0, b1) may start up to h_max - 1
+rows above b0, and its sum needs the table row just above its first row, so the device keeps the
+last table rows of the bands before (a ring of h_max + stride - 1 rows, copied forward on the
+device after each band) in front of the band's rows: the gather runs over one contiguous view of
+table rows [v0, b1), v0 the first row any output of the band needs on the stride grid.  The band
+emits exactly the output rows whose windows end inside it.  The full table is never
+materialised: the device holds two ring-plus-band tables, the band's image rows when they come
+from the host, and its output rows.
 
 Image rows come from a callback (host numpy rows, a memory map, a generator, pinned host tensors
-or device tensors); pageable host rows are staged through pinned buffers, and every band is
-uploaded on a copy stream while the previous band is being computed.  All window sizes of a band
-come from one pass over its table (window_sum_multi).  Output rows go to a callback as device
-tensors, on the compute stream, valid once that stream is synchronised; `banded_window_sums`
-collects them into host arrays.
+or device tensors).  Device rows are built in place.  Host rows are uploaded into device buffers
+on rows of whole 128-byte lines (pageable rows staged through pinned buffers) on a copy stream,
+each band while the previous band is being computed.  All window sizes of a band come from one
+pass over its table view (window_sum_multi), on a second stream, so that one band's gather
+overlaps the next band's build.  Output rows go to a callback as device tensors, on the gather
+stream, valid once that stream is synchronised; `banded_window_sums` collects them into host
+arrays.
 
-Cost over the whole-image path: the h_max - 1 overlap rows are built again for every band, and
-their outputs are discarded: about (h_max - 1) / band_rows extra table rows per band.
+Cost over the whole-image path: per band, the copy of the ring's rows, and the outputs of the
+view's first rows (windows that end above the band), which the gather computes and drops.
 
 `build_table_streamed` is the other use of bands: the whole image's table in HBM, built band by
-band as the image arrives.  There the bands do not overlap; each band's build starts from the
-column totals of the rows above it and leaves those through its own last row for the next band.
+band as the image arrives, with the same carried column totals.
 """
 from __future__ import annotations
 
@@ -43,24 +48,24 @@ def _check_windows(H: int, W: int, windows: Sequence[Tuple[int, int]], stride: i
 
 
 def band_plan(H: int, h_max: int, stride: int, band_rows: int) -> List[Tuple[int, int, int]]:
-    """[(r0, b0, b1)]: the band of rows [b0, b1) and the first image row r0 its local table starts
-    at (b0 - h_max + 1 rounded down to a multiple of the stride, at least 0)."""
+    """[(v0, b0, b1)]: the band of rows [b0, b1) and the first table row v0 of the view its gather
+    runs on: b0 - h_max rounded down to a multiple of the stride (the row above the first row of
+    any window the band emits), or 0.  b0 - v0 is at most h_max + stride - 1."""
     if band_rows < 1:
         raise ValueError("band_rows must be >= 1")
     plan = []
     b0 = 0
     while b0 < H:
         b1 = min(H, b0 + band_rows)
-        r0 = max(0, b0 - (h_max - 1))
-        r0 -= r0 % stride
-        plan.append((r0, b0, b1))
+        v0 = max(0, (b0 - h_max) // stride * stride)
+        plan.append((v0, b0, b1))
         b0 = b1
     return plan
 
 
-def band_outputs(r0: int, b0: int, b1: int, H: int, h: int, stride: int) -> Tuple[int, int]:
-    """Output rows [k0, k1) of an h-tall window whose last row lies in [b0, b1), and the output
-    row of the local table (rows from r0) that k0 corresponds to."""
+def band_outputs(v0: int, b0: int, b1: int, H: int, h: int, stride: int) -> Tuple[int, int]:
+    """Output rows [k0, k1) of an h-tall window whose last row lies in [b0, b1) (output row k of
+    the image is output row k - v0 / stride of the band's view)."""
     oh = (H - h) // stride + 1
     # last row of output k is k*stride + h - 1; it lies in [b0, b1) for k in [k0, k1)
     k0 = max(0, -(-(b0 - h + 1) // stride))
@@ -78,7 +83,8 @@ class _Uploader:
         self.np_dtype = np.uint8 if pixel_type == "u8" else np.uint16
         self.t_dtype = torch.uint8 if pixel_type == "u8" else torch.uint16
         self.copy = torch.cuda.Stream(dev)
-        self.dimg = [torch.empty((rows_max, W), dtype=self.t_dtype, device=dev) for _ in range(2)]
+        # rows on whole 128-byte lines: the builds take the same plans as on a resident image
+        self.dimg = [api.empty_image(rows_max, W, self.t_dtype, dev) for _ in range(2)]
         self.pinned = [torch.empty((rows_max, W), dtype=torch.uint8 if self.np_dtype == np.uint8 else torch.int16,
                                    pin_memory=True) for _ in range(2)]
         self.uploaded = [torch.cuda.Event() for _ in range(2)]
@@ -128,8 +134,9 @@ class BandedWindowSums:
     """Streams an H x W image through the device in bands and produces window sums.
 
     read_rows(r0, r1) -> image rows [r0, r1) as a (r1-r0, W) numpy array, pinned host tensor or
-    device tensor.
-    on_rows(i, k0, rows) receives, for window i, the device tensor of its output rows [k0, k0+n).
+    device tensor (built in place: unit column stride, any row pitch).
+    on_rows(i, k0, rows) receives, for window i, the device tensor of its output rows [k0, k0+n),
+    on the gather stream (current while on_rows runs), valid once that stream is synchronised.
     """
 
     def __init__(self, H: int, W: int, windows: Sequence[Tuple[int, int]], stride: int = 1,
@@ -146,45 +153,99 @@ class BandedWindowSums:
         self.plan = band_plan(H, self.h_max, stride, band_rows)
         big = any(api.default_out_dtype(h, w, pixel_type) == torch.uint64 for h, w in self.windows)
         self.out_dtype = out_dtype or (torch.uint64 if big else torch.uint32)
-        self.compute = torch.cuda.Stream(self.dev)
-        rows_max = max(b1 - r0 for r0, _, b1 in self.plan)
-        self.rows_max = rows_max
-        self.up = _Uploader(rows_max, W, pixel_type, self.dev)      # double-buffered image bands
-        self.dimg = self.up.dimg
-        self.table = api.empty_table(rows_max, W, self.dev)
+        self.compute = torch.cuda.Stream(self.dev)           # builds (and uploads' hand-over)
+        self.gather = torch.cuda.Stream(self.dev)            # gathers
+        self.rows_max = max(b1 - b0 for _, b0, b1 in self.plan)
+        self.ring = self.h_max + stride - 1          # table rows kept in front of each band
+        self.up = None                               # host-row uploads, made on first use
+        # two ring-plus-band tables, alternating: band i's ring rows are copied into the other
+        self.tables = [api.empty_table(self.ring + self.rows_max, W, self.dev) for _ in range(2)]
+        self.carry = api.empty_totals(W, self.dev)
         self.bpp = 1 if pixel_type == "u8" else 2
+        self.t_dtype = torch.uint8 if pixel_type == "u8" else torch.uint16
+
+    def _device_rows(self, rows, n: int) -> Optional[torch.Tensor]:
+        """`rows` itself when it is a device band the build can read in place, else None."""
+        if not (isinstance(rows, torch.Tensor) and rows.is_cuda):
+            return None
+        if tuple(rows.shape) != (n, self.W):
+            raise ValueError("read_rows returned shape %s, expected %s" % (tuple(rows.shape), (n, self.W)))
+        if rows.dtype not in (self.t_dtype, torch.int16 if self.bpp == 2 else torch.int8):
+            raise ValueError("read_rows returned %s rows for %s pixels" % (rows.dtype, self.pixel_type))
+        if rows.stride(1) != 1:
+            return None
+        return rows if rows.dtype == self.t_dtype else rows.view(self.t_dtype)
 
     def run(self, read_rows: Callable, on_rows: Callable) -> None:
-        plan = self.plan
-        self.up.start(self.compute)
-        self.up.stage(0, plan[0][0], plan[0][2], read_rows)
-        for bi, (r0, b0, b1) in enumerate(plan):
+        """Builds run on the compute stream, gathers on a second stream: band i's gather overlaps
+        band i+1's build, whose strips alone do not fill the GPU.  The two tables alternate; a
+        table is written again (the next ring, then the band two later) only after the gather
+        that read it has finished."""
+        plan, R, W = self.plan, self.ring, self.W
+        A, B = self.compute, self.gather
+        pending = None          # host rows: staged through the uploader
+        first_rows = read_rows(plan[0][1], plan[0][2])
+        dev_rows = self._device_rows(first_rows, plan[0][2] - plan[0][1])
+        if dev_rows is None:
+            if self.up is None:
+                self.up = _Uploader(self.rows_max, W, self.pixel_type, self.dev)
+            self.up.start(A)
+            self.up.stage(0, plan[0][1], plan[0][2], lambda a, b: first_rows)
+            pending = 0
+        B.wait_stream(A)
+        gathered = [None, None]          # event: the last gather that read table 0 / 1 is done
+        for bi, (v0, b0, b1) in enumerate(plan):
+            n = b1 - b0
             slot = bi & 1
-            if bi + 1 < len(plan):
-                nr0, _, nb1 = plan[bi + 1]
-                self.up.stage(slot ^ 1, nr0, nb1, read_rows)
-            n = b1 - r0
-            img = self.up.acquire(self.compute, slot, n)
-            S = self.table[:n]
-            ws = api.workspace(api.build_workspace_bytes(n, self.W, self.bpp, False), self.dev, self.compute)
-            api.sat_build(img, sat=S, ws=ws, stream=self.compute)
-            self.up.release(self.compute, slot)
-            # every window with output rows in this band, in one pass over the band's table
+            if pending is not None:
+                if bi + 1 < len(plan):
+                    self.up.stage(slot ^ 1, plan[bi + 1][1], plan[bi + 1][2], read_rows)
+                img = self.up.acquire(A, slot, n)
+            else:
+                img = dev_rows if bi == 0 else self._device_rows(read_rows(b0, b1), n)
+                if img is None:
+                    raise ValueError("read_rows must return device rows for every band once it has for one")
+            T = self.tables[slot]
+            # the band's table rows, after the ring's R rows (global row y at index y - b0 + R);
+            # table `slot` was last read by the gather of band bi - 2, which the copy of band bi - 1
+            # below already waited for
+            with torch.cuda.stream(A):
+                ws = api.workspace(api.build_workspace_bytes(n, W, self.bpp, False), self.dev, A)
+                api.sat_build_band(img, carry=None if bi == 0 else self.carry, rows_above=b0,
+                                   sat=T[R:R + n], total=self.carry, ws=ws, stream=A)
+                built = torch.cuda.Event()
+                built.record(A)
+                if pending is not None:
+                    self.up.release(A, slot)
+                if bi + 1 < len(plan):
+                    # the next band's ring: this table's rows [n, n + R), global rows [b1 - R, b1),
+                    # into the other table once the gather of band bi - 1 has read it
+                    if gathered[slot ^ 1] is not None:
+                        A.wait_event(gathered[slot ^ 1])
+                    self.tables[slot ^ 1][:R].copy_(T[n:n + R])
             todo = []
             for i, (h, w) in enumerate(self.windows):
-                k0, k1 = band_outputs(r0, b0, b1, self.H, h, self.stride)
-                if k1 > k0 and h <= n:
+                k0, k1 = band_outputs(v0, b0, b1, self.H, h, self.stride)
+                if k1 > k0:
                     todo.append((i, k0, k1))
             if not todo:
                 continue
-            with torch.cuda.stream(self.compute):
-                outs = api.window_sum_multi(S, [self.windows[i] for i, _, _ in todo], self.stride,
-                                            pixel_type=self.pixel_type, out_dtype=self.out_dtype,
-                                            stream=self.compute)
+            with torch.cuda.stream(B):
+                B.wait_event(built)
+                view = T[v0 - b0 + R:R + n]
+                hs = [self.windows[i] for i, _, _ in todo]
+                if any(h > view.shape[0] for h, _ in hs):
+                    raise AssertionError("band view shorter than a window it emits")
+                outs = api.window_sum_multi(view, hs, self.stride, pixel_type=self.pixel_type,
+                                            out_dtype=self.out_dtype, stream=B)
+                done = torch.cuda.Event()
+                done.record(B)
+                gathered[slot] = done
                 for (i, k0, k1), out in zip(todo, outs):
-                    lk0 = k0 - r0 // self.stride       # output row of the local table
+                    lk0 = k0 - v0 // self.stride       # output row of the view
                     on_rows(i, k0, out[lk0:lk0 + (k1 - k0)])
-        self.compute.synchronize()
+        A.wait_stream(B)
+        A.synchronize()
 
 
 def banded_window_sums(read_rows: Callable, H: int, W: int, windows: Sequence[Tuple[int, int]], stride: int = 1,

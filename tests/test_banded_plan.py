@@ -1,5 +1,6 @@
 """Band arithmetic of the out-of-core path, on the CPU: every output row is produced by exactly one
-band, from a local table whose rows contain its whole window."""
+band, from a view of table rows that holds the row above its window (or starts at image row 0),
+on the view's stride grid, with at most h_max + stride - 1 rows carried from the bands above."""
 import itertools
 
 import pytest
@@ -17,6 +18,7 @@ def test_every_output_row_once_and_window_inside_local_rows(H, h_max, stride, ba
         assert b1 == b0n
     for r0, b0, b1 in plan:
         assert r0 % stride == 0 and 0 <= r0 <= b0 < b1 <= H
+        assert b0 - r0 <= h_max + stride - 1                   # the ring the device keeps
     for h in sorted({1, h_max, max(1, h_max // 2)}):
         oh = (H - h) // stride + 1
         seen = []
@@ -25,8 +27,8 @@ def test_every_output_row_once_and_window_inside_local_rows(H, h_max, stride, ba
             for k in range(k0, k1):
                 top, last = k * stride, k * stride + h - 1
                 assert b0 <= last < b1                          # emitted by the band holding its last row
-                assert r0 <= top and last < b1                  # whole window inside the local rows
-                assert (top - r0) % stride == 0                 # on the local table's stride grid
+                assert top == 0 or r0 <= top - 1                # the row above the window is in the view
+                assert (top - r0) % stride == 0                 # on the view's stride grid
             seen.extend(range(k0, k1))
         assert seen == list(range(oh))
 
