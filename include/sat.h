@@ -320,8 +320,10 @@ sat_status window_moments(const uint64_t *const *tables, int32_t k, sat_dtype pi
  * variants that take shorter strips (-1 restores the variant's height; sat_batch_workspace_bytes
  * follows it).  Kind 3 (tests only) sets a nonzero seed on this thread that makes later builds
  * sleep a pseudo-random time before every lookback publication, to perturb the order in which
- * strips finish; 0 turns it off.  Results are unchanged.  Used by the tile-shape tuner and the
- * tests. */
+ * strips finish; 0 turns it off.  Kind 4 sets the number of column segments (1..8; 0 restores
+ * the built-in choice) that later helper-wave builds of one image of at most 32768 rows on this
+ * thread split each strip into, each segment a separate work item (capped at one per block).
+ * Results are unchanged.  Used by the tile-shape tuner and the tests. */
 int32_t sat_variant_count(int32_t kind);
 const char *sat_variant_name(int32_t kind, int32_t index);
 sat_status sat_force_variant(int32_t kind, int32_t index);

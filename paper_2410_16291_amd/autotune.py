@@ -66,6 +66,20 @@ def forced_strip(rows: Optional[int]):
         api.force_variant(2, -1)
 
 
+@contextlib.contextmanager
+def forced_segments(n: Optional[int]):
+    """Run the body with helper-wave builds of one image on this thread split into `n` column
+    segments per strip (None: the built-in choice)."""
+    if n is None:
+        yield
+        return
+    api.force_variant(4, int(n))
+    try:
+        yield
+    finally:
+        api.force_variant(4, 0)
+
+
 def strip_height(name: str) -> Optional[int]:
     """Full strip height (rows per wave x waves) of a build variant, from its name."""
     m = re.search(r"rw(\d+)_nw(\d+)", name)

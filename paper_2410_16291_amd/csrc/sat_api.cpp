@@ -3,6 +3,7 @@
 // synchronous before the first HIP call, so every error path is testable without a GPU.
 #include "sat.h"
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -15,8 +16,9 @@
 namespace {
 
 thread_local std::string g_err = "no error";
-// build variant, gather variant, batch strip height, lookback stress seed (0: off)
-thread_local int g_force[4] = {-1, -1, -1, 0};
+// build variant, gather variant, batch strip height, lookback stress seed (0: off), column
+// segments of a helper-wave build (0: the built-in choice)
+thread_local int g_force[5] = {-1, -1, -1, 0, 0};
 
 sat_status fail(sat_status st, const char *fmt, ...) {
     char buf[512];
@@ -251,6 +253,35 @@ sat_status check_build_variant(int v, int bpp, bool sq, const char *who) {
     return SAT_OK;
 }
 
+// Column segments per strip of a helper-wave build of one image (1: each strip sweeps whole rows).
+// The strips are the build's parallelism.  On images of at most kSegAutoRows rows each strip is
+// split into segments of at least kMinSegBlocks blocks that separate workgroups build (a
+// pre-pass supplies the row totals left of each segment), about two rounds of resident
+// workgroups' worth.  Measured with the helper pipelines (ms, whole rows -> built-in segments):
+// 8-bit 2000 x 4000 0.096 -> 0.079, 2000 x 16000 0.218 -> 0.131, 3000 x 12000 0.207 -> 0.147,
+// 4096 x 16000 0.262 -> 0.170-0.186, 2048 x 32768 0.336 -> 0.173, 1500 x 85000 0.818 -> 0.292;
+// 16-bit with squares 4096 x 8192 0.250 -> 0.178.  Taller images gained nothing or lost:
+// 16-bit 8192^2 with squares 0.314 -> 0.309-0.311, 8750 x 85000 1.62 -> 1.59-1.78, 16000^2
+// 0.49 -> 0.59.  A forced count (sat_force_variant kind 4) applies up to kSegMaxRows rows, for
+// which the workspace reserves the pre-pass area.
+constexpr int64_t kSegAutoRows = 4096;
+int choose_segments(int v, const satk::BuildDesc &d, int bpp, bool sq) {
+    const satk::BuildVariant &var = satk::build_variant(v);
+    if ((var.mode != satk::MODE_HELPER && var.mode != satk::MODE_HELPER3) || !var.lookback() ||
+        d.H > satk::kSegMaxRows)
+        return 1;
+    const int forced = g_force[4];
+    if (forced <= 0 && d.H > kSegAutoRows) return 1;
+    const int64_t most = std::min<int64_t>(satk::kMaxSeg, forced > 0 ? d.nblocks : d.nblocks / satk::kMinSegBlocks);
+    if (most < 2) return 1;
+    int64_t want = forced;
+    if (forced <= 0) {
+        const int64_t cap = satk::build_variant_capacity(v, bpp, sq);
+        want = cap > 0 ? std::max<int64_t>(2, 2 * cap / d.nstrips) : 1;
+    }
+    return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(want, most)));
+}
+
 int64_t state_words_for(const satk::BuildVariant &v, int64_t H, int64_t W, bool sq, int strip_h) {
     const int64_t strips = (H + strip_h - 1) / strip_h;
     const int64_t wp = (W + v.bw() - 1) / v.bw() * v.bw();
@@ -273,6 +304,13 @@ int64_t build_state_words_any(int64_t H, int64_t W, int bpp, bool sq) {
         if (w > words) words = w;
     }
     return words;
+}
+
+// Offset of the segment pre-pass area in a single-image build's workspace: after the largest
+// lookback state any variant may use, on a 256-byte boundary.
+size_t seg_area_offset(int64_t H, int64_t W, int bpp, bool sq) {
+    const size_t end = sizeof(satk::BuildCtrl) + 8 * static_cast<size_t>(build_state_words_any(H, W, bpp, sq));
+    return (end + 255) / 256 * 256;
 }
 
 void fill_desc(satk::BuildDesc &d, const satk::BuildVariant &v, const void *image, int bpp, int64_t H,
@@ -303,6 +341,8 @@ void fill_desc(satk::BuildDesc &d, const satk::BuildVariant &v, const void *imag
                     (!sat_sq || reinterpret_cast<uintptr_t>(sat_sq) % 16 == 0);
     d.sat_vec = (sa && spitch % 2 == 0) ? 1 : 0;
     d.stress = static_cast<uint32_t>(g_force[3]);
+    d.nseg = 1;
+    d.seg_blocks = d.nblocks;
 }
 
 // Whether a build of `rows` rows in all (rows above included) may keep 32-bit lookback state
@@ -441,8 +481,23 @@ sat_status build_one(const void *image, sat_dtype pixel_type, int64_t H, int64_t
     d.total_q = total_sq;
     d.narrow = narrow_state(var, sq, rows_above + H, bpp) ? 1u : 0u;
     const int64_t words = state_words_for(var, H, W, sq, strip_h);
-    hipError_t e = satk::launch_build(v, bpp, sq, &d, 1, nullptr, d.nstrips, workspace, words,
-                                      static_cast<hipStream_t>(stream));
+    const int nseg = choose_segments(v, d, bpp, sq);
+    if (nseg > 1) {
+        d.seg_blocks = (d.nblocks + nseg - 1) / nseg;
+        d.nseg = (d.nblocks + d.seg_blocks - 1) / d.seg_blocks;
+        // pre-pass area: row sums of segments 0 .. kMaxSeg - 2 (then of squares), then the
+        // boundary columns (then of squares)
+        const int64_t ns = (satk::kMaxSeg - 1) * H, np = (satk::kMaxSeg - 1) * (H + 1);
+        uint64_t *sums = reinterpret_cast<uint64_t *>(static_cast<char *>(workspace) + seg_area_offset(H, W, bpp, sq));
+        uint64_t *sums_q = sq ? sums + ns : nullptr;
+        uint64_t *pre = sums + ns * (sq ? 2 : 1);
+        d.seg_pre = pre;
+        d.seg_pre_q = sq ? pre + np : nullptr;
+        const hipError_t e = satk::launch_seg_prepass(bpp, sq, d, sums, sums_q, static_cast<hipStream_t>(stream));
+        if (e != hipSuccess) return hip_fail(e, who);
+    }
+    hipError_t e = satk::launch_build(v, bpp, sq, &d, 1, nullptr, static_cast<int64_t>(d.nstrips) * d.nseg,
+                                      workspace, words, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, who);
     return ok();
 }
@@ -469,8 +524,9 @@ size_t sat_build_workspace_bytes(int64_t H, int64_t W, sat_dtype pixel_type, int
     if (pixel_type != SAT_U8 && pixel_type != SAT_U16) return 0;
     const int v = choose_build_variant(H, W, 1, bytes_of(pixel_type), with_sq != 0, 16);
     if (v < 0 || v >= satk::build_variant_count()) return 0;
-    return sizeof(satk::BuildCtrl) +
-           8 * static_cast<size_t>(build_state_words_any(H, W, bytes_of(pixel_type), with_sq != 0));
+    const int bpp = bytes_of(pixel_type);
+    if (H <= satk::kSegMaxRows) return seg_area_offset(H, W, bpp, with_sq != 0) + satk::seg_area_bytes(H, with_sq != 0);
+    return sizeof(satk::BuildCtrl) + 8 * static_cast<size_t>(build_state_words_any(H, W, bpp, with_sq != 0));
 }
 
 sat_status sat_build(const void *image, sat_dtype pixel_type, int64_t H, int64_t W, int64_t image_pitch,
@@ -1109,6 +1165,12 @@ int32_t sat_variant_supported(int32_t kind, int32_t index, sat_dtype pixel_type,
 }
 
 sat_status sat_force_variant(int32_t kind, int32_t index) {
+    if (kind == 4) {
+        if (index < 0 || index > satk::kMaxSeg)
+            return fail(SAT_ERR_ARG, "sat_force_variant: column segments must be 0 (built-in) .. %d", satk::kMaxSeg);
+        g_force[4] = index;
+        return ok();
+    }
     if (kind == 3) {
         if (index < 0) return fail(SAT_ERR_ARG, "sat_force_variant: stress seed must be >= 0");
         g_force[3] = index;
@@ -1120,7 +1182,7 @@ sat_status sat_force_variant(int32_t kind, int32_t index) {
         g_force[2] = index;
         return ok();
     }
-    if (kind != 0 && kind != 1) return fail(SAT_ERR_ARG, "sat_force_variant: kind must be 0, 1, 2 or 3");
+    if (kind != 0 && kind != 1) return fail(SAT_ERR_ARG, "sat_force_variant: kind must be 0 .. 4");
     if (index < -1 || index >= sat_variant_count(kind))
         return fail(SAT_ERR_ARG, "sat_force_variant: index out of range");
     g_force[kind] = index;

@@ -1044,10 +1044,34 @@ struct Build2 {
         }
     }
 
-    static __device__ void strip(const BuildDesc &d, int strip_idx, uint64_t *state, unsigned int *fault, Smem &sm) {
+    // Compute wave of a segment that starts mid-row (segment k >= 1 at column x0): the row totals
+    // left of x0 for its rows (lane r: row yw + r) and the table value at (yw - 1, x0 - 1), from
+    // the boundary column the pre-pass wrote.
+    static __device__ __forceinline__ void seg_carries(const BuildDesc &d, int seg, int64_t yw, int lane, int rows_ok,
+                                                       uint64_t &lrow, uint64_t &lrow_q, uint64_t &ucarry,
+                                                       uint64_t &ucarry_q) {
+        const int64_t off = static_cast<int64_t>(seg - 1) * (d.H + 1);
+        const uint64_t *P = d.seg_pre + off;
+        ucarry = P[yw];
+        if (lane < rows_ok) lrow = P[yw + lane + 1] - P[yw + lane];
+        if constexpr (SQ) {
+            const uint64_t *PQ = d.seg_pre_q + off;
+            ucarry_q = PQ[yw];
+            if (lane < rows_ok) lrow_q = PQ[yw + lane + 1] - PQ[yw + lane];
+        }
+    }
+
+    // One work item: strip item / nseg, its column segment item % nseg (blocks b0 .. b0 + nb - 1).
+    static __device__ void strip(const BuildDesc &d, int item, uint64_t *state, unsigned int *fault, Smem &sm) {
         const int lane = threadIdx.x & 63;
         const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
         const bool helper = wave == HELPER;
+        const int nseg = d.nseg;
+        const int strip_idx = nseg > 1 ? item / nseg : item;
+        const int seg = nseg > 1 ? item - strip_idx * nseg : 0;
+        const int b0 = seg * d.seg_blocks;
+        const int nb = d.nblocks - b0 < d.seg_blocks ? d.nblocks - b0 : d.seg_blocks;
+        const int64_t x0 = static_cast<int64_t>(b0) * BW;
         const int th = d.strip_h, rw = d.wave_rows;                       // th <= TH, rw <= RW
         const int64_t ys = static_cast<int64_t>(strip_idx) * th;
         const int nvalid = static_cast<int>(d.H - ys < th ? d.H - ys : th);
@@ -1058,6 +1082,7 @@ struct Build2 {
         uint64_t *Q_w = SQ ? d.Q + yw * d.spitch : nullptr;
         const uint32_t pitch_bytes = static_cast<uint32_t>(d.spitch * 8);
         uint64_t lrow = 0, lrow_q = 0, ucarry = 0, ucarry_q = 0;
+        if (seg > 0 && rows_ok > 0) seg_carries(d, seg, yw, lane, rows_ok, lrow, lrow_q, ucarry, ucarry_q);
 
         if constexpr (!P3) {
             // One loop for all waves, one barrier per block.  Measured on tall 8-bit images (two
@@ -1065,24 +1090,24 @@ struct Build2 {
             // table stores of the block, is 5-7 % faster than separate helper and compute loops.
             if (helper) {
                 __builtin_amdgcn_s_setprio(3);   // see below
-                load_tile(d, sm, 0, ys, 0, nvalid, lane);
+                load_tile(d, sm, 0, ys, x0, nvalid, lane);
                 wait_loads();
-                prepare(d, sm, 0, 0, 0, strip_idx, nvalid, rw, lane, state, fault);
+                prepare(d, sm, 0, 0, x0, strip_idx, nvalid, rw, lane, state, fault);
             }
             lds_barrier();
-            if (helper && d.nblocks > 1) load_tile(d, sm, 1, ys, BW, nvalid, lane);
-            for (int b = 0; b < d.nblocks; ++b) {
-                const int buf = b & 1;
-                const int64_t xb = static_cast<int64_t>(b) * BW;
+            if (helper && nb > 1) load_tile(d, sm, 1, ys, x0 + BW, nvalid, lane);
+            for (int i = 0; i < nb; ++i) {
+                const int buf = i & 1;
+                const int64_t xb = x0 + static_cast<int64_t>(i) * BW;
                 if (!helper) {
                     compute(d, sm, buf, buf, xb, wave, rw, lane, rows_ok, S_w, Q_w, pitch_bytes, lrow, lrow_q,
                             ucarry, ucarry_q);
-                } else if (b + 1 < d.nblocks) {
+                } else if (i + 1 < nb) {
                     wait_loads();
                     prepare(d, sm, buf ^ 1, buf ^ 1, xb + BW, strip_idx, nvalid, rw, lane, state, fault);
                 }
                 lds_barrier();
-                if (helper && b + 2 < d.nblocks) load_tile(d, sm, buf, ys, xb + 2 * BW, nvalid, lane);
+                if (helper && i + 2 < nb) load_tile(d, sm, buf, ys, xb + 2 * BW, nvalid, lane);
             }
             return;
         }
@@ -1094,18 +1119,18 @@ struct Build2 {
             // the leftover issue slots and its short lookback and DMA steps became the critical
             // path.  Its work is a few instructions per block, so it goes first.
             __builtin_amdgcn_s_setprio(3);
-            load_tile(d, sm, 0, ys, 0, nvalid, lane);
-            if (d.nblocks > 1) load_tile(d, sm, 1, ys, BW, nvalid, lane);
+            load_tile(d, sm, 0, ys, x0, nvalid, lane);
+            if (nb > 1) load_tile(d, sm, 1, ys, x0 + BW, nvalid, lane);
             wait_loads();
             lds_barrier();                                                        // Z
             lds_barrier();                                                        // X'
-            lookback_block(d, sm, 0, 0, strip_idx, lane, state, fault);
+            lookback_block(d, sm, 0, x0, strip_idx, lane, state, fault);
             lds_barrier();                                                        // Y'
-            for (int b = 0; b < d.nblocks; ++b) {
-                const int64_t xb = static_cast<int64_t>(b) * BW;
-                if (b + 2 < d.nblocks) load_tile(d, sm, (b + 2) % NTILE, ys, xb + 2 * BW, nvalid, lane);
+            for (int i = 0; i < nb; ++i) {
+                const int64_t xb = x0 + static_cast<int64_t>(i) * BW;
+                if (i + 2 < nb) load_tile(d, sm, (i + 2) % NTILE, ys, xb + 2 * BW, nvalid, lane);
                 lds_barrier();                                                    // X_b
-                if (b + 1 < d.nblocks) lookback_block(d, sm, (b + 1) & 1, xb + BW, strip_idx, lane, state, fault);
+                if (i + 1 < nb) lookback_block(d, sm, (i + 1) & 1, xb + BW, strip_idx, lane, state, fault);
                 wait_loads();
                 lds_barrier();                                                    // Y_b
             }
@@ -1115,11 +1140,11 @@ struct Build2 {
             colsums(sm, 0, 0, wave, row0, rows_ok, lane);
             lds_barrier();                                                        // X'
             lds_barrier();                                                        // Y'
-            for (int b = 0; b < d.nblocks; ++b) {
-                const int64_t xb = static_cast<int64_t>(b) * BW;
-                if (b + 1 < d.nblocks) colsums(sm, (b + 1) % NTILE, (b + 1) & 1, wave, row0, rows_ok, lane);
+            for (int i = 0; i < nb; ++i) {
+                const int64_t xb = x0 + static_cast<int64_t>(i) * BW;
+                if (i + 1 < nb) colsums(sm, (i + 1) % NTILE, (i + 1) & 1, wave, row0, rows_ok, lane);
                 lds_barrier();                                                    // X_b
-                compute(d, sm, b % NTILE, b & 1, xb, wave, rw, lane, rows_ok, S_w, Q_w, pitch_bytes, lrow, lrow_q,
+                compute(d, sm, i % NTILE, i & 1, xb, wave, rw, lane, rows_ok, S_w, Q_w, pitch_bytes, lrow, lrow_q,
                         ucarry, ucarry_q);
                 lds_barrier();                                                    // Y_b
             }
@@ -1615,6 +1640,133 @@ __global__ void clear_kernel(uint64_t *state, long long nwords, BuildCtrl *ctrl,
     }
 }
 
+// Pre-pass of a build split into column segments (BuildDesc::nseg > 1).  A segment that starts at
+// column x0 > 0 needs, for each row of its strip, the row's total left of x0, and the table value
+// just above its strip at column x0 - 1: both come from the table's column x0 - 1, which this
+// pass computes for every segment boundary from one read of the image left of the last segment.
+//
+// segsum_kernel: sums[k * H + y] = sum of row y over segment k's columns (k < nseg - 1), and of the
+// squared pixels; one wave per row, 16-byte loads where the rows allow them.
+template <typename T, bool SQ>
+__global__ __launch_bounds__(256) void segsum_kernel(BuildDesc d, long long segw, uint64_t *sums, uint64_t *sums_q) {
+    const int wave = static_cast<int>(threadIdx.x >> 6), lane = static_cast<int>(threadIdx.x & 63);
+    const int64_t y = static_cast<int64_t>(blockIdx.x) * 4 + wave;
+    const int k = static_cast<int>(blockIdx.y);
+    if (y >= d.H) return;
+    const int64_t xb = static_cast<int64_t>(k) * segw;
+    const int64_t xe = xb + segw < d.W ? xb + segw : d.W;
+    const T *row = static_cast<const T *>(d.img) + y * d.ipitch;
+    uint64_t acc = 0, accq = 0;
+    if (d.img_vb >= 16) {
+        constexpr int E = 16 / static_cast<int>(sizeof(T));      // pixels per 16-byte load
+        for (int64_t x = xb + static_cast<int64_t>(lane) * E; x < xe; x += 64 * E) {
+            if (x + E <= xe) {
+                const u32x4 v = *reinterpret_cast<const u32x4 *>(row + x);
+#pragma unroll
+                for (int w = 0; w < 4; ++w) {
+#pragma unroll
+                    for (int e = 0; e < 4 / static_cast<int>(sizeof(T)); ++e) {
+                        const uint64_t px = (v[w] >> (8 * sizeof(T) * e)) & (sizeof(T) == 1 ? 0xffu : 0xffffu);
+                        acc += px;
+                        if (SQ) accq += px * px;
+                    }
+                }
+            } else {
+                for (int64_t xx = x; xx < xe; ++xx) {
+                    const uint64_t px = row[xx];
+                    acc += px;
+                    if (SQ) accq += px * px;
+                }
+            }
+        }
+    } else {
+        for (int64_t x = xb + lane; x < xe; x += 64) {
+            const uint64_t px = row[x];
+            acc += px;
+            if (SQ) accq += px * px;
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        acc += __shfl_xor(acc, o);
+        if (SQ) accq += __shfl_xor(accq, o);
+    }
+    if (lane == 0) {
+        sums[static_cast<int64_t>(k) * d.H + y] = acc;
+        if (SQ) sums_q[static_cast<int64_t>(k) * d.H + y] = accq;
+    }
+}
+
+// Exclusive scan of one value per thread over a 1024-thread block (Hillis-Steele in LDS), and the
+// block's sum; `buf` is 1024 words of LDS, free again on return.
+__device__ __forceinline__ uint64_t block_exclusive_scan(uint64_t v, uint64_t *buf) {
+    const int t = static_cast<int>(threadIdx.x);
+    buf[t] = v;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        const uint64_t add = t >= o ? buf[t - o] : 0;
+        __syncthreads();
+        buf[t] += add;
+        __syncthreads();
+    }
+    const uint64_t incl = buf[t];
+    __syncthreads();
+    return incl - v;
+}
+__device__ __forceinline__ uint64_t block_sum(uint64_t v, uint64_t *buf) {
+    const uint64_t ex = block_exclusive_scan(v, buf);
+    buf[threadIdx.x] = ex + v;
+    __syncthreads();
+    const uint64_t total = buf[1023];
+    __syncthreads();
+    return total;
+}
+
+// segscan_kernel: for segment k = blockIdx.x + 1, its boundary column x0 - 1 (x0 = k * segw):
+// word 0 the carried column totals left of x0 (zero without a carry), word y + 1 = word y + the
+// total of row y left of x0 (sums of segments 0 .. k - 1).  Each thread takes a run of consecutive
+// rows: run totals, a scan of the runs across the block, then the run's words.
+template <bool SQ>
+__global__ __launch_bounds__(1024) void segscan_kernel(BuildDesc d, long long segw, const uint64_t *sums,
+                                                       const uint64_t *sums_q, uint64_t *pre, uint64_t *pre_q) {
+    __shared__ uint64_t part[1024], part_q[1024];
+    const int k = static_cast<int>(blockIdx.x) + 1;
+    const int t = static_cast<int>(threadIdx.x);
+    const int64_t x0 = static_cast<int64_t>(k) * segw;
+    uint64_t c = 0, cq = 0;
+    if (d.carry) {
+        for (int64_t x = t; x < x0; x += 1024) {
+            c += d.carry[x];
+            if (SQ) cq += d.carry_q[x];
+        }
+    }
+    const uint64_t K = block_sum(c, part), KQ = SQ ? block_sum(cq, part_q) : 0;
+    const int64_t run = (d.H + 1023) / 1024;
+    const int64_t r0 = static_cast<int64_t>(t) * run;
+    const int64_t r1 = r0 + run < d.H ? r0 + run : d.H;
+    uint64_t tot = 0, tot_q = 0;
+    for (int64_t y = r0; y < r1; ++y)
+        for (int j = 0; j < k; ++j) {
+            tot += sums[static_cast<int64_t>(j) * d.H + y];
+            if (SQ) tot_q += sums_q[static_cast<int64_t>(j) * d.H + y];
+        }
+    uint64_t *P = pre + static_cast<int64_t>(k - 1) * (d.H + 1);
+    uint64_t *PQ = SQ ? pre_q + static_cast<int64_t>(k - 1) * (d.H + 1) : nullptr;
+    uint64_t base = K + block_exclusive_scan(tot, part), base_q = SQ ? KQ + block_exclusive_scan(tot_q, part_q) : 0;
+    if (t == 0) {
+        P[0] = K;
+        if (SQ) PQ[0] = KQ;
+    }
+    for (int64_t y = r0; y < r1; ++y) {
+        for (int j = 0; j < k; ++j) {
+            base += sums[static_cast<int64_t>(j) * d.H + y];
+            if (SQ) base_q += sums_q[static_cast<int64_t>(j) * d.H + y];
+        }
+        P[y + 1] = base;
+        if (SQ) PQ[y + 1] = base_q;
+    }
+}
+
 // Reduce-then-scan ablation, phase 1: column totals of every strip (TH rows) of one image.
 template <typename T, bool SQ, int PX, int TH>
 __global__ __launch_bounds__(256) void colsum_kernel(BuildDesc d, uint64_t *state) {
@@ -1964,7 +2116,28 @@ hipError_t launch_pow_typed(const BuildDesc &d, void *workspace, int64_t state_w
     return hipGetLastError();
 }
 
+template <typename T, bool SQ>
+hipError_t launch_seg_typed(const BuildDesc &d, uint64_t *sums, uint64_t *sums_q, hipStream_t stream) {
+    const long long segw = static_cast<long long>(d.seg_blocks) * (d.Wp / d.nblocks);
+    hipLaunchKernelGGL((segsum_kernel<T, SQ>), dim3(static_cast<unsigned>((d.H + 3) / 4), d.nseg - 1), dim3(256), 0,
+                       stream, d, segw, sums, sums_q);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((segscan_kernel<SQ>), dim3(d.nseg - 1), dim3(1024), 0, stream, d, segw, sums, sums_q,
+                       const_cast<uint64_t *>(d.seg_pre), const_cast<uint64_t *>(d.seg_pre_q));
+    return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t launch_seg_prepass(int bpp, bool sq, const BuildDesc &d, uint64_t *sums, uint64_t *sums_q,
+                              hipStream_t stream) {
+    if (d.nseg < 2) return hipSuccess;
+    if (bpp == 1) return sq ? launch_seg_typed<uint8_t, true>(d, sums, sums_q, stream)
+                            : launch_seg_typed<uint8_t, false>(d, sums, sums_q, stream);
+    return sq ? launch_seg_typed<uint16_t, true>(d, sums, sums_q, stream)
+              : launch_seg_typed<uint16_t, false>(d, sums, sums_q, stream);
+}
 
 int power_build_capacity(int bpp, int np) {
     if (bpp == 1) {

@@ -36,6 +36,13 @@ struct BuildDesc {
     uint32_t narrow;      // 1: the lookback keeps 32-bit state words (no squared table and every
                           // column total, carry included, below 2^30); the same for every image
                           // of a launch, and only for variants whose strips run the lookback
+    int32_t nseg;         // column segments per strip (helper-wave builds of one image; else 1):
+                          // work item i is strip i / nseg, segment i % nseg
+    int32_t seg_blocks;   // blocks per segment (nblocks when nseg == 1)
+    const uint64_t *seg_pre, *seg_pre_q;   // nseg > 1: for segment k >= 1, H + 1 words from
+                          // (k - 1) * (H + 1): word y + 1 is the table value at row y, column
+                          // k * seg_blocks * block width - 1, word 0 the carry's part of it (the
+                          // rows above a band); squares likewise
 };
 
 // Workspace layout: 256-byte control header, then the lookback state.
@@ -166,6 +173,21 @@ int mean_std_chain_v(int variant, int64_t stride);
 // plan_mean_std, q > 0), gather_items items in all, device copy dev_gdescs.  ready: n counters
 // inside the cleared state words (the launch zeroes them with the lookback state).
 bool fused_build_variant(int variant);
+// Column segments of the helper-wave build: at most kMaxSeg per strip, each at least
+// kMinSegBlocks blocks wide (built-in choice), for images of at most kSegMaxRows rows.  The pre-pass writes, after the lookback state, per-row totals of
+// the segments and the boundary columns of the table (seg_pre) that let a segment start mid-row.
+constexpr int kMaxSeg = 8;
+constexpr int kMinSegBlocks = 2;
+constexpr int64_t kSegMaxRows = 32768;
+// Bytes of the pre-pass area for an H-row image (squares: twice).
+inline size_t seg_area_bytes(int64_t H, bool sq) {
+    return static_cast<size_t>(kMaxSeg - 1) * static_cast<size_t>(2 * H + 1) * 8 * (sq ? 2 : 1);
+}
+// Enqueue the pre-pass of a segmented build (d.nseg > 1): sums (nseg - 1) * H words (and as many
+// for squares) of scratch, then d.seg_pre / d.seg_pre_q.
+hipError_t launch_seg_prepass(int bpp, bool sq, const BuildDesc &d, uint64_t *sums, uint64_t *sums_q,
+                              hipStream_t stream);
+
 // Host-to-device copy by a kernel reading pinned host memory at its device address src_dev.
 hipError_t launch_upload(const void *src_dev, void *dst, size_t nbytes, hipStream_t stream);
 

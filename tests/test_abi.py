@@ -368,3 +368,20 @@ def test_sat_upload_validation(lib):
     assert lib.sat_upload(IMG + 8, OUT, 64, None) == SAT_ERR_ARG
     assert lib.sat_upload(IMG, OUT + 4, 64, None) == SAT_ERR_ARG
     assert "aligned" in lib.sat_last_error().decode()
+
+
+def test_force_segments_validation(lib):
+    assert lib.sat_force_variant(4, 9) == SAT_ERR_ARG
+    assert lib.sat_force_variant(4, -1) == SAT_ERR_ARG
+    assert lib.sat_force_variant(4, 3) == SAT_OK
+    assert lib.sat_force_variant(4, 0) == SAT_OK
+
+
+def test_workspace_reserves_the_segment_area(lib):
+    """Images of at most 32768 rows get room for the column-segment pre-pass after the lookback
+    state; taller ones do not."""
+    small = lib.sat_build_workspace_bytes(8192, 8192, SAT_U16, 1)
+    assert small >= 256 + 7 * (2 * 8192 + 1) * 8 * 2
+    tall_a = lib.sat_build_workspace_bytes(32769, 1000, SAT_U8, 0)
+    tall_b = lib.sat_build_workspace_bytes(32768, 1000, SAT_U8, 0)
+    assert tall_b - tall_a > 7 * (2 * 32768 + 1) * 8 - 64 * 1024
