@@ -334,3 +334,19 @@ def test_cyclic_gc_is_paused_during_the_loop_and_restored():
     Server(Watch(clock), budget_bytes=200e9, slots=2).run(stream(duration=0.2), clock=clock, idle=clock.idle)
     assert seen and not any(seen)
     assert gc.isenabled()
+
+
+def test_arena_cuts_long_lived_blocks_from_the_top():
+    """Tables (top=True) pack towards the region's end and transients towards its start, so the
+    free space between them stays in one piece."""
+    a = Arena(64 * 256)
+    t1 = a.alloc(8 * 256, top=True)
+    x = a.alloc(4 * 256)
+    t2 = a.alloc(8 * 256, top=True)
+    assert t1 == 56 * 256 and t2 == 48 * 256 and x == 0
+    a.release(x)
+    assert a.largest_free == 48 * 256                  # one run below the two tables
+    a.release(t1)
+    assert a.starts == [0, 56 * 256] and a.lens == [48 * 256, 8 * 256]
+    a.release(t2)
+    assert a.starts == [0] and a.lens == [64 * 256]
