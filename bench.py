@@ -415,8 +415,8 @@ def banded_section(torch, dev, H, W, band_rows):
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         res[name] = {"ms": round(dt * 1e3, 2), "gpix_s": round(H * W / dt / 1e9, 2), "bands": len(job.plan),
-                     "device_GB": round((sum(t.storage().nbytes() for t in (job.up.dimg if job.up else []))
-                                         + sum(t.storage().nbytes() for t in job.tables)) / 1e9, 2)}
+                     "device_GB": round((sum(t.untyped_storage().nbytes() for t in (job.up.dimg if job.up else []))
+                                         + sum(t.untyped_storage().nbytes() for t in job.tables)) / 1e9, 2)}
         del job, src
         torch.cuda.empty_cache()
     # the whole table in HBM, built band by band as the image streams in (no overlap rows: each
