@@ -376,22 +376,32 @@ __global__ __launch_bounds__(kLdsBS) void chain_lds_kernel(ChainArgs a, int32_t 
         inside[k] = kk < span && col >= 0 && col < W;
         colk[k] = static_cast<int32_t>(col < 0 ? 0 : (col > W - 1 ? W - 1 : col));
     }
-    auto gload = [&](int64_t j, uint64_t (&pre)[NL]) {
+    // The ring keeps table values in the output type (sums mod 2^32 for 32-bit outputs need only
+    // the low word of each entry), so 32-bit outputs load only low words: the dead high halves of
+    // 64-bit loads were reused as registers for the LDS reads, which then had to wait for the
+    // table row loaded ahead, and the prefetch bought nothing.
+    auto gload = [&](int64_t j, OutT (&pre)[NL]) {
         const int64_t jj = j <= jlast ? j : jlast;
         const int64_t t = it.r + jj * a.q - 1;
         const uint64_t *p = a.S + (t > 0 ? t : 0) * a.spitch;
+        if constexpr (sizeof(OutT) == 4) {
+            const uint32_t *p32 = reinterpret_cast<const uint32_t *>(p);
 #pragma unroll
-        for (int k = 0; k < NL; ++k) pre[k] = p[colk[k]];
+            for (int k = 0; k < NL; ++k) pre[k] = p32[2 * static_cast<int64_t>(colk[k])];
+        } else {
+#pragma unroll
+            for (int k = 0; k < NL; ++k) pre[k] = p[colk[k]];
+        }
     };
     int slot = static_cast<int>(it.j0 % nslot);
-    auto step = [&](int64_t j, const uint64_t (&pre)[NL]) {
+    auto step = [&](int64_t j, const OutT (&pre)[NL]) {
         __syncthreads();                                   // the slot reused now was last read a step ago
         const bool rowok = it.r + j * a.q > 0;             // row -1 is all zero
         OutT *dst = ring + slot * span;
 #pragma unroll
         for (int k = 0; k < NL; ++k) {
             const int kk = k * kLdsBS + tid;
-            if (kk < span) dst[kk] = (rowok && inside[k]) ? static_cast<OutT>(pre[k]) : OutT(0);
+            if (kk < span) dst[kk] = (rowok && inside[k]) ? pre[k] : OutT(0);
         }
         __syncthreads();
         const OutT *cur = dst;
@@ -424,7 +434,7 @@ __global__ __launch_bounds__(kLdsBS) void chain_lds_kernel(ChainArgs a, int32_t 
         }
         slot = slot + 1 == nslot ? 0 : slot + 1;
     };
-    uint64_t pre0[NL], pre1[NL];
+    OutT pre0[NL], pre1[NL];
     gload(it.j0, pre0);
     gload(it.j0 + 1, pre1);
 #pragma unroll 1
