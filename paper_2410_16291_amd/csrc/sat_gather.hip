@@ -57,30 +57,43 @@ __device__ __forceinline__ ItemMap map_item(int64_t item, int64_t oh, int64_t ch
 // top-right-outside, top-left-outside.  Loads are issued for every l (indices clamped into the
 // row) so that all of a thread's loads are in flight before the first use; terms that fall
 // outside the table (row y0-1 < 0 or column x0-1 < 0) are masked to zero afterwards.
+// The four corner entries of one window, as E: 32-bit outputs (sums mod 2^32) need only the low
+// word of each table entry, so they load half the bytes.
+template <typename E>
 struct Corners {
-    uint64_t b1, b0, t1, t0;
+    E b1, b0, t1, t0;
 };
 
-__device__ __forceinline__ Corners load_corners(const uint64_t *__restrict__ top, const uint64_t *__restrict__ bot,
-                                                int64_t l, const GatherDesc &d) {
+template <typename E>
+__device__ __forceinline__ Corners<E> load_corners(const uint64_t *__restrict__ top, const uint64_t *__restrict__ bot,
+                                                   int64_t l, const GatherDesc &d) {
     const int64_t lc = l < d.ow ? l : d.ow - 1;
     const int64_t x0 = lc * d.stride;
     const int64_t x1 = x0 + d.win_w - 1;
     const int64_t xm = x0 > 0 ? x0 - 1 : 0;
-    Corners c;
-    c.b1 = bot[x1];
-    c.b0 = bot[xm];
-    c.t1 = top[x1];
-    c.t0 = top[xm];
+    Corners<E> c;
+    if constexpr (sizeof(E) == 4) {
+        const uint32_t *b32 = reinterpret_cast<const uint32_t *>(bot), *t32 = reinterpret_cast<const uint32_t *>(top);
+        c.b1 = b32[2 * x1];
+        c.b0 = b32[2 * xm];
+        c.t1 = t32[2 * x1];
+        c.t0 = t32[2 * xm];
+    } else {
+        c.b1 = bot[x1];
+        c.b0 = bot[xm];
+        c.t1 = top[x1];
+        c.t0 = top[xm];
+    }
     return c;
 }
 
-__device__ __forceinline__ uint64_t corner_sum(const Corners &c, int64_t l, const GatherDesc &d, bool has_top) {
+template <typename E>
+__device__ __forceinline__ E corner_sum(const Corners<E> &c, int64_t l, const GatherDesc &d, bool has_top) {
     const bool has_left = l * d.stride > 0;
-    const uint64_t b0 = has_left ? c.b0 : 0;
-    const uint64_t t1 = has_top ? c.t1 : 0;
-    const uint64_t t0 = (has_top && has_left) ? c.t0 : 0;
-    return c.b1 - t1 - b0 + t0;
+    const E b0 = has_left ? c.b0 : E(0);
+    const E t1 = has_top ? c.t1 : E(0);
+    const E t0 = (has_top && has_left) ? c.t0 : E(0);
+    return static_cast<E>(c.b1 - t1 - b0 + t0);
 }
 
 template <typename OutT, int V>
@@ -93,9 +106,9 @@ __global__ __launch_bounds__(256) void window_sum_kernel(GatherDesc d, int64_t b
     const uint64_t *top = d.S + (has_top ? y0 - 1 : 0) * d.spitch;
     OutT *out = static_cast<OutT *>(d.out) + m.k * d.opitch;
     const int64_t l0 = m.c * (256 * V) + threadIdx.x;
-    Corners c[V];
+    Corners<OutT> c[V];
 #pragma unroll
-    for (int v = 0; v < V; ++v) c[v] = load_corners(top, bot, l0 + v * 256, d);
+    for (int v = 0; v < V; ++v) c[v] = load_corners<OutT>(top, bot, l0 + v * 256, d);
 #pragma unroll
     for (int v = 0; v < V; ++v) {
         const int64_t l = l0 + v * 256;
@@ -130,9 +143,9 @@ __global__ __launch_bounds__(256) void window_sum_multi_kernel(MultiArgs a, int6
         if (m.k >= d.oh) continue;
         const uint64_t *bot = S + (y0 + d.win_h - 1) * spitch;
         OutT *out = static_cast<OutT *>(d.out) + m.k * d.opitch;
-        Corners c[V];
+        Corners<OutT> c[V];
 #pragma unroll
-        for (int v = 0; v < V; ++v) c[v] = load_corners(top, bot, l0 + v * 256, d);
+        for (int v = 0; v < V; ++v) c[v] = load_corners<OutT>(top, bot, l0 + v * 256, d);
 #pragma unroll
         for (int v = 0; v < V; ++v) {
             const int64_t l = l0 + v * 256;
@@ -153,11 +166,11 @@ __device__ __forceinline__ void mean_std_row(const GatherDesc &d, int64_t k, int
     const uint64_t n = static_cast<uint64_t>(d.win_h) * static_cast<uint64_t>(d.win_w);
     const double dn = static_cast<double>(n);
     const int64_t l0 = c * (256 * V) + threadIdx.x;
-    Corners cs[V], cq[V];
+    Corners<uint64_t> cs[V], cq[V];
 #pragma unroll
     for (int v = 0; v < V; ++v) {
-        cs[v] = load_corners(topS, botS, l0 + v * 256, d);
-        cq[v] = load_corners(topQ, botQ, l0 + v * 256, d);
+        cs[v] = load_corners<uint64_t>(topS, botS, l0 + v * 256, d);
+        cq[v] = load_corners<uint64_t>(topQ, botQ, l0 + v * 256, d);
     }
 #pragma unroll
     for (int v = 0; v < V; ++v) {
@@ -222,10 +235,12 @@ struct ChainArgs {
     ChainWin win[kChainMaxWin];
 };
 
-template <int V, int N>
+// Table entries of one chain row, in the output type: sums mod 2^32 need only the low word of
+// each entry, so 32-bit outputs load half the bytes.
+template <typename E, int V, int N>
 struct ChainRow {
-    uint64_t left[V];
-    uint64_t right[N][V];
+    E left[V];
+    E right[N][V];
 };
 
 template <typename OutT, int V, int N>
@@ -260,18 +275,28 @@ __global__ __launch_bounds__(256) void chain_sum_kernel(ChainArgs a) {
             xr[i][v] = li * s + a.win[i].w - 1;
         }
     }
-    auto load = [&](int64_t j, ChainRow<V, N> &row) {
+    auto load = [&](int64_t j, ChainRow<OutT, V, N> &row) {
         const int64_t t = (it.r + j * a.q) * a.stride - 1;
         const uint64_t *p = a.S + (t > 0 ? t : 0) * a.spitch;
+        if constexpr (sizeof(OutT) == 4) {
+            const uint32_t *p32 = reinterpret_cast<const uint32_t *>(p);     // low words
 #pragma unroll
-        for (int v = 0; v < V; ++v) row.left[v] = p[xl[v]];
+            for (int v = 0; v < V; ++v) row.left[v] = p32[2 * static_cast<int64_t>(xl[v])];
 #pragma unroll
-        for (int i = 0; i < N; ++i)
+            for (int i = 0; i < N; ++i)
 #pragma unroll
-            for (int v = 0; v < V; ++v) row.right[i][v] = p[xr[i][v]];
+                for (int v = 0; v < V; ++v) row.right[i][v] = p32[2 * static_cast<int64_t>(xr[i][v])];
+        } else {
+#pragma unroll
+            for (int v = 0; v < V; ++v) row.left[v] = p[xl[v]];
+#pragma unroll
+            for (int i = 0; i < N; ++i)
+#pragma unroll
+                for (int v = 0; v < V; ++v) row.right[i][v] = p[xr[i][v]];
+        }
     };
 
-    ChainRow<V, N> cur, nxt;
+    ChainRow<OutT, V, N> cur, nxt;
     OutT prev[V];
     int slot[N];
 #pragma unroll
@@ -287,7 +312,7 @@ __global__ __launch_bounds__(256) void chain_sum_kernel(ChainArgs a) {
             OutT D[V];
 #pragma unroll
             for (int v = 0; v < V; ++v) {
-                const uint64_t lv = has_left[v] ? cur.left[v] : 0;
+                const OutT lv = has_left[v] ? cur.left[v] : OutT(0);
                 D[v] = row_ok ? static_cast<OutT>(cur.right[i][v] - lv) : OutT(0);
             }
             const int64_t p = j - cw.L;
@@ -897,13 +922,13 @@ __global__ __launch_bounds__(256) void moments_kernel(MomentDesc d, int64_t band
     const uint64_t n = static_cast<uint64_t>(d.win_h) * static_cast<uint64_t>(d.win_w);
     const double dn = static_cast<double>(n);
     const int64_t l0 = m.c * (256 * V) + threadIdx.x;
-    Corners c[K][V];
+    Corners<uint64_t> c[K][V];
 #pragma unroll
     for (int p = 0; p < K; ++p) {
         const uint64_t *bot = d.T[p] + y1 * d.spitch;
         const uint64_t *top = d.T[p] + (has_top ? y0 - 1 : 0) * d.spitch;
 #pragma unroll
-        for (int v = 0; v < V; ++v) c[p][v] = load_corners(top, bot, l0 + v * 256, g);
+        for (int v = 0; v < V; ++v) c[p][v] = load_corners<uint64_t>(top, bot, l0 + v * 256, g);
     }
 #pragma unroll
     for (int v = 0; v < V; ++v) {
