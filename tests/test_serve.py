@@ -320,20 +320,23 @@ def test_a_table_that_splits_the_free_space_is_rebuilt_for_its_query():
     assert rep.n == 1 and rep.misses == 1 and rep.evictions == 1
 
 
-def test_cyclic_gc_is_paused_during_the_loop_and_restored():
+def test_cyclic_gc_is_paused_and_switch_interval_shortened_during_the_loop():
     import gc
+    import sys
     seen = []
 
     class Watch(FakeExecutor):
         def is_done(self, h):
-            seen.append(gc.isenabled())
+            seen.append((gc.isenabled(), sys.getswitchinterval()))
             return super().is_done(h)
 
     clock = Clock()
     assert gc.isenabled()
+    before = sys.getswitchinterval()
     Server(Watch(clock), budget_bytes=200e9, slots=2).run(stream(duration=0.2), clock=clock, idle=clock.idle)
-    assert seen and not any(seen)
-    assert gc.isenabled()
+    assert seen and not any(on for on, _ in seen)
+    assert all(abs(iv - Server.SWITCH_INTERVAL) < 1e-9 for _, iv in seen)
+    assert gc.isenabled() and sys.getswitchinterval() == before
 
 
 def test_arena_cuts_long_lived_blocks_from_the_top():
