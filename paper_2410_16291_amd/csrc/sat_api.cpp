@@ -193,14 +193,16 @@ BuildPlan helper_plan(int64_t H, int64_t W, int bpp, bool sq) {
         v = (n48 > ncu && n64 <= ncu) ? kVarHelperPx4 : kVarHelperPx8;
     }
     // The three-stage helper pipeline (column sums on the compute waves, the helper's lookback
-    // overlapping their block) shortens each block where the helper's path sets the pace, at the
-    // cost of a third tile buffer (one workgroup per CU for 8-bit 512-column tiles).  Measured
-    // (ms, two-stage -> three-stage): 8192^2 u16 with squares 0.346 -> 0.311, 12000^2 0.712 ->
-    // 0.682, 16000^2 u8 0.594 -> 0.552, 2000 x 16000 u8 0.255 -> 0.227, 20000^2 u8 0.969 -> 0.928;
-    // rows of 85000 pixels (166 blocks per strip) kept the two-stage pipeline: 8750 rows 1.709 vs
-    // 1.740, 70000 rows 11.27 vs 11.77.
+    // overlapping their block and the DMA of the tile after next) shortens each block where the
+    // helper's path sets the pace, at the cost of a third tile buffer (one workgroup per CU for
+    // 8-bit 512-column tiles).  Measured (ms, two-stage -> three-stage, one GPU, bit-exact):
+    // 8192^2 u16 with squares 0.346 -> 0.311, 12000^2 0.712 -> 0.682, 16000^2 u8 0.594 -> 0.552,
+    // 2000 x 16000 u8 0.255 -> 0.227, 20000^2 u8 0.969 -> 0.928.  Rows of 85000 pixels gained
+    // once the helper's barrier after the DMA stopped waiting for it: 8750 rows 1.52 -> 1.27,
+    // 17500 rows 3.13 -> 2.68, 4375 rows 1.26 -> 1.07, 70000 rows 10.99 -> 10.95; 8192 x 40000
+    // u16 with squares 1.52 -> 1.22.
     const int v3 = v == kVarHelperPx4 ? kVarHelper3Px4 : kVarHelper3Px8;
-    if (W <= 32768 && satk::build_variant_capacity(v3, bpp, sq) > 0) v = v3;
+    if (satk::build_variant_capacity(v3, bpp, sq) > 0) v = v3;
     return {v, helper_strip_h(v, H, bpp, sq)};
 }
 

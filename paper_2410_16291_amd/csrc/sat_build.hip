@@ -228,6 +228,17 @@ __device__ __forceinline__ void lds_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+// Barrier for the helper wave just after it issued a tile's LDS DMA that no wave reads before a
+// later barrier.  The release fence of lds_barrier would make the helper wait for that DMA here
+// (LDS DMA writes LDS and is counted on the vector memory counter), so the tile's load latency
+// would be paid before the barrier instead of overlapping the lookback that follows.  Only the
+// helper's own LDS accesses are waited for; the DMA is waited for at the next barrier.
+__device__ __forceinline__ void dma_barrier() {
+    __builtin_amdgcn_s_waitcnt(0xc07f);          // lgkmcnt(0); vmcnt and expcnt at their maximum
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // ------------------------------------------------------------------ rows of one table block
 //
 // A wave's rows of one block of one table: for every row, the lane's pixel pair of each 128-column
@@ -1129,7 +1140,7 @@ struct Build2 {
             for (int i = 0; i < nb; ++i) {
                 const int64_t xb = x0 + static_cast<int64_t>(i) * BW;
                 if (i + 2 < nb) load_tile(d, sm, (i + 2) % NTILE, ys, xb + 2 * BW, nvalid, lane);
-                lds_barrier();                                                    // X_b
+                dma_barrier();                                                    // X_b: tile b+2 in flight
                 if (i + 1 < nb) lookback_block(d, sm, (i + 1) & 1, xb + BW, strip_idx, lane, state, fault);
                 wait_loads();
                 lds_barrier();                                                    // Y_b

@@ -4,10 +4,10 @@ oracle's tables (needs an MI355X with 256 compute units, the device the plan is 
 The plan picks the helper-wave variant and its strip height from the image shape: eight pixels
 per lane at 48-row strips (24-row strips for very few strips, balanced heights for tall images),
 four pixels per lane at one 64-row strip per CU, and four pixels per lane at 32, 48 or 64 rows (or
-balanced heights) for narrow images and 16-bit images with squares; images up to 32768 pixels
-wide take the three-stage helper pipeline, wider ones the two-stage one.  Each case below lands in
-one branch; widths that are not a multiple of the block width end in a ragged block.  Tables must
-be bit-exact.
+balanced heights) for narrow images and 16-bit images with squares.  Every image takes the
+three-stage helper pipeline where its three tile buffers fit the LDS; 16-bit images at eight pixels
+per lane keep the two-stage one.  Each case below lands in one branch; widths that are not a
+multiple of the block width end in a ragged block.  Tables must be bit-exact.
 """
 import numpy as np
 import pytest
@@ -30,13 +30,13 @@ CASES = [
     (7000, 3001, np.uint8, False, "narrow: 4 px/lane, 32-row strips, ragged"),
     (12000, 1000, np.uint16, True, "16-bit with squares: 4 px/lane, 48-row strips"),
     (20000, 1000, np.uint16, True, "16-bit with squares: balanced heights"),
-    (6000, 5000, np.uint16, False, "16-bit without squares: 8 px/lane, 48-row strips"),
+    (6000, 5000, np.uint16, False, "16-bit without squares: two-stage helper, 8 px/lane, 48-row strips"),
     (1, 4096, np.uint8, True, "one row: 8 px/lane, one strip"),
     (5, 8200, np.uint16, True, "five rows, 16-bit with squares, ragged"),
     (1, 1, np.uint8, False, "one pixel: narrow, 4 px/lane"),
     (47, 4096, np.uint16, False, "one strip just short of 48 rows"),
-    (300, 40000, np.uint8, False, "wider than 32768: two-stage helper, 8 px/lane"),
-    (100, 33000, np.uint16, True, "wider than 32768, 16-bit with squares: two-stage helper, 4 px/lane, ragged"),
+    (300, 40000, np.uint8, False, "wider than 32768: three-stage helper, 8 px/lane"),
+    (100, 33000, np.uint16, True, "wider than 32768, 16-bit with squares: three-stage helper, 4 px/lane, ragged"),
 ]
 
 
