@@ -197,12 +197,15 @@ BuildPlan helper_plan(int64_t H, int64_t W, int bpp, bool sq) {
     // helper's path sets the pace, at the cost of a third tile buffer (one workgroup per CU for
     // 8-bit 512-column tiles).  Measured (ms, two-stage -> three-stage, one GPU, bit-exact):
     // 8192^2 u16 with squares 0.346 -> 0.311, 12000^2 0.712 -> 0.682, 16000^2 u8 0.594 -> 0.552,
-    // 2000 x 16000 u8 0.255 -> 0.227, 20000^2 u8 0.969 -> 0.928.  Rows of 85000 pixels gained
-    // once the helper's barrier after the DMA stopped waiting for it: 8750 rows 1.52 -> 1.27,
-    // 17500 rows 3.13 -> 2.68, 4375 rows 1.26 -> 1.07, 70000 rows 10.99 -> 10.95; 8192 x 40000
-    // u16 with squares 1.52 -> 1.22.
+    // 2000 x 16000 u8 0.255 -> 0.227, 20000^2 u8 0.969 -> 0.928.  Wider rows gained once the
+    // helper's barrier after the DMA stopped waiting for it: 85000-pixel rows, 8750 rows 1.52 ->
+    // 1.27, 17500 rows 3.13 -> 2.68, 4375 rows 1.26 -> 1.07; 8192 x 40000 u16 with squares 1.52 ->
+    // 1.22.  Tall wide images, where the two-stage pipeline keeps two workgroups on every CU over
+    // several rounds, stay with it: 70000 x 85000 tied alone (10.99 vs 10.95) and was 2-8 % slower
+    // in three stages right after a gather.
     const int v3 = v == kVarHelperPx4 ? kVarHelper3Px4 : kVarHelper3Px8;
-    if (satk::build_variant_capacity(v3, bpp, sq) > 0) v = v3;
+    const bool tall_wide = W > 32768 && (H + 47) / 48 > 2 * ncu;
+    if (!tall_wide && satk::build_variant_capacity(v3, bpp, sq) > 0) v = v3;
     return {v, helper_strip_h(v, H, bpp, sq)};
 }
 

@@ -4,10 +4,11 @@ oracle's tables (needs an MI355X with 256 compute units, the device the plan is 
 The plan picks the helper-wave variant and its strip height from the image shape: eight pixels
 per lane at 48-row strips (24-row strips for very few strips, balanced heights for tall images),
 four pixels per lane at one 64-row strip per CU, and four pixels per lane at 32, 48 or 64 rows (or
-balanced heights) for narrow images and 16-bit images with squares.  Every image takes the
-three-stage helper pipeline where its three tile buffers fit the LDS; 16-bit images at eight pixels
-per lane keep the two-stage one.  Each case below lands in one branch; widths that are not a
-multiple of the block width end in a ragged block.  Tables must be bit-exact.
+balanced heights) for narrow images and 16-bit images with squares.  Images take the three-stage
+helper pipeline where its three tile buffers fit the LDS, except images wider than 32768 pixels
+with more than two rounds of 48-row strips; those, and 16-bit images at eight pixels per lane, take
+the two-stage one.  Each case below lands in one branch; widths that are not a multiple of the block
+width end in a ragged block.  Tables must be bit-exact.
 """
 import numpy as np
 import pytest
@@ -37,6 +38,7 @@ CASES = [
     (47, 4096, np.uint16, False, "one strip just short of 48 rows"),
     (300, 40000, np.uint8, False, "wider than 32768: three-stage helper, 8 px/lane"),
     (100, 33000, np.uint16, True, "wider than 32768, 16-bit with squares: three-stage helper, 4 px/lane, ragged"),
+    (24700, 33000, np.uint8, False, "wider than 32768, more than two rounds of strips: two-stage helper, balanced heights"),
 ]
 
 
