@@ -172,10 +172,22 @@ struct BuildPlan {
     int strip_h;
 };
 
+// Images of at most this many rows split helper-wave strips into column segments (choose_segments).
+constexpr int64_t kSegAutoRows = 4096;
+
 int helper_strip_h(int v, int64_t H, int bpp, bool sq) {
     const int64_t ncu = device_cus();
     const int64_t cap = satk::build_variant_capacity(v, bpp, sq);
     const int th = satk::build_variant(v).th();
+    if (v == kVarHelper3Px8 && H > kSegAutoRows && (H + th - 1) / th <= ncu) {
+        // One round: the shortest strips (at least half a tile) that still fit on the CUs.
+        // Measured (ms per build): 4375 x 85000 u8 1.06-1.10 at 48 rows -> 0.93-0.98 at 24; 8750
+        // x 85000 u8 1.465-1.475 at 48 rows, 1.456-1.463 at 36-44, 1.73-1.88 at 24-32 (two
+        // rounds).  Shorter images split their strips into column segments instead (below), and
+        // there 24-row strips lost: 3200 x 4100 u8 0.091 -> 0.097.
+        const int64_t h = (H + ncu - 1) / ncu;
+        return static_cast<int>(h < th / 2 ? th / 2 : h);
+    }
     if (v == kVarHelperPx8 || v == kVarHelper3Px8) {
         if (4 * ((H + th - 1) / th) <= ncu) return th / 2;
         return balanced_strip_h(H, th, cap);
@@ -269,7 +281,6 @@ sat_status check_build_variant(int v, int bpp, bool sq, const char *who) {
 // 16-bit 8192^2 with squares 0.314 -> 0.309-0.311, 8750 x 85000 1.62 -> 1.59-1.78, 16000^2
 // 0.49 -> 0.59.  A forced count (sat_force_variant kind 4) applies up to kSegMaxRows rows, for
 // which the workspace reserves the pre-pass area.
-constexpr int64_t kSegAutoRows = 4096;
 int choose_segments(int v, const satk::BuildDesc &d, int bpp, bool sq) {
     const satk::BuildVariant &var = satk::build_variant(v);
     if ((var.mode != satk::MODE_HELPER && var.mode != satk::MODE_HELPER3) || !var.lookback() ||

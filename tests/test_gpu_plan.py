@@ -2,9 +2,11 @@
 oracle's tables (needs an MI355X with 256 compute units, the device the plan is measured on).
 
 The plan picks the helper-wave variant and its strip height from the image shape: eight pixels
-per lane at 48-row strips (24-row strips for very few strips, balanced heights for tall images),
-four pixels per lane at one 64-row strip per CU, and four pixels per lane at 32, 48 or 64 rows (or
-balanced heights) for narrow images and 16-bit images with squares.  Images take the three-stage
+per lane at 48-row strips split into column segments for images of at most 4096 rows, in one
+round of the shortest strips that fit on the CUs (24 to 48 rows) above that, or in heights
+balanced over rounds for taller images; four pixels per lane at one 64-row strip per CU; and four
+pixels per lane at 32, 48 or 64 rows (or balanced heights) for narrow images and 16-bit images
+with squares.  Images take the three-stage
 helper pipeline where its three tile buffers fit the LDS, except images wider than 32768 pixels
 with more than two rounds of 48-row strips; those, and 16-bit images at eight pixels per lane, take
 the two-stage one.  Each case below lands in one branch; widths that are not a multiple of the block
@@ -23,10 +25,12 @@ pytestmark = pytest.mark.gpu
 CASES = [
     # (H, W, pixel dtype, squares, branch)
     (2000, 4096, np.uint8, False, "8 px/lane, 24-row strips (few strips)"),
-    (3200, 4100, np.uint8, True, "8 px/lane, 48-row strips, ragged last block, with squares"),
+    (3200, 4100, np.uint8, True, "8 px/lane, 48-row strips split into column segments, ragged last block, with squares"),
+    (5000, 4200, np.uint8, False, "8 px/lane, one round of the shortest strips: 24 rows, ragged"),
+    (9000, 4096, np.uint8, False, "8 px/lane, one round of the shortest strips: 36 rows"),
     (16000, 4096, np.uint8, False, "4 px/lane, one 64-row strip per CU"),
-    (20000, 4352, np.uint8, False, "8 px/lane, 48-row strips, more strips than CUs"),
-    (30000, 4096, np.uint8, False, "8 px/lane, heights balanced over two rounds"),
+    (20000, 4352, np.uint8, False, "8 px/lane, more 48-row strips than CUs: heights balanced over two rounds"),
+    (30000, 4096, np.uint8, False, "8 px/lane, heights balanced over three rounds"),
     (9000, 2000, np.uint8, False, "narrow: 4 px/lane, 48-row strips"),
     (7000, 3001, np.uint8, False, "narrow: 4 px/lane, 32-row strips, ragged"),
     (12000, 1000, np.uint16, True, "16-bit with squares: 4 px/lane, 48-row strips"),
@@ -36,7 +40,7 @@ CASES = [
     (5, 8200, np.uint16, True, "five rows, 16-bit with squares, ragged"),
     (1, 1, np.uint8, False, "one pixel: narrow, 4 px/lane"),
     (47, 4096, np.uint16, False, "one strip just short of 48 rows"),
-    (300, 40000, np.uint8, False, "wider than 32768: three-stage helper, 8 px/lane"),
+    (300, 40000, np.uint8, False, "wider than 32768: three-stage helper, 8 px/lane, 24-row strips"),
     (100, 33000, np.uint16, True, "wider than 32768, 16-bit with squares: three-stage helper, 4 px/lane, ragged"),
     (24700, 33000, np.uint8, False, "wider than 32768, more than two rounds of strips: two-stage helper, balanced heights"),
 ]
