@@ -836,7 +836,7 @@ struct TileStage {
     // straight into LDS.  The resource ends after the last valid row, so rows past the image read
     // as zero without a branch; the lane part of the address is one VGPR, the chunk part a scalar
     // offset.  Otherwise element by element, zeros outside the image.
-    template <int VB>
+    template <int VB, bool FULL = false>
     static __device__ __forceinline__ void dma(const BuildDesc &d, uint32_t *tile, int64_t ys, int64_t xb, int nvalid,
                                                int lane) {
         constexpr int CB = 64 * VB;                         // bytes per wave load
@@ -848,9 +848,7 @@ struct TileStage {
             __builtin_amdgcn_make_buffer_rsrc(const_cast<unsigned char *>(base), 0, static_cast<int>(recs), kRsrcWord3);
         const uint32_t lb = static_cast<uint32_t>(lane) * VB;
         const uint32_t voff = (lb / ROWB) * pitchb + lb % ROWB;
-        const int nch = (nvalid * ROWB + CB - 1) / CB;      // chunks holding valid rows
-#pragma unroll 4
-        for (int c = 0; c < nch; ++c) {
+        auto chunk = [&](int c) {
             const uint32_t cb = static_cast<uint32_t>(c) * CB;
             const uint32_t so = (cb / ROWB) * pitchb + cb % ROWB;
             auto *dst = (__attribute__((address_space(3))) void *)(tile + c * (CB / 4));
@@ -858,14 +856,30 @@ struct TileStage {
                 __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, dst, 16, voff, static_cast<int>(so), 0, 0);
             else
                 __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, dst, 4, voff, static_cast<int>(so), 0, 0);
+        };
+        if constexpr (FULL) {
+            // Every chunk of the tile, so that each tile load is at least kFullLoads vector memory
+            // instructions and a wait may leave the next tile's loads in flight (kFullLoads).
+            // Rows past nvalid lie past the resource and read as zero.
+#pragma unroll
+            for (int c = 0; c < TILEB / CB; ++c) chunk(c);
+        } else {
+            const int nch = (nvalid * ROWB + CB - 1) / CB;      // chunks holding valid rows
+#pragma unroll 4
+            for (int c = 0; c < nch; ++c) chunk(c);
         }
     }
 
+    // Vector memory instructions a FULL tile load issues at least (16-byte chunks; 4-byte chunks
+    // issue four times as many); the element path instead waits for its own loads.
+    static constexpr int kFullLoads = TILEB / 1024 < 63 ? TILEB / 1024 : 63;
+
+    template <bool FULL = false>
     static __device__ void load(const BuildDesc &d, uint32_t *tile_buf, int64_t ys, int64_t xb, int nvalid,
                                 int lane) {
         if (d.img_vb >= 4 && xb + BW <= d.W) {
-            if (d.img_vb >= 16) dma<16>(d, tile_buf, ys, xb, nvalid, lane);
-            else dma<4>(d, tile_buf, ys, xb, nvalid, lane);
+            if (d.img_vb >= 16) dma<16, FULL>(d, tile_buf, ys, xb, nvalid, lane);
+            else dma<4, FULL>(d, tile_buf, ys, xb, nvalid, lane);
         } else {
             const T *img = static_cast<const T *>(d.img);
             T *tile = reinterpret_cast<T *>(tile_buf);
@@ -1221,9 +1235,15 @@ struct BuildPow {
     static constexpr int ROWB = BW * static_cast<int>(sizeof(T));
     static constexpr int TILEB = TH * ROWB;
     static_assert(NP >= 1 && NP <= 4 && NP * PX <= 32, "power count and lane pixels fit the done mask");
+    // Tile buffers: two, or three where the state with two already takes more than half of the
+    // 160 KiB of LDS (one workgroup per CU) and a third still fits.  With three the DMA of block
+    // b+3 is issued as block b's buffer frees, so a tile has a whole block step to land.
+    static constexpr size_t kLds2 = 2 * static_cast<size_t>(TILEB) + 2 * NP * NW * BW * 8 + 2 * NP * BW * 8 + 8;
+    static constexpr int NTILE = kLds2 > 80 * 1024 && kLds2 + TILEB <= 156 * 1024 ? 3 : 2;
+    using Stage = TileStage<T, PX, TH>;
 
     struct Smem {
-        uint32_t tile[2][TILEB / 4];                      // image tiles of blocks b and b+1
+        uint32_t tile[NTILE][TILEB / 4];                  // image tiles of blocks b, b+1 (, b+2)
         uint64_t cs[2][NP][NW][BW];                       // per compute wave column sums of pixel^p
         uint64_t v[2][NP][BW];                            // column totals above the strip
         long long ticket;
@@ -1297,16 +1317,16 @@ struct BuildPow {
             }
     }
 
-    // Helper wave: per-wave column sums of every power of tile `buf`, the lookback, and the
-    // column totals above the strip for the compute waves.
-    static __device__ void prepare(const BuildDesc &d, Smem &sm, int buf, int64_t xb, int strip, int nvalid, int rw,
-                                   int lane, uint64_t *state, unsigned int *fault) {
+    // Helper wave: per-wave column sums of every power of tile tb into buffer buf, the lookback,
+    // and the column totals above the strip for the compute waves.
+    static __device__ void prepare(const BuildDesc &d, Smem &sm, int tb, int buf, int64_t xb, int strip, int nvalid,
+                                   int rw, int lane, uint64_t *state, unsigned int *fault) {
         uint64_t a[NP][PX];
 #pragma unroll
         for (int p = 0; p < NP; ++p)
 #pragma unroll
             for (int i = 0; i < PX; ++i) a[p][i] = 0;
-        const T *tile = reinterpret_cast<const T *>(sm.tile[buf]) + 2 * lane;
+        const T *tile = reinterpret_cast<const T *>(sm.tile[tb]) + 2 * lane;
         for (int w = 0; w < NW; ++w) {
             SumT<T, 1> c1[PX];
             SumT<T, 2> c2[PX];
@@ -1357,9 +1377,9 @@ struct BuildPow {
             for (int i = 0; i < PX; ++i) sm.v[buf][p][lane * PX + i] = v[p][i];
     }
 
-    // Compute wave: the rows of power P (table P-1) of block (buf, xb).
+    // Compute wave: the rows of power P (table P-1) of block xb (tile tb, sums and totals buf).
     template <int P>
-    static __device__ __forceinline__ void power_rows(const BuildDesc &d, const Smem &sm, int buf, int64_t xb, int wave,
+    static __device__ __forceinline__ void power_rows(const BuildDesc &d, const Smem &sm, int tb, int buf, int64_t xb, int wave,
                                                       int rw, int lane, int rows_ok, int64_t yw, uint32_t pitch_bytes,
                                                       uint64_t &lrow, uint64_t &ucarry) {
         using ST = PowScan<T, P>;
@@ -1384,7 +1404,7 @@ struct BuildPow {
         uint64_t *blk0 = table(d, P - 1) + yw * d.spitch + xb;
         const bool vec = d.sat_vec && xb + BW <= d.W;
         const uint32_t row_recs = static_cast<uint32_t>((d.W - xb) * 8);
-        const T *trow = reinterpret_cast<const T *>(sm.tile[buf] + wave * rw * ROWB / 4) + 2 * lane;
+        const T *trow = reinterpret_cast<const T *>(sm.tile[tb] + wave * rw * ROWB / 4) + 2 * lane;
         uint64_t acc[PX];
 #pragma unroll
         for (int i = 0; i < PX; ++i) acc[i] = 0;
@@ -1448,32 +1468,42 @@ struct BuildPow {
 #pragma unroll
         for (int p = 0; p < NP; ++p) { lrow[p] = 0; ucarry[p] = 0; }
 
-        // Separate helper and compute loops, as in Build2::strip.
+        // Separate helper and compute loops, as in Build2::strip.  Tile loads are FULL: with
+        // three buffers the helper waits for tile b+1 while tile b+2, issued after it, stays in
+        // flight (vector memory instructions complete in order, and tile b+2 is at least
+        // kFullLoads of them); with two, or when no later tile was issued, it waits for all.
         if (helper) {
-            TileStage<T, PX, TH>::load(d, sm.tile[0], ys, 0, nvalid, lane);
+            const int nb = d.nblocks;
+            Stage::template load<true>(d, sm.tile[0], ys, 0, nvalid, lane);
             __builtin_amdgcn_s_waitcnt(0x0070);
-            prepare(d, sm, 0, 0, strip_idx, nvalid, rw, lane, state, fault);
+            prepare(d, sm, 0, 0, 0, strip_idx, nvalid, rw, lane, state, fault);
             lds_barrier();
-            if (d.nblocks > 1) TileStage<T, PX, TH>::load(d, sm.tile[1], ys, BW, nvalid, lane);
-            for (int b = 0; b < d.nblocks; ++b) {
+            if (nb > 1) Stage::template load<true>(d, sm.tile[1], ys, BW, nvalid, lane);
+            if (NTILE == 3 && nb > 2) Stage::template load<true>(d, sm.tile[2 % NTILE], ys, 2 * BW, nvalid, lane);
+            for (int b = 0; b < nb; ++b) {
                 const int buf = b & 1;
                 const int64_t xb = static_cast<int64_t>(b) * BW;
-                if (b + 1 < d.nblocks) {
-                    __builtin_amdgcn_s_waitcnt(0x0070);
-                    prepare(d, sm, buf ^ 1, xb + BW, strip_idx, nvalid, rw, lane, state, fault);
+                if (b + 1 < nb) {
+                    constexpr int K = Stage::kFullLoads;
+                    if (NTILE == 3 && b + 2 < nb)
+                        __builtin_amdgcn_s_waitcnt((K & 15) | ((K >> 4) << 14) | (7 << 4));   // vmcnt(K) lgkmcnt(0)
+                    else
+                        __builtin_amdgcn_s_waitcnt(0x0070);
+                    prepare(d, sm, (b + 1) % NTILE, buf ^ 1, xb + BW, strip_idx, nvalid, rw, lane, state, fault);
                 }
                 lds_barrier();
-                if (b + 2 < d.nblocks) TileStage<T, PX, TH>::load(d, sm.tile[buf], ys, xb + 2 * BW, nvalid, lane);
+                if (b + NTILE < nb)
+                    Stage::template load<true>(d, sm.tile[b % NTILE], ys, xb + NTILE * BW, nvalid, lane);
             }
         } else {
             lds_barrier();
             for (int b = 0; b < d.nblocks; ++b) {
-                const int buf = b & 1;
+                const int buf = b & 1, tb = b % NTILE;
                 const int64_t xb = static_cast<int64_t>(b) * BW;
-                power_rows<1>(d, sm, buf, xb, wave, rw, lane, rows_ok, yw, pitch_bytes, lrow[0], ucarry[0]);
-                if constexpr (NP >= 2) power_rows<2>(d, sm, buf, xb, wave, rw, lane, rows_ok, yw, pitch_bytes, lrow[1], ucarry[1]);
-                if constexpr (NP >= 3) power_rows<3>(d, sm, buf, xb, wave, rw, lane, rows_ok, yw, pitch_bytes, lrow[2], ucarry[2]);
-                if constexpr (NP >= 4) power_rows<4>(d, sm, buf, xb, wave, rw, lane, rows_ok, yw, pitch_bytes, lrow[3], ucarry[3]);
+                power_rows<1>(d, sm, tb, buf, xb, wave, rw, lane, rows_ok, yw, pitch_bytes, lrow[0], ucarry[0]);
+                if constexpr (NP >= 2) power_rows<2>(d, sm, tb, buf, xb, wave, rw, lane, rows_ok, yw, pitch_bytes, lrow[1], ucarry[1]);
+                if constexpr (NP >= 3) power_rows<3>(d, sm, tb, buf, xb, wave, rw, lane, rows_ok, yw, pitch_bytes, lrow[2], ucarry[2]);
+                if constexpr (NP >= 4) power_rows<4>(d, sm, tb, buf, xb, wave, rw, lane, rows_ok, yw, pitch_bytes, lrow[3], ucarry[3]);
                 lds_barrier();
             }
         }

@@ -33,6 +33,7 @@ POWER_CASES = [
     # (H, W, pitch_extra, offset): image shape, extra pitch elements, misaligning element offset
     (1, 1, 0, 0), (3, 200, 0, 0), (65, 129, 0, 0), (1000, 1300, 0, 0), (257, 4099, 5, 1),
     (700, 1024, 0, 0), (2000, 777, 3, 0),
+    (300, 2048, 0, 0), (300, 2000, 0, 0),     # 16-byte tile DMA over 8 blocks; ragged last block
 ]
 
 
