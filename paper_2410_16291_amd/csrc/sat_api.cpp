@@ -277,23 +277,31 @@ sat_status check_build_variant(int v, int bpp, bool sq, const char *who) {
 // workgroups' worth.  Measured with the helper pipelines (ms, whole rows -> built-in segments):
 // 8-bit 2000 x 4000 0.096 -> 0.079, 2000 x 16000 0.218 -> 0.131, 3000 x 12000 0.207 -> 0.147,
 // 4096 x 16000 0.262 -> 0.170-0.186, 2048 x 32768 0.336 -> 0.173, 1500 x 85000 0.818 -> 0.292;
-// 16-bit with squares 4096 x 8192 0.250 -> 0.178.  Taller images gained nothing or lost:
-// 16-bit 8192^2 with squares 0.314 -> 0.309-0.311, 8750 x 85000 1.62 -> 1.59-1.78, 16000^2
-// 0.49 -> 0.59.  A forced count (sat_force_variant kind 4) applies up to kSegMaxRows rows, for
-// which the workspace reserves the pre-pass area.
+// 16-bit with squares 4096 x 8192 0.250 -> 0.178.  Taller images take three segments where
+// their strips are at their least height (below); elsewhere they gained nothing or lost.  A
+// forced count (sat_force_variant kind 4) applies up to kSegMaxRows rows, for which the
+// workspace reserves the pre-pass area.
 int choose_segments(int v, const satk::BuildDesc &d, int bpp, bool sq) {
     const satk::BuildVariant &var = satk::build_variant(v);
     if ((var.mode != satk::MODE_HELPER && var.mode != satk::MODE_HELPER3) || !var.lookback() ||
         d.H > satk::kSegMaxRows)
         return 1;
     const int forced = g_force[4];
-    if (forced <= 0 && d.H > kSegAutoRows) return 1;
+    // Taller images are split only where the plan's strips are at their least height (half a
+    // tile): the image is then too short to give every CU a strip of a useful height.  Measured
+    // on one GPU (ms, whole rows -> 3 segments): 6000^2 u16 with squares 0.252 -> 0.219, 8192^2
+    // 0.316 -> 0.308, 7000 x 16000 0.558 -> 0.539; u8 at 24-row strips 5000 x 12000 0.237 ->
+    // 0.204, 6000 x 20000 0.336 -> 0.296, 6000 x 40000 0.579 -> 0.518.  Taller strips lost:
+    // 12000^2 0.66 -> 0.78, 16000^2 0.48 -> 0.57, 8750 x 85000 1.48 -> 1.56, 8192 x 85000 at
+    // 32-row strips 1.39 -> 1.44.
+    const bool tall = d.H > kSegAutoRows;
+    if (forced <= 0 && tall && 2 * d.strip_h > var.th()) return 1;
     const int64_t most = std::min<int64_t>(satk::kMaxSeg, forced > 0 ? d.nblocks : d.nblocks / satk::kMinSegBlocks);
     if (most < 2) return 1;
     int64_t want = forced;
     if (forced <= 0) {
         const int64_t cap = satk::build_variant_capacity(v, bpp, sq);
-        want = cap > 0 ? std::max<int64_t>(2, 2 * cap / d.nstrips) : 1;
+        want = tall ? 3 : (cap > 0 ? std::max<int64_t>(2, 2 * cap / d.nstrips) : 1);
     }
     return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(want, most)));
 }

@@ -6,7 +6,8 @@ per lane at 48-row strips split into column segments for images of at most 4096 
 round of the shortest strips that fit on the CUs (24 to 48 rows) above that, or in heights
 balanced over rounds for taller images; four pixels per lane at one 64-row strip per CU; and four
 pixels per lane at 32, 48 or 64 rows (or balanced heights) for narrow images and 16-bit images
-with squares.  Images take the three-stage
+with squares.  Above 4096 rows, strips at their least height (half a tile) are split into three
+column segments.  Images take the three-stage
 helper pipeline where its three tile buffers fit the LDS, except images wider than 32768 pixels
 with more than two rounds of 48-row strips; those, and 16-bit images at eight pixels per lane, take
 the two-stage one.  Each case below lands in one branch; widths that are not a multiple of the block
@@ -26,7 +27,7 @@ CASES = [
     # (H, W, pixel dtype, squares, branch)
     (2000, 4096, np.uint8, False, "8 px/lane, 24-row strips (few strips)"),
     (3200, 4100, np.uint8, True, "8 px/lane, 48-row strips split into column segments, ragged last block, with squares"),
-    (5000, 4200, np.uint8, False, "8 px/lane, one round of the shortest strips: 24 rows, ragged"),
+    (5000, 4200, np.uint8, False, "8 px/lane, one round of the shortest strips: 24 rows in 3 column segments, ragged"),
     (9000, 4096, np.uint8, False, "8 px/lane, one round of the shortest strips: 36 rows"),
     (16000, 4096, np.uint8, False, "4 px/lane, one 64-row strip per CU"),
     (20000, 4352, np.uint8, False, "8 px/lane, more 48-row strips than CUs: heights balanced over two rounds"),
@@ -34,6 +35,7 @@ CASES = [
     (9000, 2000, np.uint8, False, "narrow: 4 px/lane, 48-row strips"),
     (7000, 3001, np.uint8, False, "narrow: 4 px/lane, 32-row strips, ragged"),
     (12000, 1000, np.uint16, True, "16-bit with squares: 4 px/lane, 48-row strips"),
+    (6000, 1500, np.uint16, True, "16-bit with squares above 4096 rows at 32-row strips: 3 column segments, ragged"),
     (20000, 1000, np.uint16, True, "16-bit with squares: balanced heights"),
     (6000, 5000, np.uint16, False, "16-bit without squares: two-stage helper, 8 px/lane, 48-row strips"),
     (1, 4096, np.uint8, True, "one row: 8 px/lane, one strip"),
